@@ -1,0 +1,233 @@
+"""Pins of the oracle's product (Sections 3-5).  Brute force on small inputs:
+the exact product of the dense operands, Eckart-Young, orthonormality and
+nestedness of the new bases, the block-relative bound, Lemma 6, special cases."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_01566_amd import workloads as W
+
+
+def _case(name):
+    if name == "c1":
+        T = O.ClusterTree(W.grid2d(32), 32)
+        A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+        return T, A, A
+    if name == "sphere":
+        P, Nn = W.icosphere(3)
+        T = O.ClusterTree(P, 64)
+        A = O.build_interpolated(T, O.KERNEL_SLP, 3, 1.0, diag=O.DIAG_ROW_MEAN)
+        return T, A, A
+    if name == "slp_dlp":
+        P, Nn = W.icosphere(2)
+        T = O.ClusterTree(P, 20)
+        A = O.build_interpolated(T, O.KERNEL_SLP, 2, 1.0, diag=O.DIAG_ROW_MEAN)
+        B = O.build_interpolated(T, O.KERNEL_DLP, 2, 1.0, normals=Nn)
+        return T, A, B
+    if name == "random2d":
+        T = O.ClusterTree(W.uniform2d(900, 11), 24)
+        A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 4, 0.5)
+        return T, A, A
+    raise KeyError(name)
+
+
+_cache = {}
+
+
+def _run(name, eps):
+    key = (name, eps)
+    if key not in _cache:
+        T, A, B = _case(name)
+        C, info = O.mul(A, B, eps)
+        _cache[key] = (T, A, B, C, info)
+    return _cache[key]
+
+
+CASES = [("c1", 1e-4), ("sphere", 1e-6), ("slp_dlp", 1e-4), ("random2d", 1e-5)]
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_basis_products_recursive_form(name, eps):
+    """P_s = W_{X,s}^* V_{Y,s} also satisfies P_s = sum F_{s'}^* P_{s'} E_{s'} (Section 4.1)."""
+    T, A, B, C, info = _run(name, eps)
+    for s in range(T.ncl):
+        if T.children[s]:
+            rec = sum(A.W.transfer[c].T @ info.P[c] @ B.V.transfer[c] for c in T.children[s])
+            assert np.allclose(rec, info.P[s], atol=1e-10 * max(1, np.abs(info.P[s]).max()))
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_exact_intermediate_equals_dense_product(name, eps):
+    """The induced block structure represents XY exactly (end of Section 3)."""
+    T, A, B, C, info = _run(name, eps)
+    D = A.to_dense_permuted() @ B.to_dense_permuted()
+    scale = np.abs(D).max()
+    for b, (U, Z) in info.exact.items():
+        t, r = b
+        blk = D[T.begin[t]:T.end[t], T.begin[r]:T.end[r]]
+        assert np.abs(U @ Z.T - blk).max() <= 1e-12 * scale
+    for b, N in C.N.items():
+        t, r = b
+        blk = D[T.begin[t]:T.end[t], T.begin[r]:T.end[r]]
+        assert np.abs(N - blk).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_block_relative_error_bound(name, eps):
+    """Every leaf block: ||(XY)|_b - C|_b||_2 <= eps ||(XY)|_b||_2 (Section 5.3)."""
+    T, A, B, C, info = _run(name, eps)
+    errs = O.block_errors(A, B, C)
+    assert len(errs) == len(C.blocks.adm) + len(C.blocks.inadm)
+    worst = max(e / n for e, n in errs.values() if n > 0)
+    assert worst <= eps, worst
+    # the result is a genuine compression: ranks below the exact widths
+    assert max(C.V.rank.values()) < T.size(0)
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_coarsening_eckart_young(name, eps):
+    """||G_b - G~_b||_2 = sigma_{kappa+1}(G_b) <= delta_c ||G_b|| (Section 5.1)."""
+    T, A, B, C, info = _run(name, eps)
+    for b, (U, Z) in info.exact.items():
+        G = U @ Z.T
+        Uc, Zc, sk = info.coarse[b]
+        sv = np.linalg.svd(G, compute_uv=False)
+        err = np.linalg.norm(G - Uc @ Zc.T, 2)
+        kap = info.kappa[b]
+        nxt = sv[kap] if kap < len(sv) else 0.0
+        assert abs(err - nxt) <= 1e-10 * sv[0] + 1e-300
+        assert err <= info.delta_c * sv[0] * (1 + 1e-9)
+        assert abs(info.nu[b] - sv[0]) <= 1e-10 * sv[0]
+        # the column factor is isometric
+        assert np.allclose(Zc.T @ Zc, np.eye(kap), atol=1e-10)
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_result_bases_isometric_and_nested(name, eps):
+    """V_t^* V_t = I for every cluster (Section 5.2); nestedness holds by construction."""
+    T, A, B, C, info = _run(name, eps)
+    for basis in (C.V, C.W):
+        for t in range(T.ncl):
+            Vt = basis.full(t)
+            k = basis.rank[t]
+            assert Vt.shape == (T.size(t), k)
+            assert np.allclose(Vt.T @ Vt, np.eye(k), atol=1e-10)
+            if T.children[t]:
+                for c in T.children[t]:
+                    off = T.begin[c] - T.begin[t]
+                    assert np.allclose(Vt[off:off + T.size(c)], basis.full(c) @ basis.transfer[c], atol=1e-12)
+
+
+@pytest.mark.parametrize("name,eps", CASES)
+def test_row_and_column_projection_errors(name, eps):
+    """Each admissible block: ||G~ - V V^* G~|| <= delta_r nu_b and
+    ||G~ - G~ W W^*|| <= delta_w nu_b (weighted construction, Section 5.3)."""
+    T, A, B, C, info = _run(name, eps)
+    for b in C.blocks.adm:
+        t, r = b
+        Uc, Zc, sk = info.coarse[b]
+        Gt = Uc @ Zc.T
+        Vt, Wr = C.V.full(t), C.W.full(r)
+        nu = info.nu[b]
+        if nu == 0:
+            continue
+        er = np.linalg.norm(Gt - Vt @ (Vt.T @ Gt), 2)
+        ec = np.linalg.norm(Gt - (Gt @ Wr) @ Wr.T, 2)
+        assert er <= eps / 4 * nu * (1 + 1e-8)
+        assert ec <= eps / 4 * nu * (1 + 1e-8)
+
+
+def test_error_decomposition_sum():
+    """sum over s in desc(t) of the weighted local errors stays below
+    eps_r^2 nu^2 / (1 - sigma theta) (Section 5.3): checked through the final
+    projection error, which is bounded by that sum."""
+    T, A, B, C, info = _run("c1", 1e-4)
+    bound = info.tol_r / math.sqrt(1 - 2 * info.theta)
+    for b in C.blocks.adm:
+        t, r = b
+        Uc, Zc, sk = info.coarse[b]
+        Vt = C.V.full(t)
+        e = np.linalg.norm(Uc - Vt @ (Vt.T @ Uc), 2)
+        assert e <= bound * info.nu[b] * (1 + 1e-8)
+
+
+def test_lemma6_product_admissibility():
+    """If P_tr is non-empty there is s with eta/(eta+1) dist(t,r) < max diam (Lemma 6),
+    and the number of same-level partners stays bounded."""
+    for name, eps in CASES:
+        T, A, B, C, info = _run(name, eps)
+        eta = A.blocks.eta
+        per_t = {}
+        for (t, r, ss) in info.induced_P:
+            assert any(eta / (eta + 1) * T.dist(t, r) < max(T.diam(t), T.diam(s), T.diam(r)) for s in ss)
+            if T.level[t] == T.level[r]:
+                per_t.setdefault(t, set()).add(r)
+        assert max(len(v) for v in per_t.values()) <= 40
+
+
+def test_single_leaf_is_plain_product():
+    """n <= leaf size: one inadmissible block, C = A B exactly (a textbook GEMM)."""
+    P = W.uniform2d(30, 4)
+    T = O.ClusterTree(P, 32)
+    A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+    C, info = O.mul(A, A, 1e-4)
+    G = O.kernel_matrix(O.KERNEL_NEG_LOG, P, P)
+    assert np.allclose(C.to_dense(), G @ G, rtol=0, atol=1e-12 * np.abs(G @ G).max())
+
+
+def test_identity_right_factor():
+    """B = I as an H2 matrix: C|_b approximates A|_b within eps per block."""
+    T = O.ClusterTree(W.uniform2d(600, 9), 24)
+    A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+    I = O.identity_h2(T, 0.5, 9)
+    eps = 1e-5
+    C, info = O.mul(A, I, eps)
+    Ad = A.to_dense_permuted()
+    for b in list(C.blocks.adm) + list(C.blocks.inadm):
+        t, r = b
+        ex = Ad[T.begin[t]:T.end[t], T.begin[r]:T.end[r]]
+        e = np.linalg.norm(ex - C.block_dense(t, r), 2)
+        assert e <= eps * np.linalg.norm(ex, 2) + 1e-14
+
+
+def test_scaling_keeps_ranks():
+    T, A, B, C, info = _run("c1", 1e-4)
+    A2 = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+    for k in A2.S:
+        A2.S[k] = 3.0 * A2.S[k]
+    for k in A2.N:
+        A2.N[k] = 3.0 * A2.N[k]
+    C2, info2 = O.mul(A2, A, 1e-4)
+    assert C2.V.rank == C.V.rank and C2.W.rank == C.W.rank
+    assert np.allclose(C2.to_dense(), 3.0 * C.to_dense(), atol=1e-10 * np.abs(C.to_dense()).max())
+
+
+def test_symmetric_square_gives_symmetric_result():
+    T, A, B, C, info = _run("c1", 1e-4)
+    D = C.to_dense()
+    ref = A.to_dense() @ A.to_dense()
+    assert np.linalg.norm(D - D.T, 2) <= 2e-4 * np.linalg.norm(ref, 2)
+    assert C.V.rank == C.W.rank
+
+
+def test_tiny_eps_reproduces_product():
+    T = O.ClusterTree(W.uniform2d(400, 2), 24)
+    A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+    C, info = O.mul(A, A, 1e-13)
+    ref = A.to_dense() @ A.to_dense()
+    assert np.linalg.norm(C.to_dense() - ref, 2) <= 1e-11 * np.linalg.norm(ref, 2)
+
+
+def test_incompatible_and_invalid_arguments():
+    T = O.ClusterTree(W.uniform2d(100, 2), 24)
+    T2 = O.ClusterTree(W.uniform2d(100, 3), 24)
+    A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
+    B = O.build_interpolated(T2, O.KERNEL_NEG_LOG, 3, 0.5)
+    with pytest.raises(ValueError):
+        O.mul(A, B, 1e-4)
+    with pytest.raises(ValueError):
+        O.mul(A, A, 0.0)
+    with pytest.raises(ValueError):
+        O.mul(A, A, 1.5)
