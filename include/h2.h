@@ -1,0 +1,172 @@
+/* C ABI of the MI355X adaptive H2-matrix product.
+ *
+ * Problem (Section 3 of the paper): given H2-matrices X (row tree T_I, column
+ * tree T_J) and Y (row tree T_J, column tree T_K) sharing the middle cluster
+ * tree, approximate Z = X Y by an H2-matrix on the block tree T_{IxK} built by
+ * the admissibility condition, with isometric nested row and column bases
+ * (Section 5.2) chosen adaptively so that every admissible block b satisfies
+ * ||(XY)|_b - C|_b||_2 <= eps ||(XY)|_b||_2 (Section 5.3, block-relative error
+ * control).  Inadmissible blocks are stored exactly.
+ *
+ * Conventions
+ *  - Every call returns h2_status; no exception crosses the ABI.  On failure
+ *    output handles are set to NULL, nothing partial is returned, and
+ *    h2_last_error() gives a message for the calling thread.
+ *  - Host arrays passed in are copied during the call; the caller keeps them.
+ *    Handles are created by the library and released by the caller with the
+ *    matching *_destroy call.  Output buffers are caller-allocated.
+ *  - Matrices are row-major.  Index sets of dense outputs are in the ORIGINAL
+ *    point order (not the tree's permuted order).
+ *  - Device memory and the HIP stream belong to the context; all device work
+ *    of a call is ordered on that stream and completed before the call
+ *    returns.
+ */
+#ifndef H2_H
+#define H2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  H2_OK = 0,
+  H2_ERR_INVALID_ARG = 1,   /* null/invalid pointer, size, eps not in (0,1), non-finite input */
+  H2_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed */
+  H2_ERR_DEVICE = 3,        /* HIP error (message holds the HIP string) */
+  H2_ERR_INCOMPATIBLE = 4,  /* X's column tree is not Y's row tree */
+  H2_ERR_TOO_LARGE = 5,     /* size above a documented limit (rank cap, dense size) */
+  H2_ERR_NOT_CONVERGED = 6  /* reserved */
+} h2_status;
+
+typedef struct h2_context_s* h2_context;
+typedef struct h2_tree_s* h2_tree;
+typedef struct h2_matrix_s* h2_matrix;
+
+/* Context on HIP device `device` with its own stream. */
+h2_status h2_context_create(int device, h2_context* out);
+void h2_context_destroy(h2_context ctx);
+/* Message of the calling thread's last failure ("" if none).  Valid until the
+ * thread's next library call. */
+const char* h2_last_error(void);
+
+/* Cluster tree (Definition 1) of n points (row-major n x dim, dim 1..3) by
+ * geometric bisection: a cluster with more than leaf_size points is split
+ * along the longest edge of its bounding box at the midpoint (first axis on
+ * ties; points below the midpoint go to the first child; if one side would be
+ * empty, the cluster is halved by a stable sort along that axis).
+ * Errors: INVALID_ARG for n < 1, dim outside 1..3, leaf_size < 1, non-finite
+ * coordinates. */
+h2_status h2_build_cluster_tree(h2_context ctx, const double* points, int64_t n, int dim, int leaf_size,
+                                h2_tree* out);
+/* perm[k] = original index of the k-th point in tree order (n entries). */
+h2_status h2_tree_permutation(h2_tree tree, int64_t* perm);
+/* Sizes: n, number of clusters, depth (levels), number of leaves. */
+h2_status h2_tree_info(h2_tree tree, int64_t* n, int* nclusters, int* depth, int* nleaves);
+/* Cluster arrays (nclusters entries each, any may be NULL): first/one-past-last
+ * position in tree order, parent (-1 at the root), level. */
+h2_status h2_tree_clusters(h2_tree tree, int64_t* begin, int64_t* end, int* parent, int* level);
+void h2_tree_destroy(h2_tree tree);
+
+typedef enum {
+  H2_KERNEL_NEG_LOG = 0,   /* -log|x-y|                                  */
+  H2_KERNEL_LAPLACE_SLP = 1, /* 1/(4 pi |x-y|)                           */
+  H2_KERNEL_LAPLACE_DLP = 2  /* (x-y).n_y / (4 pi |x-y|^3), normals given */
+} h2_kernel;
+
+typedef enum {
+  H2_DIAG_ZERO = 0,              /* g(x,x) = 0                                       */
+  H2_DIAG_ROW_NEARFIELD_MEAN = 1 /* mean of the row's other nearfield kernel values  */
+} h2_diag_rule;
+
+/* H2-matrix of the point-collocation kernel matrix g(x_i, y_j) by tensor
+ * Chebyshev interpolation of order `order` per axis (rank k = order^dim) on the
+ * clusters' bounding boxes (eq. interpolation/vsw, transfers eq. transfer).
+ * Block tree by the admissibility condition max(diam) <= 2 eta dist.
+ * Double layer: normals (host, n x 3, unit) for the column points; the column
+ * basis holds normal derivatives of the Lagrange polynomials.
+ * Errors: INVALID_ARG (order < 1, order^dim > 64, eta <= 0, DLP without normals
+ * or dim != 3, non-finite normals), OUT_OF_MEMORY, DEVICE. */
+h2_status h2_build_interpolated(h2_context ctx, h2_tree rows, h2_tree cols, int kernel, const double* normals,
+                                int order, double eta, int diag, h2_matrix* out);
+
+typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32_BULK = 1 } h2_precision;
+
+typedef struct {
+  int precision;       /* h2_precision; FP32 bulk is used only for eps >= 1e-5, tighter
+                          eps runs the bulk in FP64 (stats.prec_used tells which ran)   */
+  double theta;        /* weight base, 0 => 1/(2*sigma), sigma = max children (= 2)   */
+  double budget_coarse;/* fractions of eps for coarsening, rows, columns; 0 => 1/4 */
+  double budget_row;
+  double budget_col;
+  int max_rank;        /* rank cap of the result bases (<= 64; 0 => default)          */
+  int coarse_rank;     /* rank cap of a coarsened block (<= 64; 0 => default 64)       */
+  int timing;          /* 1: per-phase device times; 2: also per-kernel-class times     */
+} h2_mul_options;
+
+typedef struct {
+  double t_phase[8];   /* device ms: 0 operand prep, 1 exact product, 2 leaf assembly,
+                          3 coarsening, 4 row basis, 5 column basis, 6 couplings, 7 total */
+  double t_plan_ms;    /* host planning time of this call (0 when the plan was cached)   */
+  double bytes_alg;    /* algorithmic bytes moved by the product (see DESIGN notes)      */
+  double flops_alg;
+  int prec_used;       /* h2_precision actually used for the bulk                        */
+  int rank_max_row, rank_max_col, coarse_rank_max;
+  int64_t n_adm, n_inadm;
+  int64_t launches;
+  /* per kernel class (0 gemm fp64, 1 gemm fp32, 2 qr, 3 svd, 4 chol, 5 fill, 6 convert):
+     device ms (timing == 2 only), launches, algorithmic bytes and flops of one product */
+  double t_kind[8];
+  int64_t launches_kind[8];
+  double bytes_kind[8];
+  double flops_kind[8];
+} h2_mul_stats;
+
+/* Default options (all fields as documented above). */
+void h2_mul_default_options(h2_mul_options* opt);
+
+/* C = X Y with the block-relative bound eps (0 < eps < 1), see the header
+ * comment.  X and Y are read-only and stay resident.  The product plan
+ * (integer work lists) is cached on the pair (X, Y) and reused.
+ * Errors: INVALID_ARG, INCOMPATIBLE (X's column tree differs from Y's row
+ * tree), TOO_LARGE (a rank cap was exceeded: raise max_rank / coarse_rank, or
+ * an operand rank above 64), OUT_OF_MEMORY, DEVICE. */
+h2_status h2_mul(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opt,
+                 h2_matrix* C, h2_mul_stats* stats);
+
+/* Dense matrix (rows x cols, row-major, leading dimension ld >= cols, original
+ * index order), for small cases: rows*cols <= 2^26, else TOO_LARGE. */
+h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld);
+
+/* One leaf block of M as dense: block index b in [0, n_adm + n_inadm) (first
+ * the admissible leaves, then the inadmissible ones, in the order of
+ * h2_matrix_blocks).  out: |t| x |s| row-major in tree order. */
+h2_status h2_block_dense(h2_matrix M, int64_t b, double* out);
+
+/* Sizes of M: numbers of admissible / inadmissible leaves, rank cap, maximal
+ * row and column ranks. */
+h2_status h2_matrix_info(h2_matrix M, int64_t* n_adm, int64_t* n_inadm, int* kcap, int* rank_max_row,
+                         int* rank_max_col);
+/* Leaf blocks as (row cluster, column cluster) pairs: first the admissible
+ * ones, then the inadmissible ones (2*(n_adm+n_inadm) ints). */
+h2_status h2_matrix_blocks(h2_matrix M, int* pairs);
+/* Ranks of the row and column cluster bases (nclusters entries each). */
+h2_status h2_matrix_ranks(h2_matrix M, int* row_ranks, int* col_ranks);
+/* Storage of M in bytes (bases, transfers, couplings, nearfield). */
+h2_status h2_matrix_storage(h2_matrix M, int64_t* bytes);
+void h2_matrix_destroy(h2_matrix M);
+
+/* Diagnostic: runs every device kernel (batched GEMM in FP64 and FP32 with all
+ * transpose combinations, streaming QR, Jacobi SVD, Cholesky
+ * orthonormalisation) on seeded data and writes each kernel's error against a
+ * host evaluation of its definition into errors[0..min(nerrors,*ntests)-1];
+ * *ntests receives the number of tests.  Synchronous; allocates its own
+ * device memory.  Not used by h2_mul. */
+h2_status h2_selftest(h2_context ctx, double* errors, int nerrors, int* ntests);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2_H */

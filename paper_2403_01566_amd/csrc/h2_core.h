@@ -1,0 +1,150 @@
+// Host-side structures of the H2 product library: cluster/block trees,
+// resident H2-matrices, the product plan (integer work lists) and its
+// executor.  All floating-point work of the product runs in h2_kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/h2.h"
+#include "h2_kernels.h"
+
+namespace h2 {
+
+struct Error : std::runtime_error {
+  h2_status code;
+  Error(h2_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define H2_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) {                                                                   \
+      if (e_ == hipErrorOutOfMemory) throw ::h2::Error(H2_ERR_OUT_OF_MEMORY, hipGetErrorString(e_)); \
+      throw ::h2::Error(H2_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
+    }                                                                                         \
+  } while (0)
+
+// ---------------------------------------------------------------- trees
+struct Tree {
+  int64_t n = 0;
+  int dim = 0, leaf_size = 0, ncl = 0, depth = 0;
+  std::vector<double> pts;        // original points, n x dim
+  std::vector<int64_t> perm;      // tree position -> original index
+  std::vector<int64_t> begin, end;
+  std::vector<int> parent, level;
+  std::vector<std::vector<int>> children;
+  std::vector<double> lo, hi;     // ncl x dim bounding boxes
+  int64_t size(int t) const { return end[t] - begin[t]; }
+  bool leaf(int t) const { return children[t].empty(); }
+  double diam(int t) const;
+  double dist(int t, int s) const;
+};
+
+std::shared_ptr<Tree> build_tree(const double* pts, int64_t n, int dim, int leaf_size);
+
+enum BlockKind : int { BK_ADM = 0, BK_INADM = 1, BK_SPLIT = 2 };
+
+struct BlockTree {
+  const Tree* rows = nullptr;
+  const Tree* cols = nullptr;
+  double eta = 0;
+  struct Node {
+    int t, s, kind;
+    int child0, nchild;  // children in `nodes`
+    int leaf_index;      // index among adm (kind ADM) or inadm (kind INADM) leaves
+    int depth;
+  };
+  std::vector<Node> nodes;
+  std::vector<int> adm, inadm;           // node indices of leaves
+  std::map<std::pair<int, int>, int> index;
+  int find(int t, int s) const {
+    auto it = index.find({t, s});
+    return it == index.end() ? -1 : it->second;
+  }
+};
+
+void build_block_tree(BlockTree& bt, const Tree& rows, const Tree& cols, double eta);
+
+// ---------------------------------------------------------------- device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void release();
+  template <typename T>
+  T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+struct Context;
+
+// A cluster basis in padded layout: leaf rows of all leaves in one n x kc
+// array (tree order), transfers ncl x kc x kc (E[t]: k_t x k_parent, i.e.
+// V_parent restricted to t equals V_t E_t), ranks per cluster.
+struct BasisDev {
+  double* leaf = nullptr;
+  double* transfer = nullptr;
+  float* leaf32 = nullptr;
+  float* transfer32 = nullptr;
+};
+
+struct Matrix {
+  Context* ctx = nullptr;
+  std::shared_ptr<Context> hold;  // keeps the context (stream, plan cache) alive
+  ~Matrix();
+  std::shared_ptr<Tree> rows, cols;
+  BlockTree bt;
+  int kc = 0;             // rank cap (= operand rank for interpolated matrices)
+  bool w_is_v = false;    // column basis identical to row basis
+  BasisDev V, W;
+  double* S = nullptr;    // n_adm x kc x kc couplings
+  double* N = nullptr;    // packed nearfield
+  float* S32 = nullptr;
+  float* N32 = nullptr;
+  std::vector<int64_t> noff;  // per inadm leaf offset into N
+  int64_t nsize = 0;
+  std::vector<int> rank_row, rank_col;  // host copies
+  std::vector<std::unique_ptr<DevBuf>> bufs;
+  bool has32 = false;
+  uint64_t id = 0;
+  double* alloc64(size_t count);
+  float* alloc32(size_t count);
+  void ensure_fp32(hipStream_t s);
+};
+
+struct Plan;
+
+// Device, stream and plan cache.  Shared by the context handle and every
+// matrix created in it, so handles may be released in any order.
+struct Context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int* overflow = nullptr;  // device flag set by rank-cap overflows
+  std::map<std::pair<uint64_t, uint64_t>, std::shared_ptr<Plan>> plans;
+  uint64_t next_id = 1;
+  std::weak_ptr<Context> self;
+  ~Context();
+  void evict(uint64_t matrix_id);
+};
+
+std::unique_ptr<Matrix> build_interpolated(Context* ctx, std::shared_ptr<Tree> rows, std::shared_ptr<Tree> cols,
+                                           int kernel, const double* normals, int order, double eta, int diag);
+
+std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
+                                 h2_mul_stats* stats);
+
+void to_dense(const Matrix& M, double* out, int64_t ld);
+void block_dense(const Matrix& M, int64_t b, double* out);
+int selftest(hipStream_t s, int* overflow, double* errors, int nerrors);
+
+}  // namespace h2

@@ -1,0 +1,113 @@
+// Internal interface between the host planner and the gfx950 kernels.
+// Every floating-point step of the product runs in these kernels; the host
+// only builds integer work lists (plans) and launches them.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace h2k {
+
+// Item flags.
+enum : int {
+  IT_TRANS_A = 1,     // use A^T
+  IT_TRANS_B = 2,     // use B^T
+  IT_COPY = 4,        // C += alpha * op(A) (A is m x n, B unused)
+  IT_SCALE_INV = 8,   // multiply alpha by 1/(*scale) (0 if *scale == 0)
+};
+
+// One contribution alpha * op(A) * op(B) (or alpha * op(A)) to a task's output.
+// Matrices are row-major with the given leading dimensions.
+template <typename T>
+struct GemmItem {
+  const T* a;
+  const T* b;
+  const double* scale;  // optional device scalar (see IT_SCALE_INV)
+  int lda, ldb, k, flags;
+  double alpha;
+};
+
+// One output matrix C (m x n, row-major, ldc): C = (beta ? C : 0) + sum of items.
+template <typename T>
+struct GemmTask {
+  T* c;
+  int ldc, m, n, item0, nitem, beta, pad;
+};
+
+struct GemmTile {
+  int task, m0, n0, pad;
+};
+
+// Streaming Householder QR, R factor only: A (m x w, row-major, lda) -> R (w x w).
+// R is upper triangular (rows >= min(m,w) are zero); with trans_r the kernel
+// stores R^T instead.
+struct QrTask {
+  const double* a;
+  double* r;
+  int lda, ldr, m, w, trans_r, pad;
+};
+
+// One-sided Jacobi on a small matrix A (rows x cols, row-major, lda), rotating
+// columns: A J = B with orthogonal columns.  Singular values are the column
+// norms of B; the left singular vectors are the normalised columns.  Outputs:
+// sigma (descending, cols entries), the number kept, and an orthonormal basis
+// of the kept left singular vectors (rows x kcap, zero beyond kept, ldu).
+// Threshold tau = tol_abs + tol_rel * sigma_1 + tol_scale * (tol_ptr ? *tol_ptr : 0).
+// frob == 0: keep sigma_i > tau (largest dropped value below tau);
+// frob == 1: keep the fewest values such that the Frobenius norm of the
+// dropped tail is at most tau.  Overflow sets bits `ovf_bit` in *overflow.
+struct SvdTask {
+  const double* a;
+  double* u;
+  double* sigma;    // cols entries
+  int* rank;        // 1 entry
+  const double* tol_ptr;
+  double tol_abs, tol_rel, tol_scale;
+  int lda, ldu, rows, cols, kcap, trans_a, frob, ovf_bit;
+};
+
+// Lower bound of a block norm from the R factors of its pieces: for every
+// group, tau[g] = factor[g] * max over its matrices of the largest row norm
+// (row j of R^T = column j of R, whose norm is that of column j of the
+// condensed block, a lower bound of its spectral norm).
+struct RefMat {
+  const double* a;
+  int lda, rows, cols;
+};
+struct RefTask {
+  int first, count;
+  double factor;
+  double* out;
+};
+
+// Scaled Cholesky step for orthonormalising a tall m x w matrix Y from its
+// Gram matrix G = Y^T Y (w x w): D = diag(G)^(1/2), D^-1 G D^-1 = R'^T R',
+// outputs T = D^-1 R'^-1 (so Y T has orthonormal columns) and R = R' D
+// (so Y = (Y T) R).  Only the first *weff columns are used (rest zero).
+struct CholTask {
+  const double* g;
+  double* t;
+  double* r;
+  const int* weff;  // optional; null = w
+  int ldg, ldt, ldr, w;
+};
+
+struct FillTask {
+  void* p;
+  int ld, m, n, pad;
+  double value;       // diagonal value when diag != 0, fill value otherwise
+  int diag, elem;     // elem: 8 double / 4 float
+};
+
+void launch_gemm_f64(const GemmItem<double>* items, const GemmTask<double>* tasks, const GemmTile* tiles,
+                     int ntiles, hipStream_t s);
+void launch_gemm_f32(const GemmItem<float>* items, const GemmTask<float>* tasks, const GemmTile* tiles,
+                     int ntiles, hipStream_t s);
+void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s);
+void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s);
+void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s);
+void launch_ref(const RefTask* tasks, const RefMat* mats, int ntasks, hipStream_t s);
+void launch_fill(const FillTask* tasks, int ntasks, hipStream_t s);
+void launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
+void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
+
+}  // namespace h2k

@@ -1,0 +1,1853 @@
+// Product planner and executor.
+//
+// Once per operand pair the host builds the integer structure of the product
+// (Sections 3-5 of the paper) and emits level-batched launches of the gfx950
+// kernels; every floating-point operation of the product runs in those
+// kernels.
+//
+// Exact product (Sections 3 and 4).  The host walks the union of the induced
+// block tree (Definition 8) and the prescribed result block tree.  Every node
+// (t,r) routes its pending sub-products X|_{t x s} Y|_{s x r} by the four
+// accumulator cases of Section 3.2 and carries, as its accumulator
+// (Definition 5):
+//   C_tr (kX x kY)  uniform part V_{X,t} C_tr W_{Y,r}^*: the products with both
+//                   factors admissible, S_{X,ts} P_s S_{Y,sr} (Section 4.1);
+//   A_tr (|t| x kY) right semi-uniform part A_tr W_{Y,r}^* (case 1);
+//   B_tr (|r| x kX) left semi-uniform part V_{X,t} B_tr^* (case 2);
+//   N_tr            dense part (case 3; only where t or r is a leaf cluster).
+// Splitting (Sections 3.3, 4.3): C_{t'r'} = E_{X,t'} C_tr F_{Y,r'}^*,
+// A_{t'r'} = A_tr|_{t'} F_{Y,r'}^*, B_{t'r'} = B_tr|_{r'} E_{X,t'}^*, N
+// restricted; the product-tree children refine the pending triples.
+// The semi-uniform terms X|_{t x s} V_{Y,s} and Y|_{s x r}^* W_{X,s} (the
+// yields of the basis trees of Section 4.2) are formed bottom-up, level by
+// level, over the operand block trees (Phi, Psi).
+//
+// Coarsening (Section 5.1): below each admissible result leaf the exact
+// blocks are agglomerated pairwise along the induced tree; every merge is a
+// truncated SVD (QR of the factors, one-sided Jacobi on the small core) with
+// relative tolerance delta_c / (number of merges of that block), so the
+// accumulated error stays below delta_c ||G_b|| (Remark 13).
+//
+// Adaptive bases (Sections 5.2, 5.3): row basis bottom-up with weights
+// omega = theta^{(level s - level t)/2} ||G_b||, leaf SVD of the weighted
+// condensed blocks, non-leaf SVD of the stacked projections, truncation at
+// eps_r = delta_r sqrt(1 - sigma theta); the column basis the same way on the
+// adjoint; couplings S_b = V_t^* G~_b W_r.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+
+#include "h2_core.h"
+
+namespace h2 {
+
+using h2k::GemmItem;
+using h2k::GemmTask;
+using h2k::GemmTile;
+
+// ------------------------------------------------------------------ device references
+enum : int { WS_NONE = -1, WS_D = 0, WS_F = 1, WS_I = 2 };
+
+template <typename T>
+struct DRef {
+  int ws = WS_NONE;
+  T* ext = nullptr;
+  int64_t off = 0;
+  static DRef external(T* p) {
+    DRef r;
+    r.ext = p;
+    return r;
+  }
+  DRef operator+(int64_t d) const {
+    DRef r = *this;
+    r.off += d;
+    return r;
+  }
+};
+
+template <typename T>
+struct PItem {
+  DRef<T> a, b;
+  DRef<double> scale;
+  int lda, ldb, k, flags;
+  double alpha;
+};
+template <typename T>
+struct PTask {
+  DRef<T> c;
+  int ldc, m, n, item0, nitem, beta;
+};
+struct PQr {
+  DRef<double> a, r;
+  int lda, ldr, m, w, trans_r;
+};
+struct PSvd {
+  DRef<double> a, u, sigma;
+  DRef<int> rank;
+  DRef<double> tolref;  // coarsening: per-block absolute reference (times delta_c)
+  int tolkind;          // 0: coarsening (Frobenius tail), 1: row, 2: column (largest dropped value)
+  double tolfactor;
+  int lda, ldu, rows, cols, kcap;
+};
+struct PRef {
+  int first, count;
+  double factor;
+  DRef<double> out;
+};
+struct PRefMat {
+  DRef<double> a;
+  int lda, rows, cols;
+};
+struct PChol {
+  DRef<double> g, t, r;
+  DRef<int> weff;
+  int ldg, ldt, ldr, w;
+};
+struct PFill {
+  DRef<double> p;
+  int ld, m, n, diag;
+  double value;
+};
+
+enum StepKind { SK_GEMM_D, SK_GEMM_F, SK_QR, SK_SVD, SK_CHOL, SK_FILL, SK_CVT_F2D, SK_REF };
+
+enum Phase { PH_PREP = 0, PH_EXACT = 1, PH_LEAF = 2, PH_COARSE = 3, PH_ROW = 4, PH_COL = 5, PH_COUPLE = 6 };
+
+struct Step {
+  StepKind kind;
+  int phase = 0;
+  std::vector<PItem<double>> itd;
+  std::vector<PTask<double>> tkd;
+  std::vector<PItem<float>> itf;
+  std::vector<PTask<float>> tkf;
+  std::vector<PQr> qr;
+  std::vector<PSvd> svd;
+  std::vector<PChol> chol;
+  std::vector<PFill> fill;
+  std::vector<PRef> ref;
+  std::vector<PRefMat> refmat;
+  DRef<float> cvt_in;
+  DRef<double> cvt_out;
+  int64_t cvt_n = 0;
+  int wmax = 0;
+  size_t desc_off = 0, desc2_off = 0, tiles_off = 0;
+  int ndesc = 0, ntiles = 0;
+  double flops = 0, bytes = 0;
+};
+
+struct Plan {
+  std::vector<Step> steps;
+  int64_t wsd = 0, wsf = 0, wsi = 0;
+  DevBuf bufd, buff, bufi, desc;
+  std::vector<char> hdesc;
+  int kc = 0, kappa_cap = 0;
+  DRef<double> res_vleaf, res_vtr, res_wleaf, res_wtr, res_S, res_N;
+  DRef<int> res_rank_row, res_rank_col;
+  DRef<double> coarse_sigma_roots;   // not used directly
+  BlockTree cbt;
+  std::vector<int64_t> cnoff;
+  int64_t cnsize = 0;
+  double bytes_alg = 0, flops_alg = 0;
+  int64_t n_adm = 0, n_inadm = 0;
+  bool f32 = false;
+  double eps_set = -1;
+  double theta = 0.25, sigma_br = 2.0;
+  double budget[3] = {0.25, 0.25, 0.25};
+  int64_t launches = 0;
+  int max_coarse_K = 0;
+  double t_kind[8] = {0}, bytes_kind[8] = {0}, flops_kind[8] = {0};
+  int64_t launches_kind[8] = {0};
+};
+
+// ------------------------------------------------------------------ plan builder
+struct Builder {
+  Plan& P;
+  int phase = 0;
+  explicit Builder(Plan& p) : P(p) {}
+  DRef<double> wd(int64_t n) {
+    DRef<double> r;
+    r.ws = WS_D;
+    r.off = P.wsd;
+    P.wsd += (std::max<int64_t>(n, 1) + 31) & ~int64_t(31);
+    return r;
+  }
+  DRef<float> wf(int64_t n) {
+    DRef<float> r;
+    r.ws = WS_F;
+    r.off = P.wsf;
+    P.wsf += (std::max<int64_t>(n, 1) + 63) & ~int64_t(63);
+    return r;
+  }
+  DRef<int> wi(int64_t n) {
+    DRef<int> r;
+    r.ws = WS_I;
+    r.off = P.wsi;
+    P.wsi += (std::max<int64_t>(n, 1) + 63) & ~int64_t(63);
+    return r;
+  }
+  Step& step(StepKind k) {
+    P.steps.emplace_back();
+    P.steps.back().kind = k;
+    P.steps.back().phase = phase;
+    return P.steps.back();
+  }
+};
+
+template <typename T>
+struct WS;
+template <>
+struct WS<double> {
+  static DRef<double> get(Builder& b, int64_t n) { return b.wd(n); }
+  static constexpr StepKind kind = SK_GEMM_D;
+  static std::vector<PItem<double>>& items(Step& s) { return s.itd; }
+  static std::vector<PTask<double>>& tasks(Step& s) { return s.tkd; }
+};
+template <>
+struct WS<float> {
+  static DRef<float> get(Builder& b, int64_t n) { return b.wf(n); }
+  static constexpr StepKind kind = SK_GEMM_F;
+  static std::vector<PItem<float>>& items(Step& s) { return s.itf; }
+  static std::vector<PTask<float>>& tasks(Step& s) { return s.tkf; }
+};
+
+// GEMM step writer.  Items follow their task.
+template <typename T>
+struct GW {
+  Step* s;
+  explicit GW(Step& st) : s(&st) {}
+  void task(DRef<T> c, int ldc, int m, int n, int beta = 0) {
+    s->bytes += (double)sizeof(T) * m * n * (beta ? 2 : 1);
+    PTask<T> t;
+    t.c = c;
+    t.ldc = ldc;
+    t.m = m;
+    t.n = n;
+    t.item0 = (int)WS<T>::items(*s).size();
+    t.nitem = 0;
+    t.beta = beta;
+    WS<T>::tasks(*s).push_back(t);
+  }
+  void mm(DRef<T> a, int lda, DRef<T> b, int ldb, int k, int flags = 0, double alpha = 1.0,
+          DRef<double> scale = DRef<double>()) {
+    if (k <= 0) return;
+    PItem<T> x;
+    x.a = a;
+    x.b = b;
+    x.scale = scale;
+    x.lda = lda;
+    x.ldb = ldb;
+    x.k = k;
+    x.flags = flags;
+    x.alpha = alpha;
+    WS<T>::items(*s).push_back(x);
+    auto& tk = WS<T>::tasks(*s).back();
+    tk.nitem++;
+    s->flops += 2.0 * tk.m * tk.n * k;
+    s->bytes += (double)sizeof(T) * ((double)tk.m * k + (double)k * tk.n);
+  }
+  void copy(DRef<T> a, int lda, int flags = 0, double alpha = 1.0) {
+    PItem<T> x;
+    x.a = a;
+    x.b = DRef<T>();
+    x.lda = lda;
+    x.ldb = 0;
+    x.k = 0;
+    x.flags = flags | h2k::IT_COPY;
+    x.alpha = alpha;
+    WS<T>::items(*s).push_back(x);
+    auto& tk = WS<T>::tasks(*s).back();
+    tk.nitem++;
+    s->bytes += (double)sizeof(T) * tk.m * tk.n;
+  }
+};
+
+// ------------------------------------------------------------------ union tree node
+struct UNode {
+  int t = 0, r = 0, parent = -1, depth = 0;
+  int tc = -1;      // node of the result block tree, -1 below an admissible result leaf
+  int below = -1;   // admissible result leaf (result tree node) owning this node, or -1
+  bool split = false, fin = false;
+  int child0 = -1, nchild = 0;
+  std::vector<std::pair<int, int>> aa, sa, sb, nn, ns, sn;  // (X block node, Y block node)
+  bool hasC = false, hasA = false, hasB = false, hasN = false;
+  int64_t offC = -1, offTmp = -1, offA = -1, offB = -1, offN = -1, offVC = -1;
+  int ldA = 0, ldB = 0;
+  int form = 0;        // 0 internal, 1 semi-uniform leaf, 2 dense U=G, 3 dense Z=G^T, 4 nearfield output
+  int64_t offG = -1;   // phase-A precision: U (semi-uniform) or G / G^T (dense)
+  int64_t offZa = -1;  // phase-A precision: Z (semi-uniform)
+  // coarsening (FP64 workspace offsets)
+  int height = -1, K = 0, m = 0, n = 0;
+  int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
+          Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1;
+  int nmerge = 1;
+};
+
+static inline DRef<double> Dw(int64_t off) {
+  DRef<double> d;
+  d.ws = WS_D;
+  d.off = off;
+  return d;
+}
+static inline DRef<int> Iw(int64_t off) {
+  DRef<int> d;
+  d.ws = WS_I;
+  d.off = off;
+  return d;
+}
+template <typename T>
+static inline DRef<T> Tw(int64_t off) {
+  DRef<T> d;
+  d.ws = std::is_same<T, float>::value ? WS_F : WS_D;
+  d.off = off;
+  return d;
+}
+
+// full cluster basis references in phase-A precision
+template <typename T>
+struct FB {
+  const Tree* T_ = nullptr;
+  int k = 0;
+  DRef<T> leaf, tr;
+  std::vector<DRef<T>> lvl;
+  DRef<T> full(int t) const {
+    if (T_->leaf(t)) return leaf + T_->begin[t] * k;
+    return lvl[T_->level[t]] + T_->begin[t] * k;
+  }
+  DRef<T> E(int t) const { return tr + (int64_t)t * k * k; }
+};
+
+// ------------------------------------------------------------------ planner
+class Planner {
+ public:
+  Context* ctx;
+  Matrix* X;
+  Matrix* Y;
+  const Tree& TI;
+  const Tree& TJ;
+  const Tree& TK;
+  int kX, kY;
+  Plan& P;
+  Builder B;
+  BlockTree& C;
+  std::vector<UNode> un;
+  std::vector<int> phi_need, psi_need, dy_need, dx_need;
+  int kc, kcap;  // result rank cap, coarsened rank cap
+  std::vector<std::map<int, int64_t>> row_proj, col_proj;
+  std::vector<int> bnode;  // admissible result leaf -> union node rooting its coarsening
+
+  Planner(Context* c, Matrix* x, Matrix* y, Plan& p, int kc_, int kcap_)
+      : ctx(c), X(x), Y(y), TI(*x->rows), TJ(*x->cols), TK(*y->cols), kX(x->kc), kY(y->kc), P(p), B(p),
+        C(p.cbt), kc(kc_), kcap(kcap_) {}
+
+  void build_union();
+  template <typename T>
+  void phaseA();
+  void coarsen();
+  void basis(bool rows);
+  void couplings();
+};
+
+void Planner::build_union() {
+  const BlockTree& bx = X->bt;
+  const BlockTree& by = Y->bt;
+  phi_need.assign(bx.nodes.size(), 0);
+  dx_need.assign(bx.nodes.size(), 0);
+  psi_need.assign(by.nodes.size(), 0);
+  dy_need.assign(by.nodes.size(), 0);
+  un.clear();
+  UNode root;
+  root.tc = 0;
+  if (C.nodes[0].kind == BK_ADM) root.below = 0;
+  un.push_back(root);
+  std::vector<std::vector<int>> pend(1, std::vector<int>{0});
+  for (size_t q = 0; q < un.size(); ++q) {
+    std::vector<int> cur = std::move(pend[q]);
+    const int t = un[q].t, r = un[q].r;
+    std::vector<int> rest;
+    for (;;) {
+      rest.clear();
+      for (int s : cur) {
+        int ix = bx.find(t, s), iy = by.find(s, r);
+        if (ix < 0 || iy < 0) throw Error(H2_ERR_DEVICE, "planner: inconsistent product tree");
+        int kx = bx.nodes[ix].kind, ky = by.nodes[iy].kind;
+        if (ky == BK_ADM) {  // case 1 (first match wins when both factors are admissible)
+          if (kx == BK_ADM) un[q].aa.push_back({ix, iy});
+          else {
+            un[q].sa.push_back({ix, iy});
+            phi_need[ix] = 1;
+          }
+        } else if (kx == BK_ADM) {  // case 2
+          un[q].sb.push_back({ix, iy});
+          psi_need[iy] = 1;
+        } else if (kx == BK_INADM || ky == BK_INADM) {  // case 3
+          if (kx == BK_INADM && ky == BK_INADM) un[q].nn.push_back({ix, iy});
+          else if (kx == BK_INADM) {
+            un[q].ns.push_back({ix, iy});
+            dy_need[iy] = 1;
+          } else {
+            un[q].sn.push_back({ix, iy});
+            dx_need[ix] = 1;
+          }
+        } else {  // case 4
+          rest.push_back(s);
+        }
+      }
+      if (!rest.empty() && TI.leaf(t) && TK.leaf(r)) {
+        std::vector<int> nx;  // both clusters are leaves: refine the triples in place
+        for (int s : rest) {
+          const auto& nd = bx.nodes[bx.find(t, s)];
+          for (int c = 0; c < nd.nchild; ++c) nx.push_back(bx.nodes[nd.child0 + c].s);
+        }
+        cur = std::move(nx);
+        continue;
+      }
+      break;
+    }
+    {
+      UNode& u = un[q];
+      const int par = u.parent;
+      u.hasC = !u.aa.empty() || (par >= 0 && un[par].hasC);
+      u.hasA = !u.sa.empty() || (par >= 0 && un[par].hasA);
+      u.hasB = !u.sb.empty() || (par >= 0 && un[par].hasB);
+      u.hasN = !u.nn.empty() || !u.ns.empty() || !u.sn.empty() || (par >= 0 && un[par].hasN);
+    }
+    const bool tc_split = un[q].tc >= 0 && C.nodes[un[q].tc].kind == BK_SPLIT;
+    if (rest.empty() && !tc_split) {
+      un[q].fin = true;
+      continue;
+    }
+    un[q].split = true;
+    std::vector<int> ct = TI.leaf(t) ? std::vector<int>{t} : TI.children[t];
+    std::vector<int> cr = TK.leaf(r) ? std::vector<int>{r} : TK.children[r];
+    const int belowq = un[q].below, depq = un[q].depth;
+    un[q].child0 = (int)un.size();
+    un[q].nchild = (int)(ct.size() * cr.size());
+    for (int t2 : ct)
+      for (int r2 : cr) {
+        std::vector<int> p2;  // product-tree children (Definition 7)
+        for (int s : rest) {
+          const auto& nx = bx.nodes[bx.find(t, s)];
+          const auto& ny = by.nodes[by.find(s, r)];
+          for (int c = 0; c < nx.nchild; ++c) {
+            const auto& cx = bx.nodes[nx.child0 + c];
+            if (cx.t != t2) continue;
+            int iy2 = by.find(cx.s, r2);
+            if (iy2 >= ny.child0 && iy2 < ny.child0 + ny.nchild) p2.push_back(cx.s);
+          }
+        }
+        UNode cn;
+        cn.t = t2;
+        cn.r = r2;
+        cn.parent = (int)q;
+        cn.depth = depq + 1;
+        if (tc_split) {
+          cn.tc = C.find(t2, r2);
+          if (cn.tc < 0) throw Error(H2_ERR_DEVICE, "planner: result tree mismatch");
+          cn.below = C.nodes[cn.tc].kind == BK_ADM ? cn.tc : -1;
+        } else {
+          cn.tc = -1;
+          cn.below = belowq;
+        }
+        un.push_back(cn);
+        pend.push_back(std::move(p2));
+      }
+  }
+  // Phi / Psi of split blocks need their split children
+  for (size_t i = 0; i < bx.nodes.size(); ++i)
+    if (phi_need[i] && bx.nodes[i].kind == BK_SPLIT)
+      for (int c = 0; c < bx.nodes[i].nchild; ++c) {
+        int ci = bx.nodes[i].child0 + c;
+        if (bx.nodes[ci].kind == BK_SPLIT) phi_need[ci] = 1;
+      }
+  for (size_t i = 0; i < by.nodes.size(); ++i)
+    if (psi_need[i] && by.nodes[i].kind == BK_SPLIT)
+      for (int c = 0; c < by.nodes[i].nchild; ++c) {
+        int ci = by.nodes[i].child0 + c;
+        if (by.nodes[ci].kind == BK_SPLIT) psi_need[ci] = 1;
+      }
+  bnode.assign(C.adm.size(), -1);
+  for (size_t i = 0; i < un.size(); ++i)
+    if (un[i].tc >= 0 && C.nodes[un[i].tc].kind == BK_ADM) bnode[C.nodes[un[i].tc].leaf_index] = (int)i;
+}
+
+template <typename T>
+void Planner::phaseA() {
+  const BlockTree& bx = X->bt;
+  const BlockTree& by = Y->bt;
+  constexpr bool isf = std::is_same<T, float>::value;
+  auto W = [&](int64_t n) { return WS<T>::get(B, n); };
+  auto ext = [&](double* d, float* f) {
+    if constexpr (isf) return DRef<float>::external(f);
+    else return DRef<double>::external(d);
+  };
+  auto newstep = [&]() { return GW<T>(B.step(WS<T>::kind)); };
+  auto R = [&](int64_t off) { return Tw<T>(off); };
+  const int kk = kX * kY;
+  B.phase = PH_PREP;
+  // ---------------- full cluster bases (eq. transfer), shared when identical ----------------
+  FB<T> VX, WX, VY, WY;
+  VX.T_ = &TI; VX.k = kX; VX.leaf = ext(X->V.leaf, X->V.leaf32); VX.tr = ext(X->V.transfer, X->V.transfer32);
+  WX.T_ = &TJ; WX.k = kX; WX.leaf = ext(X->W.leaf, X->W.leaf32); WX.tr = ext(X->W.transfer, X->W.transfer32);
+  VY.T_ = &TJ; VY.k = kY; VY.leaf = ext(Y->V.leaf, Y->V.leaf32); VY.tr = ext(Y->V.transfer, Y->V.transfer32);
+  WY.T_ = &TK; WY.k = kY; WY.leaf = ext(Y->W.leaf, Y->W.leaf32); WY.tr = ext(Y->W.transfer, Y->W.transfer32);
+  FB<T>* all[4] = {&VX, &WX, &VY, &WY};
+  std::vector<FB<T>*> uniq;
+  int alias[4];
+  for (int i = 0; i < 4; ++i) {
+    alias[i] = -1;
+    for (int j = 0; j < (int)uniq.size(); ++j)
+      if (uniq[j]->leaf.ext == all[i]->leaf.ext && uniq[j]->T_ == all[i]->T_) alias[i] = j;
+    if (alias[i] < 0) {
+      alias[i] = (int)uniq.size();
+      uniq.push_back(all[i]);
+    }
+  }
+  int depth = 0;
+  for (auto* b : uniq) {
+    depth = std::max(depth, b->T_->depth);
+    b->lvl.assign(b->T_->depth, DRef<T>());
+    for (int l = 0; l + 1 < b->T_->depth; ++l) b->lvl[l] = W(b->T_->n * b->k);
+  }
+  for (int l = depth - 2; l >= 0; --l) {
+    GW<T> g = newstep();
+    for (auto* b : uniq) {
+      const Tree& Tr = *b->T_;
+      if (l + 1 >= Tr.depth) continue;
+      for (int t = 0; t < Tr.ncl; ++t) {
+        if (Tr.level[t] != l || Tr.leaf(t)) continue;
+        for (int c : Tr.children[t]) {
+          g.task(b->lvl[l] + Tr.begin[c] * b->k, b->k, (int)Tr.size(c), b->k);
+          g.mm(b->full(c), b->k, b->E(c), b->k, b->k);
+        }
+      }
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    if (uniq[alias[i]] != all[i]) all[i]->lvl = uniq[alias[i]]->lvl;
+  // ---------------- basis products P_s = W_{X,s}^* V_{Y,s} (Section 4.1) ----------------
+  DRef<T> Pm = W((int64_t)TJ.ncl * kk);
+  {
+    GW<T> g = newstep();
+    for (int s = 0; s < TJ.ncl; ++s) {
+      g.task(Pm + (int64_t)s * kk, kY, kX, kY);
+      g.mm(WX.full(s), kX, VY.full(s), kY, (int)TJ.size(s), h2k::IT_TRANS_A);
+    }
+  }
+  auto Pref = [&](int s) { return Pm + (int64_t)s * kk; };
+  auto SX = [&](int node) { return ext(X->S, X->S32) + (int64_t)bx.nodes[node].leaf_index * kX * kX; };
+  auto SY = [&](int node) { return ext(Y->S, Y->S32) + (int64_t)by.nodes[node].leaf_index * kY * kY; };
+  auto NX = [&](int node) { return ext(X->N, X->N32) + X->noff[bx.nodes[node].leaf_index]; };
+  auto NY = [&](int node) { return ext(Y->N, Y->N32) + Y->noff[by.nodes[node].leaf_index]; };
+  // Q_{ts} = S_{X,ts} P_s for X's admissible leaves, Q'_{sr} = P_s S_{Y,sr} for Y's
+  DRef<T> Qx = W((int64_t)bx.adm.size() * kk), Qy = W((int64_t)by.adm.size() * kk);
+  auto QX = [&](int node) { return Qx + (int64_t)bx.nodes[node].leaf_index * kk; };
+  auto QY = [&](int node) { return Qy + (int64_t)by.nodes[node].leaf_index * kk; };
+  {
+    GW<T> g = newstep();
+    for (int node : bx.adm) {
+      g.task(QX(node), kY, kX, kY);
+      g.mm(SX(node), kX, Pref(bx.nodes[node].s), kY, kX);
+    }
+    for (int node : by.adm) {
+      g.task(QY(node), kY, kX, kY);
+      g.mm(Pref(by.nodes[node].t), kY, SY(node), kY, kY);
+    }
+  }
+  // ---------------- coefficients of admissible children for Phi / Psi ----------------
+  // Phi_{ts}|_{t'} gets V_{X,t'} * sum_{s' : (t',s') adm} Q_{t's'} E_{Y,s'}
+  // Psi_{sr}|_{r'} gets W_{Y,r'} * sum_{s' : (s',r') adm} Q'_{s'r'}^* F_{X,s'}
+  std::map<std::pair<int, int>, int64_t> cphi, cpsi;
+  {
+    GW<T> g = newstep();
+    for (size_t i = 0; i < bx.nodes.size(); ++i) {
+      if (!phi_need[i] || bx.nodes[i].kind != BK_SPLIT) continue;
+      const auto& nd = bx.nodes[i];
+      std::vector<int> rowsc;
+      for (int c = 0; c < nd.nchild; ++c) {
+        const auto& ch = bx.nodes[nd.child0 + c];
+        if (ch.kind == BK_ADM && std::find(rowsc.begin(), rowsc.end(), ch.t) == rowsc.end()) rowsc.push_back(ch.t);
+      }
+      for (int t2 : rowsc) {
+        DRef<T> d = W(kk);
+        cphi[{(int)i, t2}] = d.off;
+        g.task(d, kY, kX, kY);
+        for (int c = 0; c < nd.nchild; ++c) {
+          const auto& ch = bx.nodes[nd.child0 + c];
+          if (ch.kind != BK_ADM || ch.t != t2) continue;
+          if (ch.s == nd.s) g.copy(QX(nd.child0 + c), kY);
+          else g.mm(QX(nd.child0 + c), kY, VY.E(ch.s), kY, kY);
+        }
+      }
+    }
+    for (size_t i = 0; i < by.nodes.size(); ++i) {
+      if (!psi_need[i] || by.nodes[i].kind != BK_SPLIT) continue;
+      const auto& nd = by.nodes[i];
+      std::vector<int> colsc;
+      for (int c = 0; c < nd.nchild; ++c) {
+        const auto& ch = by.nodes[nd.child0 + c];
+        if (ch.kind == BK_ADM && std::find(colsc.begin(), colsc.end(), ch.s) == colsc.end()) colsc.push_back(ch.s);
+      }
+      for (int r2 : colsc) {
+        DRef<T> d = W(kk);
+        cpsi[{(int)i, r2}] = d.off;
+        g.task(d, kX, kY, kX);
+        for (int c = 0; c < nd.nchild; ++c) {
+          const auto& ch = by.nodes[nd.child0 + c];
+          if (ch.kind != BK_ADM || ch.s != r2) continue;
+          if (ch.t == nd.t) g.copy(QY(nd.child0 + c), kY, h2k::IT_TRANS_A);
+          else g.mm(QY(nd.child0 + c), kY, WX.E(ch.t), kX, kX, h2k::IT_TRANS_A);
+        }
+      }
+    }
+  }
+  // ---------------- Phi_{ts} = X|_{t x s} V_{Y,s},  Psi_{sr} = Y|_{s x r}^* W_{X,s} ----------------
+  std::vector<int64_t> phi(bx.nodes.size(), -1), psi(by.nodes.size(), -1);
+  int maxd = 0;
+  for (size_t i = 0; i < bx.nodes.size(); ++i)
+    if (phi_need[i]) {
+      phi[i] = W(TI.size(bx.nodes[i].t) * kY).off;
+      maxd = std::max(maxd, bx.nodes[i].depth);
+    }
+  for (size_t i = 0; i < by.nodes.size(); ++i)
+    if (psi_need[i]) {
+      psi[i] = W(TK.size(by.nodes[i].s) * kX).off;
+      maxd = std::max(maxd, by.nodes[i].depth);
+    }
+  for (int d = maxd; d >= 0; --d) {
+    GW<T> g = newstep();
+    for (size_t i = 0; i < bx.nodes.size(); ++i) {
+      if (!phi_need[i] || bx.nodes[i].depth != d) continue;
+      const auto& nd = bx.nodes[i];
+      const int t = nd.t, s = nd.s;
+      if (nd.kind == BK_INADM) {
+        g.task(R(phi[i]), kY, (int)TI.size(t), kY);
+        g.mm(NX((int)i), (int)TJ.size(s), VY.full(s), kY, (int)TJ.size(s));
+        continue;
+      }
+      std::vector<int> rowsc = TI.leaf(t) ? std::vector<int>{t} : TI.children[t];
+      for (int t2 : rowsc) {
+        g.task(R(phi[i]) + (TI.begin[t2] - TI.begin[t]) * kY, kY, (int)TI.size(t2), kY);
+        auto it = cphi.find({(int)i, t2});
+        if (it != cphi.end()) g.mm(VX.full(t2), kX, R(it->second), kY, kX);
+        for (int c = 0; c < nd.nchild; ++c) {
+          const int ci = nd.child0 + c;
+          const auto& ch = bx.nodes[ci];
+          if (ch.t != t2) continue;
+          if (ch.kind == BK_INADM) {
+            g.mm(NX(ci), (int)TJ.size(ch.s), VY.full(s) + (TJ.begin[ch.s] - TJ.begin[s]) * kY, kY,
+                 (int)TJ.size(ch.s));
+          } else if (ch.kind == BK_SPLIT) {
+            if (ch.s == s) g.copy(R(phi[ci]), kY);
+            else g.mm(R(phi[ci]), kY, VY.E(ch.s), kY, kY);
+          }
+        }
+      }
+    }
+    for (size_t i = 0; i < by.nodes.size(); ++i) {
+      if (!psi_need[i] || by.nodes[i].depth != d) continue;
+      const auto& nd = by.nodes[i];
+      const int s = nd.t, r = nd.s;
+      if (nd.kind == BK_INADM) {
+        g.task(R(psi[i]), kX, (int)TK.size(r), kX);
+        g.mm(NY((int)i), (int)TK.size(r), WX.full(s), kX, (int)TJ.size(s), h2k::IT_TRANS_A);
+        continue;
+      }
+      std::vector<int> colsc = TK.leaf(r) ? std::vector<int>{r} : TK.children[r];
+      for (int r2 : colsc) {
+        g.task(R(psi[i]) + (TK.begin[r2] - TK.begin[r]) * kX, kX, (int)TK.size(r2), kX);
+        auto it = cpsi.find({(int)i, r2});
+        if (it != cpsi.end()) g.mm(WY.full(r2), kY, R(it->second), kX, kY);
+        for (int c = 0; c < nd.nchild; ++c) {
+          const int ci = nd.child0 + c;
+          const auto& ch = by.nodes[ci];
+          if (ch.s != r2) continue;
+          if (ch.kind == BK_INADM) {
+            g.mm(NY(ci), (int)TK.size(r2), WX.full(s) + (TJ.begin[ch.t] - TJ.begin[s]) * kX, kX,
+                 (int)TJ.size(ch.t), h2k::IT_TRANS_A);
+          } else if (ch.kind == BK_SPLIT) {
+            if (ch.t == s) g.copy(R(psi[ci]), kX);
+            else g.mm(R(psi[ci]), kX, WX.E(ch.t), kX, kX);
+          }
+        }
+      }
+    }
+  }
+  // ---------------- dense strips for one-sided nearfield products (case 3) ----------------
+  // D^Y_{sr} = Y|_{s x r} for s a leaf, D^X_{ts} = X|_{t x s} for s a leaf
+  std::vector<int64_t> dy(by.nodes.size(), -1), dx(bx.nodes.size(), -1);
+  {
+    std::function<void(const BlockTree&, int, std::vector<int>&)> leaves = [&](const BlockTree& bt, int i,
+                                                                                std::vector<int>& out) {
+      const auto& nd = bt.nodes[i];
+      if (nd.kind != BK_SPLIT) {
+        out.push_back(i);
+        return;
+      }
+      for (int c = 0; c < nd.nchild; ++c) leaves(bt, nd.child0 + c, out);
+    };
+    std::map<int, int64_t> vs, sw;
+    GW<T> g1 = newstep();
+    for (size_t i = 0; i < by.nodes.size(); ++i) {
+      if (!dy_need[i]) continue;
+      const auto& nd = by.nodes[i];
+      dy[i] = W(TJ.size(nd.t) * TK.size(nd.s)).off;
+      std::vector<int> lv;
+      leaves(by, (int)i, lv);
+      for (int l : lv)
+        if (by.nodes[l].kind == BK_ADM && !vs.count(l)) {
+          vs[l] = W(TJ.size(nd.t) * kY).off;
+          g1.task(R(vs[l]), kY, (int)TJ.size(nd.t), kY);
+          g1.mm(VY.full(nd.t), kY, SY(l), kY, kY);
+        }
+    }
+    for (size_t i = 0; i < bx.nodes.size(); ++i) {
+      if (!dx_need[i]) continue;
+      const auto& nd = bx.nodes[i];
+      dx[i] = W(TI.size(nd.t) * TJ.size(nd.s)).off;
+      std::vector<int> lv;
+      leaves(bx, (int)i, lv);
+      for (int l : lv)
+        if (bx.nodes[l].kind == BK_ADM && !sw.count(l)) {
+          sw[l] = W((int64_t)kX * TJ.size(nd.s)).off;
+          g1.task(R(sw[l]), (int)TJ.size(nd.s), kX, (int)TJ.size(nd.s));
+          g1.mm(SX(l), kX, WX.full(nd.s), kX, kX, h2k::IT_TRANS_B);
+        }
+    }
+    GW<T> g2 = newstep();
+    for (size_t i = 0; i < by.nodes.size(); ++i) {
+      if (!dy_need[i]) continue;
+      const auto& nd = by.nodes[i];
+      const int s = nd.t, r = nd.s;
+      const int ld = (int)TK.size(r);
+      std::vector<int> lv;
+      leaves(by, (int)i, lv);
+      for (int l : lv) {
+        const auto& lf = by.nodes[l];
+        g2.task(R(dy[i]) + (TK.begin[lf.s] - TK.begin[r]), ld, (int)TJ.size(s), (int)TK.size(lf.s));
+        if (lf.kind == BK_ADM) g2.mm(R(vs[l]), kY, WY.full(lf.s), kY, kY, h2k::IT_TRANS_B);
+        else g2.copy(NY(l), (int)TK.size(lf.s));
+      }
+    }
+    for (size_t i = 0; i < bx.nodes.size(); ++i) {
+      if (!dx_need[i]) continue;
+      const auto& nd = bx.nodes[i];
+      const int t = nd.t, s = nd.s;
+      const int ld = (int)TJ.size(s);
+      std::vector<int> lv;
+      leaves(bx, (int)i, lv);
+      for (int l : lv) {
+        const auto& lf = bx.nodes[l];
+        g2.task(R(dx[i]) + (TI.begin[lf.t] - TI.begin[t]) * ld, ld, (int)TI.size(lf.t), ld);
+        if (lf.kind == BK_ADM) g2.mm(VX.full(lf.t), kX, R(sw[l]), ld, kX);
+        else g2.copy(NX(l), ld);
+      }
+    }
+  }
+  // ---------------- union tree: accumulators, top-down per depth ----------------
+  B.phase = PH_EXACT;
+  const int kU = kY + kX;
+  int64_t fin_first = -1, fin_last = -1;
+  auto fin_alloc = [&](int64_t n) {
+    DRef<T> d = W(n);
+    if (fin_first < 0) fin_first = d.off;
+    fin_last = d.off + ((std::max<int64_t>(n, 1) + (isf ? 63 : 31)) & ~int64_t(isf ? 63 : 31));
+    return d.off;
+  };
+  // final forms; their buffers form one contiguous region
+  for (auto& u : un) {
+    if (!u.fin) continue;
+    const int64_t m = TI.size(u.t), n = TK.size(u.r);
+    if (u.tc >= 0 && C.nodes[u.tc].kind == BK_INADM) {
+      u.form = 4;
+    } else if (u.hasN || std::min(m, n) < kU) {
+      u.form = (m >= n) ? 2 : 3;
+      u.offG = fin_alloc(m * n);
+    } else {
+      u.form = 1;
+      u.offG = fin_alloc(m * kU);
+      u.offZa = fin_alloc(n * kU);
+    }
+  }
+  int maxdep = 0;
+  for (auto& u : un) {
+    maxdep = std::max(maxdep, u.depth);
+    const int64_t m = TI.size(u.t), n = TK.size(u.r);
+    if (u.hasC) u.offC = W(kk).off;
+    if (u.hasA) {
+      if (u.form == 1) { u.offA = u.offG; u.ldA = kU; }
+      else { u.offA = W(m * kY).off; u.ldA = kY; }
+    }
+    if (u.hasB) {
+      if (u.form == 1) { u.offB = u.offZa + kY; u.ldB = kU; }
+      else { u.offB = W(n * kX).off; u.ldB = kX; }
+    }
+    if (u.hasN) u.offN = W(m * n).off;
+    if (u.parent >= 0 && un[u.parent].hasC && u.hasC && u.t != un[u.parent].t) u.offTmp = W(kk).off;
+    if (u.fin && u.hasC && u.form != 1) u.offVC = W(m * kY).off;
+  }
+  for (int d = 0; d <= maxdep; ++d) {
+    GW<T> g1 = newstep();
+    for (auto& u : un) {
+      if (u.depth != d || u.offTmp < 0) continue;
+      g1.task(R(u.offTmp), kY, kX, kY);
+      g1.mm(VX.E(u.t), kX, R(un[u.parent].offC), kY, kX);
+    }
+    GW<T> g2 = newstep();
+    for (auto& u : un) {
+      if (u.depth != d) continue;
+      const int t = u.t, r = u.r;
+      const int64_t m = TI.size(t), n = TK.size(r);
+      const UNode* p = u.parent >= 0 ? &un[u.parent] : nullptr;
+      if (u.hasC) {
+        g2.task(R(u.offC), kY, kX, kY);
+        if (p && p->hasC) {
+          DRef<T> src = u.offTmp >= 0 ? R(u.offTmp) : R(p->offC);
+          if (r == p->r) g2.copy(src, kY);
+          else g2.mm(src, kY, WY.E(r), kY, kY, h2k::IT_TRANS_B);
+        }
+        for (auto& pr : u.aa) g2.mm(QX(pr.first), kY, SY(pr.second), kY, kY);
+      }
+      if (u.hasA) {
+        g2.task(R(u.offA), u.ldA, (int)m, kY);
+        if (p && p->hasA) {
+          DRef<T> src = R(p->offA) + (TI.begin[t] - TI.begin[p->t]) * p->ldA;
+          if (r == p->r) g2.copy(src, p->ldA);
+          else g2.mm(src, p->ldA, WY.E(r), kY, kY, h2k::IT_TRANS_B);
+        }
+        for (auto& pr : u.sa) g2.mm(R(phi[pr.first]), kY, SY(pr.second), kY, kY);
+      }
+      if (u.hasB) {
+        g2.task(R(u.offB), u.ldB, (int)n, kX);
+        if (p && p->hasB) {
+          DRef<T> src = R(p->offB) + (TK.begin[r] - TK.begin[p->r]) * p->ldB;
+          if (t == p->t) g2.copy(src, p->ldB);
+          else g2.mm(src, p->ldB, VX.E(t), kX, kX, h2k::IT_TRANS_B);
+        }
+        for (auto& pr : u.sb) g2.mm(R(psi[pr.second]), kX, SX(pr.first), kX, kX, h2k::IT_TRANS_B);
+      }
+      if (u.hasN) {
+        g2.task(R(u.offN), (int)n, (int)m, (int)n);
+        if (p && p->hasN) {
+          const int64_t pn = TK.size(p->r);
+          g2.copy(R(p->offN) + (TI.begin[t] - TI.begin[p->t]) * pn + (TK.begin[r] - TK.begin[p->r]), (int)pn);
+        }
+        for (auto& pr : u.nn) {
+          const int s = bx.nodes[pr.first].s;
+          g2.mm(NX(pr.first), (int)TJ.size(s), NY(pr.second), (int)n, (int)TJ.size(s));
+        }
+        for (auto& pr : u.ns) {
+          const int s = bx.nodes[pr.first].s;
+          g2.mm(NX(pr.first), (int)TJ.size(s), R(dy[pr.second]), (int)n, (int)TJ.size(s));
+        }
+        for (auto& pr : u.sn) {
+          const int s = bx.nodes[pr.first].s;
+          g2.mm(R(dx[pr.first]), (int)TJ.size(s), NY(pr.second), (int)n, (int)TJ.size(s));
+        }
+      }
+    }
+  }
+  // ---------------- leaf blocks of the induced tree ----------------
+  B.phase = PH_LEAF;
+  P.cnoff.assign(C.inadm.size() + 1, 0);
+  int64_t noff = 0;
+  for (size_t i = 0; i < C.inadm.size(); ++i) {
+    P.cnoff[i] = noff;
+    const auto& nd = C.nodes[C.inadm[i]];
+    noff += TI.size(nd.t) * TK.size(nd.s);
+  }
+  P.cnoff[C.inadm.size()] = noff;
+  P.cnsize = noff;
+  P.res_N = B.wd(noff);
+  DRef<T> nearT;
+  if constexpr (isf) nearT = W(noff);
+  else nearT = P.res_N;
+  {
+    GW<T> g1 = newstep();
+    for (auto& u : un) {
+      if (u.offVC < 0) continue;
+      g1.task(R(u.offVC), kY, (int)TI.size(u.t), kY);
+      g1.mm(VX.full(u.t), kX, R(u.offC), kY, kX);
+    }
+    GW<T> g2 = newstep();
+    for (auto& u : un) {
+      if (!u.fin) continue;
+      const int t = u.t, r = u.r;
+      const int64_t m = TI.size(t), n = TK.size(r);
+      if (u.form == 1) {
+        // U = [A + V_X C | V_X],  Z = [W_Y | B]
+        g2.task(R(u.offG), kU, (int)m, kY, u.hasA ? 1 : 0);
+        if (u.hasC) g2.mm(VX.full(t), kX, R(u.offC), kY, kX);
+        g2.task(R(u.offG) + kY, kU, (int)m, kX);
+        g2.copy(VX.full(t), kX);
+        g2.task(R(u.offZa), kU, (int)n, kY);
+        g2.copy(WY.full(r), kY);
+        if (!u.hasB) g2.task(R(u.offZa) + kY, kU, (int)n, kX);
+        continue;
+      }
+      // G = A W^* + (V C) W^* + V B^* + N, or its transpose for form 3
+      DRef<T> out = (u.form == 4) ? nearT + P.cnoff[C.nodes[u.tc].leaf_index] : R(u.offG);
+      if (u.form != 3) {
+        g2.task(out, (int)n, (int)m, (int)n);
+        if (u.hasA) g2.mm(R(u.offA), u.ldA, WY.full(r), kY, kY, h2k::IT_TRANS_B);
+        if (u.hasC) g2.mm(R(u.offVC), kY, WY.full(r), kY, kY, h2k::IT_TRANS_B);
+        if (u.hasB) g2.mm(VX.full(t), kX, R(u.offB), u.ldB, kX, h2k::IT_TRANS_B);
+        if (u.hasN) g2.copy(R(u.offN), (int)n);
+      } else {
+        g2.task(out, (int)m, (int)n, (int)m);
+        if (u.hasA) g2.mm(WY.full(r), kY, R(u.offA), u.ldA, kY, h2k::IT_TRANS_B);
+        if (u.hasC) g2.mm(WY.full(r), kY, R(u.offVC), kY, kY, h2k::IT_TRANS_B);
+        if (u.hasB) g2.mm(R(u.offB), u.ldB, VX.full(t), kX, kX, h2k::IT_TRANS_B);
+        if (u.hasN) g2.copy(R(u.offN), (int)n, h2k::IT_TRANS_A);
+      }
+    }
+  }
+  // ---------------- hand over to the FP64 recompression ----------------
+  int64_t shift = 0;
+  if constexpr (isf) {
+    if (fin_last > fin_first && fin_first >= 0) {
+      DRef<double> d64 = B.wd(fin_last - fin_first);
+      shift = d64.off - fin_first;
+      Step& st = B.step(SK_CVT_F2D);
+      st.cvt_in = Tw<float>(fin_first);
+      st.cvt_out = d64;
+      st.cvt_n = fin_last - fin_first;
+    }
+    if (noff > 0) {
+      Step& st = B.step(SK_CVT_F2D);
+      st.cvt_in = nearT;
+      st.cvt_out = P.res_N;
+      st.cvt_n = noff;
+    }
+  }
+  for (auto& u : un) {
+    if (!u.fin || u.form == 4 || u.below < 0) continue;
+    const int64_t m = TI.size(u.t), n = TK.size(u.r);
+    u.m = (int)m;
+    u.n = (int)n;
+    if (u.form == 1) {
+      u.K = kU;
+      u.U = u.offG + shift;
+      u.Z = u.offZa + shift;
+    } else if (u.form == 2) {  // U = G, Z = I
+      u.K = (int)n;
+      u.U = u.offG + shift;
+      u.Z = -2;
+    } else {  // U = I, Z = G^T
+      u.K = (int)m;
+      u.U = -2;
+      u.Z = u.offG + shift;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ coarsening
+void Planner::coarsen() {
+  B.phase = PH_COARSE;
+  // Merge tree below every admissible result leaf: the leaves are the final
+  // nodes of the induced tree (exact factors U, Z); every split node of the
+  // induced tree merges its children pairwise (first the column pairs of
+  // each row child, then the rows), so a merge never joins more than two
+  // truncated pieces (width <= 2 * kcap).
+  struct MNode {
+    int t = 0, r = 0, m = 0, n = 0, K = 0, height = 0, below = -1, unode = -1;
+    int c0 = -1, c1 = -1;  // merged children (MNode indices), -1 for leaves
+    int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
+            Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1;
+  };
+  std::vector<MNode> mn;
+  std::vector<int> of_un(un.size(), -1);
+  std::function<int(int)> make = [&](int ui) -> int {
+    UNode& u = un[ui];
+    MNode x;
+    x.t = u.t;
+    x.r = u.r;
+    x.m = (int)TI.size(u.t);
+    x.n = (int)TK.size(u.r);
+    x.below = u.below;
+    x.unode = ui;
+    if (u.fin) {
+      x.K = u.K;
+      x.U = u.U;
+      x.Z = u.Z;
+      mn.push_back(x);
+      return of_un[ui] = (int)mn.size() - 1;
+    }
+    std::vector<int> kids;
+    for (int c = 0; c < u.nchild; ++c) kids.push_back(make(u.child0 + c));
+    auto merge = [&](int a, int b, int t, int r) {
+      MNode y;
+      y.t = t;
+      y.r = r;
+      y.m = (int)TI.size(t);
+      y.n = (int)TK.size(r);
+      y.below = u.below;
+      y.c0 = a;
+      y.c1 = b;
+      y.height = 1 + std::max(mn[a].height, mn[b].height);
+      mn.push_back(y);
+      return (int)mn.size() - 1;
+    };
+    int root;
+    if (kids.size() == 4) {  // children (t1,r1), (t1,r2), (t2,r1), (t2,r2)
+      int v1 = merge(kids[0], kids[1], mn[kids[0]].t, u.r);
+      int v2 = merge(kids[2], kids[3], mn[kids[2]].t, u.r);
+      root = merge(v1, v2, u.t, u.r);
+    } else if (kids.size() == 2) {
+      root = merge(kids[0], kids[1], u.t, u.r);
+    } else {
+      throw Error(H2_ERR_DEVICE, "planner: unexpected number of induced children");
+    }
+    mn[root].unode = ui;
+    return of_un[ui] = root;
+  };
+  for (size_t li = 0; li < C.adm.size(); ++li) make(bnode[li]);
+  int maxh = 0;
+  for (auto& x : mn) maxh = std::max(maxh, x.height);
+  // Truncation errors of all merges of a block add up exactly; merges of equal
+  // height act on disjoint sub-blocks, so with a Frobenius tail <= tau at every
+  // merge the total error is at most tau * sum_h sqrt(n_h).  tau_b = delta_c *
+  // nu_b / sum_h sqrt(n_h), nu_b a lower bound of ||G_b|| from the leaves.
+  std::map<int, std::map<int, int>> per_height;
+  for (auto& x : mn) per_height[x.below][x.height]++;
+  std::map<int, double> hsum;
+  std::map<int, int64_t> tau;
+  for (auto& kv : per_height) {
+    double sum = 0;
+    for (auto& hv : kv.second) sum += std::sqrt((double)hv.second);
+    hsum[kv.first] = sum;
+    tau[kv.first] = B.wd(1).off;
+  }
+  P.max_coarse_K = 0;
+  for (int h = 0; h <= maxh; ++h) {
+    std::vector<int> lv;
+    for (size_t i = 0; i < mn.size(); ++i)
+      if (mn[i].height == h) lv.push_back((int)i);
+    if (lv.empty()) continue;
+    if (h > 0) {  // U = [ext(U^_a S_a), ext(U^_b S_b)],  Z = [ext(V^_a), ext(V^_b)]
+      Step& fs = B.step(SK_FILL);
+      for (int i : lv) {
+        MNode& x = mn[i];
+        x.K = 2 * kcap;
+        x.U = B.wd((int64_t)x.m * x.K).off;
+        x.Z = B.wd((int64_t)x.n * x.K).off;
+        fs.fill.push_back({Dw(x.U), x.K, x.m, x.K, 0, 0.0});
+        fs.fill.push_back({Dw(x.Z), x.K, x.n, x.K, 0, 0.0});
+      }
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        int kid[2] = {x.c0, x.c1};
+        for (int c = 0; c < 2; ++c) {
+          const MNode& ch = mn[kid[c]];
+          const int64_t ro = TI.begin[ch.t] - TI.begin[x.t], co = TK.begin[ch.r] - TK.begin[x.r];
+          g.task(Dw(x.U) + ro * x.K + c * kcap, x.K, ch.m, kcap);
+          g.mm(Dw(ch.Uh), kcap, Dw(ch.Sb), kcap, kcap);
+          g.task(Dw(x.Z) + co * x.K + c * kcap, x.K, ch.n, kcap);
+          g.copy(Dw(ch.Vh), kcap);
+        }
+      }
+    } else {
+      Step& fs = B.step(SK_FILL);
+      for (int i : lv) {
+        MNode& x = mn[i];
+        if (x.U == -2) {
+          x.U = B.wd((int64_t)x.m * x.K).off;
+          fs.fill.push_back({Dw(x.U), x.K, x.m, x.K, 1, 1.0});
+        }
+        if (x.Z == -2) {
+          x.Z = B.wd((int64_t)x.n * x.K).off;
+          fs.fill.push_back({Dw(x.Z), x.K, x.n, x.K, 1, 1.0});
+        }
+      }
+    }
+    int wmax = 0;
+    for (int i : lv) {
+      MNode& x = mn[i];
+      wmax = std::max(wmax, x.K);
+      P.max_coarse_K = std::max(P.max_coarse_K, x.K);
+      if (x.K > 128) throw Error(H2_ERR_TOO_LARGE, "coarsening width above 128");
+      x.RZ = B.wd((int64_t)x.K * x.K).off;
+      x.Gh = B.wd((int64_t)x.m * x.K).off;
+      x.RGt = B.wd((int64_t)x.K * x.K).off;
+      x.Vk = B.wd((int64_t)x.K * kcap).off;
+      x.Sig = B.wd(x.K).off;
+      x.Kap = B.wi(1).off;
+      x.Yk = B.wd((int64_t)x.m * kcap).off;
+      x.Gy = B.wd((int64_t)kcap * kcap).off;
+      x.T1 = B.wd((int64_t)kcap * kcap).off;
+      x.R1 = B.wd((int64_t)kcap * kcap).off;
+      x.Uh = B.wd((int64_t)x.m * kcap).off;
+      x.Tm = B.wd((int64_t)x.K * kcap).off;
+      x.Zh = B.wd((int64_t)x.n * kcap).off;
+      x.Gz = B.wd((int64_t)kcap * kcap).off;
+      x.T2 = B.wd((int64_t)kcap * kcap).off;
+      x.R2 = B.wd((int64_t)kcap * kcap).off;
+      x.Vh = B.wd((int64_t)x.n * kcap).off;
+      x.Sb = B.wd((int64_t)kcap * kcap).off;
+    }
+    {  // R_Z: R factor of Z
+      Step& st = B.step(SK_QR);
+      st.wmax = wmax;
+      for (int i : lv) {
+        MNode& x = mn[i];
+        st.qr.push_back({Dw(x.Z), Dw(x.RZ), x.K, x.K, x.n, x.K, 0});
+      }
+    }
+    {  // condensed block G^ = U R_Z^* (same singular values as U Z^*)
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Gh), x.K, x.m, x.K);
+        g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
+      }
+    }
+    {  // R factor of G^, stored transposed
+      Step& st = B.step(SK_QR);
+      st.wmax = wmax;
+      for (int i : lv) {
+        MNode& x = mn[i];
+        st.qr.push_back({Dw(x.Gh), Dw(x.RGt), x.K, x.K, x.m, x.K, 1});
+      }
+    }
+    if (h == 0) {  // lower bounds of the block norms: largest column norm of the leaves' condensed factors
+      Step& st = B.step(SK_REF);
+      std::map<int, std::vector<int>> byb;
+      for (int i : lv) byb[mn[i].below].push_back(i);
+      for (auto& kv : byb) {
+        PRef r;
+        r.first = (int)st.refmat.size();
+        r.count = (int)kv.second.size();
+        r.factor = 1.0 / hsum[kv.first];
+        r.out = Dw(tau[kv.first]);
+        for (int i : kv.second) st.refmat.push_back({Dw(mn[i].RGt), mn[i].K, mn[i].K, mn[i].K});
+        st.ref.push_back(r);
+      }
+    }
+    {  // right singular vectors of G^ (left ones of R^*), Frobenius tail <= tau_b
+      Step& st = B.step(SK_SVD);
+      st.wmax = wmax;
+      for (int i : lv) {
+        MNode& x = mn[i];
+        PSvd s;
+        s.a = Dw(x.RGt);
+        s.u = Dw(x.Vk);
+        s.sigma = Dw(x.Sig);
+        s.rank = Iw(x.Kap);
+        s.tolref = Dw(tau[x.below]);
+        s.tolkind = 0;
+        s.tolfactor = 1.0;
+        s.lda = x.K;
+        s.ldu = kcap;
+        s.rows = x.K;
+        s.cols = x.K;
+        s.kcap = kcap;
+        st.svd.push_back(s);
+      }
+    }
+    {  // Y = G^ V_k  (= U^ Sigma)
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Yk), kcap, x.m, kcap);
+        g.mm(Dw(x.Gh), x.K, Dw(x.Vk), kcap, x.K);
+      }
+    }
+    {
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Gy), kcap, kcap, kcap);
+        g.mm(Dw(x.Yk), kcap, Dw(x.Yk), kcap, x.m, h2k::IT_TRANS_A);
+      }
+    }
+    {
+      Step& st = B.step(SK_CHOL);
+      st.wmax = kcap;
+      for (int i : lv) {
+        MNode& x = mn[i];
+        st.chol.push_back({Dw(x.Gy), Dw(x.T1), Dw(x.R1), Iw(x.Kap), kcap, kcap, kcap, kcap});
+      }
+    }
+    {  // U^ = Y T1 (orthonormal columns)
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Uh), kcap, x.m, kcap);
+        g.mm(Dw(x.Yk), kcap, Dw(x.T1), kcap, kcap);
+      }
+    }
+    {
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Tm), kcap, x.K, kcap);
+        g.mm(Dw(x.U), x.K, Dw(x.Uh), kcap, x.m, h2k::IT_TRANS_A);
+      }
+    }
+    {  // Z^ = Z (U^* U^) = G^* U^:  G~ = U^ U^^* G = U^ Z^^*
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Zh), kcap, x.n, kcap);
+        g.mm(Dw(x.Z), x.K, Dw(x.Tm), kcap, x.K);
+      }
+    }
+    {
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Gz), kcap, kcap, kcap);
+        g.mm(Dw(x.Zh), kcap, Dw(x.Zh), kcap, x.n, h2k::IT_TRANS_A);
+      }
+    }
+    {
+      Step& st = B.step(SK_CHOL);
+      st.wmax = kcap;
+      for (int i : lv) {
+        MNode& x = mn[i];
+        st.chol.push_back({Dw(x.Gz), Dw(x.T2), Dw(x.R2), Iw(x.Kap), kcap, kcap, kcap, kcap});
+      }
+    }
+    {  // V^ = Z^ T2, S = R2^*:  G~ = U^ S V^^*
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Vh), kcap, x.n, kcap);
+        g.mm(Dw(x.Zh), kcap, Dw(x.T2), kcap, kcap);
+        g.task(Dw(x.Sb), kcap, kcap, kcap);
+        g.copy(Dw(x.R2), kcap, h2k::IT_TRANS_A);
+      }
+    }
+  }
+  // outputs of each block's root merge, used by the basis construction
+  for (size_t li = 0; li < C.adm.size(); ++li) {
+    UNode& u = un[bnode[li]];
+    const MNode& x = mn[of_un[bnode[li]]];
+    u.Uh = x.Uh;
+    u.Vh = x.Vh;
+    u.Sb = x.Sb;
+    u.Sig = x.Sig;
+    u.Kap = x.Kap;
+  }
+}
+
+// ------------------------------------------------------------------ adaptive bases
+void Planner::basis(bool rows) {
+  B.phase = rows ? PH_ROW : PH_COL;
+  const Tree& T = rows ? TI : TK;
+  std::vector<std::vector<int>> own(T.ncl);
+  for (size_t li = 0; li < C.adm.size(); ++li) {
+    const auto& nd = C.nodes[C.adm[li]];
+    own[rows ? nd.t : nd.s].push_back((int)li);
+  }
+  DRef<double> leafout = rows ? P.res_vleaf : P.res_wleaf;
+  DRef<double> trout = rows ? P.res_vtr : P.res_wtr;
+  DRef<int> rankout = rows ? P.res_rank_row : P.res_rank_col;
+  const int kk = kc * kc;
+  std::vector<std::map<int, int64_t>> proj(T.ncl);
+  std::vector<std::vector<int>> star(T.ncl);  // row*(s) / col*(s)
+  for (int s = 0; s < T.ncl; ++s) {
+    for (int a = s; a >= 0; a = T.parent[a])
+      for (int li : own[a]) star[s].push_back(li);
+    for (int li : star[s]) proj[s][li] = B.wd((int64_t)kc * kcap).off;
+  }
+  std::vector<int64_t> vhat(T.ncl, -1);
+  const double th = P.theta;
+  const int sflag = rows ? h2k::IT_TRANS_A : 0;
+  for (int lev = T.depth - 1; lev >= 0; --lev) {
+    std::vector<int> cl;
+    for (int s = 0; s < T.ncl; ++s)
+      if (T.level[s] == lev) cl.push_back(s);
+    if (cl.empty()) continue;
+    std::vector<int64_t> gst(T.ncl, -1), rt(T.ncl, -1);
+    std::vector<int> wcol(T.ncl, 0);
+    {  // weighted condensed blocks (transposed, kcap rows per block)
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int s : cl) {
+        const bool lf = T.leaf(s);
+        const int w = lf ? (int)T.size(s) : 2 * kc;
+        wcol[s] = w;
+        const int nrow = (int)star[s].size() * kcap;
+        gst[s] = B.wd((int64_t)std::max(nrow, 1) * w).off;
+        for (size_t j = 0; j < star[s].size(); ++j) {
+          const int li = star[s][j];
+          const UNode& u = un[bnode[li]];
+          const auto& nd = C.nodes[C.adm[li]];
+          const int owner = rows ? nd.t : nd.s;
+          // 1/omega = theta^{-(level s - level owner)/2} / ||G~_b||
+          const double alpha = std::pow(th, -0.5 * (T.level[s] - T.level[owner]));
+          const DRef<double> out = Dw(gst[s]) + (int64_t)j * kcap * w;
+          const int fl = sflag | h2k::IT_TRANS_B | h2k::IT_SCALE_INV;
+          if (lf) {
+            const int64_t roff = T.begin[s] - T.begin[owner];
+            g.task(out, w, kcap, w);
+            g.mm(Dw(u.Sb), kcap, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
+          } else {
+            const int c0 = T.children[s][0], c1 = T.children[s][1];
+            g.task(out, w, kcap, kc);
+            g.mm(Dw(u.Sb), kcap, Dw(proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+            g.task(out + kc, w, kcap, kc);
+            g.mm(Dw(u.Sb), kcap, Dw(proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+          }
+        }
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {  // QR: one launch per width class
+      Step& st = B.step(SK_QR);
+      for (int s : cl) {
+        const int w = wcol[s];
+        if (w > 128) throw Error(H2_ERR_TOO_LARGE, "leaf size above 128");
+        if ((w > 64) != (pass == 1)) continue;
+        st.wmax = std::max(st.wmax, w);
+        rt[s] = B.wd((int64_t)w * w).off;
+        st.qr.push_back({Dw(gst[s]), Dw(rt[s]), w, w, (int)star[s].size() * kcap, w, 1});
+      }
+    }
+    for (int pass = 0; pass < 2; ++pass) {  // left singular vectors of the weighted matrix
+      Step& st = B.step(SK_SVD);
+      for (int s : cl) {
+        const int w = wcol[s];
+        if ((w > 64) != (pass == 1)) continue;
+        st.wmax = std::max(st.wmax, w);
+        PSvd v;
+        v.a = Dw(rt[s]);
+        if (T.leaf(s)) v.u = leafout + T.begin[s] * kc;
+        else {
+          vhat[s] = B.wd((int64_t)w * kc).off;
+          v.u = Dw(vhat[s]);
+        }
+        v.sigma = Dw(B.wd(w).off);
+        v.rank = rankout + s;
+        v.tolkind = rows ? 1 : 2;
+        v.tolfactor = 1.0;
+        v.lda = w;
+        v.ldu = kc;
+        v.rows = w;
+        v.cols = w;
+        v.kcap = kc;
+        st.svd.push_back(v);
+      }
+    }
+    {  // transfers and projections G^_{s,b} = V_s^* G^c_b|_s (coefficient part)
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int s : cl) {
+        if (T.leaf(s)) {
+          for (int li : star[s]) {
+            const UNode& u = un[bnode[li]];
+            const auto& nd = C.nodes[C.adm[li]];
+            const int owner = rows ? nd.t : nd.s;
+            const int64_t roff = T.begin[s] - T.begin[owner];
+            g.task(Dw(proj[s][li]), kcap, kc, kcap);
+            g.mm(leafout + T.begin[s] * kc, kc, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, (int)T.size(s),
+                 h2k::IT_TRANS_A);
+          }
+        } else {
+          const int c0 = T.children[s][0], c1 = T.children[s][1];
+          g.task(trout + (int64_t)c0 * kk, kc, kc, kc);
+          g.copy(Dw(vhat[s]), kc);
+          g.task(trout + (int64_t)c1 * kk, kc, kc, kc);
+          g.copy(Dw(vhat[s]) + (int64_t)kc * kc, kc);
+          for (int li : star[s]) {
+            g.task(Dw(proj[s][li]), kcap, kc, kcap);
+            g.mm(Dw(vhat[s]), kc, Dw(proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
+            g.mm(Dw(vhat[s]) + (int64_t)kc * kc, kc, Dw(proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
+          }
+        }
+      }
+    }
+  }
+  if (rows) row_proj = std::move(proj);
+  else col_proj = std::move(proj);
+}
+
+// ------------------------------------------------------------------ couplings
+void Planner::couplings() {
+  B.phase = PH_COUPLE;
+  const int kk = kc * kc;
+  std::vector<int64_t> tmp(C.adm.size());
+  {
+    GW<double> g(B.step(SK_GEMM_D));
+    for (size_t li = 0; li < C.adm.size(); ++li) {
+      const auto& nd = C.nodes[C.adm[li]];
+      const UNode& u = un[bnode[li]];
+      tmp[li] = B.wd((int64_t)kc * kcap).off;
+      g.task(Dw(tmp[li]), kcap, kc, kcap);
+      g.mm(Dw(row_proj[nd.t][(int)li]), kcap, Dw(u.Sb), kcap, kcap);
+    }
+  }
+  {  // S_b = (V_t^* U^) S (W_r^* V^)^*
+    GW<double> g(B.step(SK_GEMM_D));
+    for (size_t li = 0; li < C.adm.size(); ++li) {
+      const auto& nd = C.nodes[C.adm[li]];
+      g.task(P.res_S + (int64_t)li * kk, kc, kc, kc);
+      g.mm(Dw(tmp[li]), kcap, Dw(col_proj[nd.s][(int)li]), kcap, kcap, h2k::IT_TRANS_B);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ finalisation
+template <typename T>
+static T* res(const DRef<T>& r, const Plan& P) {
+  if (r.ws == WS_NONE) return r.ext ? r.ext + r.off : nullptr;
+  if (r.ws == WS_D) return reinterpret_cast<T*>(P.bufd.as<double>() + r.off);
+  if (r.ws == WS_F) return reinterpret_cast<T*>(P.buff.as<float>() + r.off);
+  return reinterpret_cast<T*>(P.bufi.as<int>() + r.off);
+}
+
+template <typename T>
+static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vector<PItem<T>>& it,
+                      const std::vector<PTask<T>>& tk) {
+  auto align = [&](size_t a) {
+    while (blob.size() % a) blob.push_back(0);
+  };
+  align(64);
+  st.desc_off = blob.size();
+  std::vector<GemmItem<T>> items(it.size());
+  for (size_t i = 0; i < it.size(); ++i) {
+    items[i].a = res(it[i].a, P);
+    items[i].b = res(it[i].b, P);
+    items[i].scale = res(it[i].scale, P);
+    items[i].lda = it[i].lda;
+    items[i].ldb = it[i].ldb;
+    items[i].k = it[i].k;
+    items[i].flags = it[i].flags;
+    items[i].alpha = it[i].alpha;
+  }
+  blob.insert(blob.end(), (char*)items.data(), (char*)(items.data() + items.size()));
+  align(64);
+  st.desc2_off = blob.size();
+  std::vector<GemmTask<T>> tasks(tk.size());
+  std::vector<GemmTile> tiles;
+  for (size_t i = 0; i < tk.size(); ++i) {
+    tasks[i].c = res(tk[i].c, P);
+    tasks[i].ldc = tk[i].ldc;
+    tasks[i].m = tk[i].m;
+    tasks[i].n = tk[i].n;
+    tasks[i].item0 = tk[i].item0;
+    tasks[i].nitem = tk[i].nitem;
+    tasks[i].beta = tk[i].beta;
+    tasks[i].pad = 0;
+    for (int m0 = 0; m0 < tk[i].m; m0 += 64)
+      for (int n0 = 0; n0 < tk[i].n; n0 += 64) tiles.push_back({(int)i, m0, n0, 0});
+  }
+  blob.insert(blob.end(), (char*)tasks.data(), (char*)(tasks.data() + tasks.size()));
+  align(64);
+  st.tiles_off = blob.size();
+  blob.insert(blob.end(), (char*)tiles.data(), (char*)(tiles.data() + tiles.size()));
+  st.ntiles = (int)tiles.size();
+  st.ndesc = (int)tasks.size();
+}
+
+static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, bool inplace) {
+  std::vector<h2k::SvdTask> v(st.svd.size());
+  const double dc = eps * P.budget[0], dr = eps * P.budget[1], dw = eps * P.budget[2];
+  const double scale = std::sqrt(1.0 - P.sigma_br * P.theta);
+  for (size_t i = 0; i < st.svd.size(); ++i) {
+    const PSvd& s = st.svd[i];
+    v[i].a = res(s.a, P);
+    v[i].u = res(s.u, P);
+    v[i].sigma = res(s.sigma, P);
+    v[i].rank = res(s.rank, P);
+    v[i].tol_abs = 0.0;
+    v[i].tol_rel = 0.0;
+    v[i].tol_ptr = res(s.tolref, P);
+    v[i].tol_scale = 0.0;
+    v[i].frob = 0;
+    if (s.tolkind == 0) {
+      v[i].tol_scale = dc * s.tolfactor;
+      v[i].frob = 1;
+      v[i].ovf_bit = 1;
+    } else {
+      v[i].tol_abs = (s.tolkind == 1 ? dr : dw) * scale;
+      v[i].ovf_bit = 2;
+    }
+    v[i].lda = s.lda;
+    v[i].ldu = s.ldu;
+    v[i].rows = s.rows;
+    v[i].cols = s.cols;
+    v[i].kcap = s.kcap;
+    v[i].trans_a = 0;
+  }
+  if (!inplace) {
+    while (blob.size() % 64) blob.push_back(0);
+    st.desc_off = blob.size();
+    blob.insert(blob.end(), (char*)v.data(), (char*)(v.data() + v.size()));
+  } else {
+    std::memcpy(blob.data() + st.desc_off, v.data(), v.size() * sizeof(h2k::SvdTask));
+  }
+  st.ndesc = (int)v.size();
+}
+
+static void finalize(Plan& P, double eps) {
+  P.bufd.alloc(std::max<int64_t>(P.wsd, 1) * sizeof(double));
+  P.buff.alloc(std::max<int64_t>(P.wsf, 1) * sizeof(float));
+  P.bufi.alloc(std::max<int64_t>(P.wsi, 1) * sizeof(int));
+  std::vector<char> blob;
+  auto align = [&](size_t a) {
+    while (blob.size() % a) blob.push_back(0);
+  };
+  for (auto& st : P.steps) {
+    switch (st.kind) {
+      case SK_GEMM_D: emit_gemm(P, st, blob, st.itd, st.tkd); break;
+      case SK_GEMM_F: emit_gemm(P, st, blob, st.itf, st.tkf); break;
+      case SK_QR: {
+        align(64);
+        st.desc_off = blob.size();
+        for (auto& q : st.qr) {
+          h2k::QrTask t{res(q.a, P), res(q.r, P), q.lda, q.ldr, q.m, q.w, q.trans_r, 0};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        st.ndesc = (int)st.qr.size();
+        break;
+      }
+      case SK_SVD: resolve_svd(P, st, blob, eps, false); break;
+      case SK_CHOL: {
+        align(64);
+        st.desc_off = blob.size();
+        for (auto& c : st.chol) {
+          h2k::CholTask t{res(c.g, P), res(c.t, P), res(c.r, P), res(c.weff, P), c.ldg, c.ldt, c.ldr, c.w};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        st.ndesc = (int)st.chol.size();
+        break;
+      }
+      case SK_FILL: {
+        align(64);
+        st.desc_off = blob.size();
+        for (auto& f : st.fill) {
+          h2k::FillTask t{res(f.p, P), f.ld, f.m, f.n, 0, f.value, f.diag, 8};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        st.ndesc = (int)st.fill.size();
+        break;
+      }
+      case SK_REF: {
+        align(64);
+        st.desc_off = blob.size();
+        for (auto& r : st.ref) {
+          h2k::RefTask t{r.first, r.count, r.factor, res(r.out, P)};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        align(64);
+        st.desc2_off = blob.size();
+        for (auto& m : st.refmat) {
+          h2k::RefMat t{res(m.a, P), m.lda, m.rows, m.cols};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        st.ndesc = (int)st.ref.size();
+        break;
+      }
+      case SK_CVT_F2D: break;
+    }
+  }
+  P.hdesc = blob;
+  P.desc.alloc(std::max<size_t>(blob.size(), 64));
+  H2_HIP(hipMemcpy(P.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  P.eps_set = eps;
+  // descriptors are on the device; drop the host-side proto lists of GEMM steps
+  for (auto& st : P.steps) {
+    st.itd.clear(); st.itd.shrink_to_fit();
+    st.tkd.clear(); st.tkd.shrink_to_fit();
+    st.itf.clear(); st.itf.shrink_to_fit();
+    st.tkf.clear(); st.tkf.shrink_to_fit();
+  }
+}
+
+static void set_eps(Plan& P, double eps) {
+  if (P.eps_set == eps) return;
+  for (auto& st : P.steps)
+    if (st.kind == SK_SVD) {
+      resolve_svd(P, st, P.hdesc, eps, true);
+      H2_HIP(hipMemcpy((char*)P.desc.p + st.desc_off, P.hdesc.data() + st.desc_off,
+                       st.ndesc * sizeof(h2k::SvdTask), hipMemcpyHostToDevice));
+    }
+  P.eps_set = eps;
+}
+
+static void execute(Context* ctx, Plan& P, bool timing, bool per_kind, double* t_phase) {
+  hipStream_t s = ctx->stream;
+  char* base = (char*)P.desc.p;
+  std::vector<hipEvent_t> ev;
+  int cur_phase = -1;
+  if (timing) {
+    ev.resize(16);
+    for (auto& e : ev) H2_HIP(hipEventCreate(&e));
+  }
+  std::vector<int> phase_mark;  // event index -> phase
+  int nev = 0;
+  auto mark = [&](int ph) {
+    if (!timing) return;
+    H2_HIP(hipEventRecord(ev[nev], s));
+    phase_mark.push_back(ph);
+    ++nev;
+  };
+  P.launches = 0;
+  for (int i = 0; i < 8; ++i) {
+    P.t_kind[i] = 0;
+    P.bytes_kind[i] = 0;
+    P.flops_kind[i] = 0;
+    P.launches_kind[i] = 0;
+  }
+  const bool per_step = timing && per_kind;
+  std::vector<hipEvent_t> sev;
+  if (per_step) {
+    sev.resize(2 * P.steps.size());
+    for (auto& e : sev) H2_HIP(hipEventCreate(&e));
+  }
+  size_t si = 0;
+  for (auto& st : P.steps) {
+    if (st.phase != cur_phase) {
+      mark(st.phase);
+      cur_phase = st.phase;
+    }
+    if (per_step) H2_HIP(hipEventRecord(sev[2 * si], s));
+    switch (st.kind) {
+      case SK_GEMM_D:
+        h2k::launch_gemm_f64((const GemmItem<double>*)(base + st.desc_off), (const GemmTask<double>*)(base + st.desc2_off),
+                             (const GemmTile*)(base + st.tiles_off), st.ntiles, s);
+        P.launches += st.ntiles > 0;
+        break;
+      case SK_GEMM_F:
+        h2k::launch_gemm_f32((const GemmItem<float>*)(base + st.desc_off), (const GemmTask<float>*)(base + st.desc2_off),
+                             (const GemmTile*)(base + st.tiles_off), st.ntiles, s);
+        P.launches += st.ntiles > 0;
+        break;
+      case SK_QR:
+        h2k::launch_qr((const h2k::QrTask*)(base + st.desc_off), st.ndesc, st.wmax, s);
+        P.launches += st.ndesc > 0;
+        break;
+      case SK_SVD:
+        h2k::launch_svd((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, st.wmax, ctx->overflow, s);
+        P.launches += st.ndesc > 0;
+        break;
+      case SK_CHOL:
+        h2k::launch_chol((const h2k::CholTask*)(base + st.desc_off), st.ndesc, st.wmax, s);
+        P.launches += st.ndesc > 0;
+        break;
+      case SK_FILL:
+        h2k::launch_fill((const h2k::FillTask*)(base + st.desc_off), st.ndesc, s);
+        P.launches += st.ndesc > 0;
+        break;
+      case SK_CVT_F2D:
+        h2k::launch_convert_f32_to_f64(res(st.cvt_in, P), res(st.cvt_out, P), st.cvt_n, s);
+        P.launches += 1;
+        break;
+      case SK_REF:
+        h2k::launch_ref((const h2k::RefTask*)(base + st.desc_off), (const h2k::RefMat*)(base + st.desc2_off),
+                        st.ndesc, s);
+        P.launches += st.ndesc > 0;
+        break;
+    }
+    H2_HIP(hipGetLastError());
+    if (per_step) H2_HIP(hipEventRecord(sev[2 * si + 1], s));
+    const int kind = (int)st.kind;
+    P.bytes_kind[kind] += st.bytes;
+    P.flops_kind[kind] += st.flops;
+    bool launched = (st.kind == SK_GEMM_D || st.kind == SK_GEMM_F) ? st.ntiles > 0
+                    : (st.kind == SK_CVT_F2D ? st.cvt_n > 0 : st.ndesc > 0);
+    P.launches_kind[kind] += launched;
+    ++si;
+  }
+  mark(99);
+  if (per_step) {
+    H2_HIP(hipEventSynchronize(sev.back()));
+    for (size_t i = 0; i < P.steps.size(); ++i) {
+      float ms = 0;
+      H2_HIP(hipEventElapsedTime(&ms, sev[2 * i], sev[2 * i + 1]));
+      P.t_kind[(int)P.steps[i].kind] += ms;
+    }
+    for (auto& e : sev) (void)hipEventDestroy(e);
+  }
+  if (timing) {
+    H2_HIP(hipEventSynchronize(ev[nev - 1]));
+    for (int i = 0; i < 8; ++i) t_phase[i] = 0.0;
+    for (int i = 0; i + 1 < nev; ++i) {
+      float ms = 0;
+      H2_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      int ph = phase_mark[i];
+      if (ph >= 0 && ph < 7) t_phase[ph] += ms;
+    }
+    float tot = 0;
+    H2_HIP(hipEventElapsedTime(&tot, ev[0], ev[nev - 1]));
+    t_phase[7] = tot;
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+}
+
+// ------------------------------------------------------------------ multiply
+static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
+                                       const h2_mul_options& opt, double eps) {
+  auto P = std::make_shared<Plan>();
+  P->f32 = f32;
+  P->kc = kc;
+  P->kappa_cap = kcap;
+  int sigma_br = 2;
+  for (auto& ch : X->rows->children) sigma_br = std::max<int>(sigma_br, (int)ch.size());
+  for (auto& ch : Y->cols->children) sigma_br = std::max<int>(sigma_br, (int)ch.size());
+  P->sigma_br = sigma_br;
+  P->theta = opt.theta > 0 ? opt.theta : 1.0 / (2.0 * sigma_br);
+  if (!(P->theta * sigma_br < 1.0)) throw Error(H2_ERR_INVALID_ARG, "theta must be below 1/sigma");
+  P->budget[0] = opt.budget_coarse > 0 ? opt.budget_coarse : 0.25;
+  P->budget[1] = opt.budget_row > 0 ? opt.budget_row : 0.25;
+  P->budget[2] = opt.budget_col > 0 ? opt.budget_col : 0.25;
+  build_block_tree(P->cbt, *X->rows, *Y->cols, X->bt.eta);
+  Planner pl(ctx, X, Y, *P, kc, kcap);
+  Builder& B = pl.B;
+  pl.build_union();
+  // result arrays
+  P->res_vleaf = B.wd(X->rows->n * kc);
+  P->res_vtr = B.wd((int64_t)X->rows->ncl * kc * kc);
+  P->res_wleaf = B.wd(Y->cols->n * kc);
+  P->res_wtr = B.wd((int64_t)Y->cols->ncl * kc * kc);
+  P->res_S = B.wd((int64_t)P->cbt.adm.size() * kc * kc);
+  P->res_rank_row = B.wi(X->rows->ncl);
+  P->res_rank_col = B.wi(Y->cols->ncl);
+  if (f32) pl.phaseA<float>();
+  else pl.phaseA<double>();
+  pl.coarsen();
+  pl.basis(true);
+  pl.basis(false);
+  pl.couplings();
+  P->n_adm = P->cbt.adm.size();
+  P->n_inadm = P->cbt.inadm.size();
+  double fl = 0;
+  for (auto& st : P->steps) {
+    if (st.kind == SK_QR)
+      for (auto& q : st.qr) {
+        st.flops += 2.0 * q.m * q.w * q.w;
+        st.bytes += 8.0 * ((double)q.m * q.w + (double)q.w * q.w);
+      }
+    if (st.kind == SK_SVD)
+      for (auto& v : st.svd) {
+        st.flops += 8.0 * 4.0 * v.rows * (double)v.cols * v.cols;  // about 8 sweeps of w^2/2 rotations
+        st.bytes += 8.0 * ((double)v.rows * v.cols + (double)v.rows * v.kcap + v.cols);
+      }
+    if (st.kind == SK_CHOL)
+      for (auto& c : st.chol) {
+        st.flops += 2.0 * c.w * c.w * c.w;
+        st.bytes += 8.0 * 3.0 * c.w * c.w;
+      }
+    if (st.kind == SK_FILL)
+      for (auto& f : st.fill) st.bytes += 8.0 * f.m * f.n;
+    if (st.kind == SK_CVT_F2D) st.bytes += 12.0 * st.cvt_n;
+    fl += st.flops;
+  }
+  P->flops_alg = fl;
+  // algorithmic bytes: operand storage read once, result written once, and every
+  // intermediate array written once and read once
+  const double w8 = 8.0;
+  double opbytes = 0;
+  for (Matrix* M : {X, Y}) {
+    opbytes += (double)(M->rows->n + M->cols->n) * M->kc * (f32 ? 4 : 8);
+    opbytes += (double)(M->rows->ncl + M->cols->ncl) * M->kc * M->kc * (f32 ? 4 : 8);
+    opbytes += (double)M->bt.adm.size() * M->kc * M->kc * (f32 ? 4 : 8) + (double)M->nsize * (f32 ? 4 : 8);
+  }
+  P->bytes_alg = opbytes + 2.0 * ((double)P->wsd * w8 + (double)P->wsf * 4.0);
+  finalize(*P, eps);
+  return P;
+}
+
+std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
+                                 h2_mul_stats* stats) {
+  if (X->cols.get() != Y->rows.get()) throw Error(H2_ERR_INCOMPATIBLE, "X's column tree is not Y's row tree");
+  if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
+  if (X->kc > 64 || Y->kc > 64) throw Error(H2_ERR_TOO_LARGE, "operand rank above 64");
+  // FP32 bulk only where its rounding (about 1e-7 of a block's norm) stays well
+  // below the truncation tolerances; tighter eps runs the bulk in FP64.
+  bool f32 = opt.precision == H2_PREC_FP32_BULK && eps >= 1e-5;
+  const int kmax = std::max(X->kc, Y->kc);
+  int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
+  int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
+  if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
+  auto t0 = std::chrono::steady_clock::now();
+  auto key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0) + 0);
+  std::shared_ptr<Plan> P;
+  auto it = ctx->plans.find(key);
+  bool built = false;
+  if (it != ctx->plans.end() && it->second->kc == kc && it->second->kappa_cap == kcap &&
+      it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta)) {
+    P = it->second;
+  } else {
+    if (f32) {
+      X->ensure_fp32(ctx->stream);
+      Y->ensure_fp32(ctx->stream);
+    }
+    P = make_plan(ctx, X, Y, f32, kc, kcap, opt, eps);
+    ctx->plans[key] = P;
+    built = true;
+  }
+  set_eps(*P, eps);
+  double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
+  double tph[8] = {0};
+  execute(ctx, *P, opt.timing != 0, opt.timing >= 2, tph);
+  int ovf = 0;
+  H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  H2_HIP(hipStreamSynchronize(ctx->stream));
+  if (ovf) {
+    if ((ovf & 2) && opt.max_rank == 0 && kc < 64) {
+      // the default cap was too small for this product: retry once with the largest cap
+      h2_mul_options o2 = opt;
+      o2.max_rank = 64;
+      return multiply(ctx, X, Y, eps, o2, stats);
+    }
+    throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "coarsened rank above coarse_rank cap"
+                                             : "basis rank above max_rank cap");
+  }
+  // result matrix owning copies of the result arrays
+  auto Cm = std::make_unique<Matrix>();
+  Cm->ctx = ctx;
+  Cm->hold = ctx->self.lock();
+  Cm->id = ctx->next_id++;
+  Cm->rows = X->rows;
+  Cm->cols = Y->cols;
+  build_block_tree(Cm->bt, *X->rows, *Y->cols, X->bt.eta);
+  Cm->kc = kc;
+  Cm->w_is_v = false;
+  auto cp = [&](const DRef<double>& src, int64_t count) {
+    double* d = Cm->alloc64(std::max<int64_t>(count, 1));
+    if (count) H2_HIP(hipMemcpyAsync(d, res(src, *P), count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+    return d;
+  };
+  Cm->V.leaf = cp(P->res_vleaf, X->rows->n * kc);
+  Cm->V.transfer = cp(P->res_vtr, (int64_t)X->rows->ncl * kc * kc);
+  Cm->W.leaf = cp(P->res_wleaf, Y->cols->n * kc);
+  Cm->W.transfer = cp(P->res_wtr, (int64_t)Y->cols->ncl * kc * kc);
+  Cm->S = cp(P->res_S, (int64_t)P->cbt.adm.size() * kc * kc);
+  Cm->N = cp(P->res_N, P->cnsize);
+  Cm->noff = P->cnoff;
+  Cm->nsize = P->cnsize;
+  Cm->rank_row.resize(X->rows->ncl);
+  Cm->rank_col.resize(Y->cols->ncl);
+  H2_HIP(hipMemcpyAsync(Cm->rank_row.data(), res(P->res_rank_row, *P), X->rows->ncl * sizeof(int),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  H2_HIP(hipMemcpyAsync(Cm->rank_col.data(), res(P->res_rank_col, *P), Y->cols->ncl * sizeof(int),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  H2_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int i = 0; i < 8; ++i) stats->t_phase[i] = tph[i];
+    stats->t_plan_ms = built ? tplan : 0.0;
+    stats->bytes_alg = P->bytes_alg;
+    stats->flops_alg = P->flops_alg;
+    stats->prec_used = f32 ? H2_PREC_FP32_BULK : H2_PREC_FP64;
+    stats->rank_max_row = Cm->rank_row.empty() ? 0 : *std::max_element(Cm->rank_row.begin(), Cm->rank_row.end());
+    stats->rank_max_col = Cm->rank_col.empty() ? 0 : *std::max_element(Cm->rank_col.begin(), Cm->rank_col.end());
+    stats->coarse_rank_max = P->max_coarse_K;
+    stats->n_adm = P->n_adm;
+    stats->n_inadm = P->n_inadm;
+    stats->launches = P->launches;
+    for (int i = 0; i < 8; ++i) {
+      stats->t_kind[i] = P->t_kind[i];
+      stats->launches_kind[i] = P->launches_kind[i];
+      stats->bytes_kind[i] = P->bytes_kind[i];
+      stats->flops_kind[i] = P->flops_kind[i];
+    }
+  }
+  return Cm;
+}
+
+}  // namespace h2

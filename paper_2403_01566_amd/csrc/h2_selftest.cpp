@@ -1,0 +1,245 @@
+// Kernel self-test behind h2_selftest(): runs each gfx950 kernel on seeded
+// random data and reports its error against a plain host evaluation of the
+// same definition (matrix product, R^T R = A^T A, singular values and
+// A A^T U = U S^2, Cholesky identities).  Diagnostic only; the product path
+// never calls it.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "h2_core.h"
+
+namespace {
+
+struct Lcg {
+  uint64_t s;
+  explicit Lcg(uint64_t seed) : s(seed * 6364136223846793005ULL + 1442695040888963407ULL) {}
+  double next() {
+    s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+    return ((s >> 11) * (1.0 / 9007199254740992.0)) * 2.0 - 1.0;
+  }
+};
+
+template <typename T>
+T* up(const std::vector<T>& h, std::vector<void*>& keep) {
+  void* p = nullptr;
+  H2_HIP(hipMalloc(&p, std::max<size_t>(h.size(), 1) * sizeof(T)));
+  H2_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  keep.push_back(p);
+  return (T*)p;
+}
+template <typename T>
+std::vector<T> down(const T* d, size_t n) {
+  std::vector<T> h(n);
+  H2_HIP(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost));
+  return h;
+}
+
+template <typename T>
+double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
+  std::vector<void*> keep;
+  Lcg g(17 + flags + m);
+  const bool ta = flags & h2k::IT_TRANS_A, tb = flags & h2k::IT_TRANS_B;
+  std::vector<std::vector<T>> A(nitem), B(nitem);
+  std::vector<h2k::GemmItem<T>> items(nitem);
+  for (int i = 0; i < nitem; ++i) {
+    A[i].resize((size_t)m * k);
+    B[i].resize((size_t)k * n);
+    for (auto& x : A[i]) x = (T)g.next();
+    for (auto& x : B[i]) x = (T)g.next();
+    items[i].a = up(A[i], keep);
+    items[i].b = up(B[i], keep);
+    items[i].scale = nullptr;
+    items[i].lda = ta ? m : k;
+    items[i].ldb = tb ? k : n;
+    items[i].k = k;
+    items[i].flags = flags;
+    items[i].alpha = 1.0 + 0.5 * i;
+  }
+  std::vector<T> c0((size_t)m * n);
+  for (auto& x : c0) x = (T)g.next();
+  T* dc = up(c0, keep);
+  h2k::GemmTask<T> task{dc, n, m, n, 0, nitem, 1, 0};
+  std::vector<h2k::GemmTile> tiles;
+  for (int i = 0; i < m; i += 64)
+    for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
+  auto* di = up(items, keep);
+  auto* dt = up(std::vector<h2k::GemmTask<T>>{task}, keep);
+  auto* dl = up(tiles, keep);
+  if (std::is_same<T, double>::value)
+    h2k::launch_gemm_f64((const h2k::GemmItem<double>*)di, (const h2k::GemmTask<double>*)dt, dl, (int)tiles.size(), s);
+  else
+    h2k::launch_gemm_f32((const h2k::GemmItem<float>*)di, (const h2k::GemmTask<float>*)dt, dl, (int)tiles.size(), s);
+  H2_HIP(hipStreamSynchronize(s));
+  auto c = down(dc, c0.size());
+  double err = 0, ref = 0;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      double v = c0[(size_t)i * n + j];
+      for (int it = 0; it < nitem; ++it)
+        for (int q = 0; q < k; ++q) {
+          double a = ta ? A[it][(size_t)q * m + i] : A[it][(size_t)i * k + q];
+          double b = tb ? B[it][(size_t)j * k + q] : B[it][(size_t)q * n + j];
+          v += (1.0 + 0.5 * it) * a * b;
+        }
+      err = std::max(err, std::fabs(v - (double)c[(size_t)i * n + j]));
+      ref = std::max(ref, std::fabs(v));
+    }
+  for (void* p : keep) (void)hipFree(p);
+  return err / std::max(ref, 1e-300);
+}
+
+double qr_test(hipStream_t s, int m, int w) {
+  std::vector<void*> keep;
+  Lcg g(99 + m + w);
+  std::vector<double> A((size_t)m * w);
+  for (auto& x : A) x = g.next();
+  // make it rank-deficient in the last columns
+  for (int i = 0; i < m; ++i) A[(size_t)i * w + w - 1] = A[(size_t)i * w];
+  double* da = up(A, keep);
+  std::vector<double> R0((size_t)w * w, 0.0);
+  double* dr = up(R0, keep);
+  h2k::QrTask t{da, dr, w, w, m, w, 0, 0};
+  auto* dt = up(std::vector<h2k::QrTask>{t}, keep);
+  h2k::launch_qr(dt, 1, w, s);
+  H2_HIP(hipStreamSynchronize(s));
+  auto R = down(dr, R0.size());
+  double err = 0, ref = 0;
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j) {
+      double g1 = 0, g2 = 0;
+      for (int r = 0; r < m; ++r) g1 += A[(size_t)r * w + i] * A[(size_t)r * w + j];
+      for (int r = 0; r < w; ++r) g2 += R[(size_t)r * w + i] * R[(size_t)r * w + j];
+      err = std::max(err, std::fabs(g1 - g2));
+      ref = std::max(ref, std::fabs(g1));
+      if (i > j && R[(size_t)i * w + j] != 0.0) err = 1.0;  // not upper triangular
+    }
+  for (void* p : keep) (void)hipFree(p);
+  return err / ref;
+}
+
+double svd_test(hipStream_t s, int w, int* overflow) {
+  std::vector<void*> keep;
+  Lcg g(7 + w);
+  // A = U diag(sig) V^T with decaying singular values, formed densely
+  std::vector<double> A((size_t)w * w, 0.0);
+  std::vector<double> sig(w);
+  for (int i = 0; i < w; ++i) sig[i] = std::pow(10.0, -10.0 * i / std::max(1, w - 1));
+  std::vector<double> X((size_t)w * w), Y((size_t)w * w);
+  for (auto& x : X) x = g.next();
+  for (auto& x : Y) x = g.next();
+  auto gs = [&](std::vector<double>& Q) {  // Gram-Schmidt on columns, twice
+    for (int pass = 0; pass < 2; ++pass)
+      for (int c = 0; c < w; ++c) {
+        for (int d = 0; d < c; ++d) {
+          double dot = 0;
+          for (int r = 0; r < w; ++r) dot += Q[(size_t)r * w + c] * Q[(size_t)r * w + d];
+          for (int r = 0; r < w; ++r) Q[(size_t)r * w + c] -= dot * Q[(size_t)r * w + d];
+        }
+        double nn = 0;
+        for (int r = 0; r < w; ++r) nn += Q[(size_t)r * w + c] * Q[(size_t)r * w + c];
+        nn = std::sqrt(nn);
+        for (int r = 0; r < w; ++r) Q[(size_t)r * w + c] /= nn;
+      }
+  };
+  gs(X);
+  gs(Y);
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j)
+      for (int q = 0; q < w; ++q) A[(size_t)i * w + j] += X[(size_t)i * w + q] * sig[q] * Y[(size_t)j * w + q];
+  double* da = up(A, keep);
+  std::vector<double> U0((size_t)w * w, 0.0), S0(w, 0.0);
+  double* du = up(U0, keep);
+  double* ds = up(S0, keep);
+  std::vector<int> rk0(1, 0);
+  int* dk = up(rk0, keep);
+  h2k::SvdTask t{da, du, ds, dk, nullptr, 0.0, 1e-6, 0.0, w, w, w, w, w, 0, 0, 1};
+  auto* dt = up(std::vector<h2k::SvdTask>{t}, keep);
+  h2k::launch_svd(dt, 1, w, overflow, s);
+  H2_HIP(hipStreamSynchronize(s));
+  auto U = down(du, U0.size());
+  auto S = down(ds, S0.size());
+  auto rk = down(dk, 1);
+  double err = 0;
+  for (int i = 0; i < w; ++i) err = std::max(err, std::fabs(S[i] - sig[i]) / sig[0]);
+  int expect = 0;
+  for (int i = 0; i < w; ++i) expect += sig[i] > 1e-6 * sig[0];
+  if (rk[0] != expect) err = 1.0;
+  // kept columns orthonormal and spanning the leading left singular space
+  for (int a = 0; a < rk[0]; ++a)
+    for (int b = 0; b < rk[0]; ++b) {
+      double d = 0;
+      for (int r = 0; r < w; ++r) d += U[(size_t)r * w + a] * U[(size_t)r * w + b];
+      err = std::max(err, std::fabs(d - (a == b)));
+    }
+  for (int a = 0; a < rk[0]; ++a) {
+    double d = 0;
+    for (int r = 0; r < w; ++r) d += U[(size_t)r * w + a] * X[(size_t)r * w + a];
+    err = std::max(err, std::fabs(std::fabs(d) - 1.0));
+  }
+  for (void* p : keep) (void)hipFree(p);
+  return err;
+}
+
+double chol_test(hipStream_t s, int w, int m) {
+  std::vector<void*> keep;
+  Lcg g(3 + w);
+  std::vector<double> Yh((size_t)m * w);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < w; ++j) Yh[(size_t)i * w + j] = g.next() * std::pow(10.0, -j * 0.5);
+  std::vector<double> G((size_t)w * w, 0.0);
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j)
+      for (int r = 0; r < m; ++r) G[(size_t)i * w + j] += Yh[(size_t)r * w + i] * Yh[(size_t)r * w + j];
+  double* dg = up(G, keep);
+  std::vector<double> z((size_t)w * w, 0.0);
+  double* dtt = up(z, keep);
+  double* drr = up(z, keep);
+  h2k::CholTask t{dg, dtt, drr, nullptr, w, w, w, w};
+  auto* dt = up(std::vector<h2k::CholTask>{t}, keep);
+  h2k::launch_chol(dt, 1, w, s);
+  H2_HIP(hipStreamSynchronize(s));
+  auto T = down(dtt, z.size());
+  auto R = down(drr, z.size());
+  // Q = Y T orthonormal, and Q R = Y
+  std::vector<double> Q((size_t)m * w, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < w; ++j)
+      for (int q = 0; q < w; ++q) Q[(size_t)i * w + j] += Yh[(size_t)i * w + q] * T[(size_t)q * w + j];
+  double err = 0;
+  for (int a = 0; a < w; ++a)
+    for (int b = 0; b < w; ++b) {
+      double d = 0;
+      for (int r = 0; r < m; ++r) d += Q[(size_t)r * w + a] * Q[(size_t)r * w + b];
+      err = std::max(err, std::fabs(d - (a == b)));
+    }
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < w; ++j) {
+      double v = 0;
+      for (int q = 0; q < w; ++q) v += Q[(size_t)i * w + q] * R[(size_t)q * w + j];
+      err = std::max(err, std::fabs(v - Yh[(size_t)i * w + j]));
+    }
+  for (void* p : keep) (void)hipFree(p);
+  return err;
+}
+
+}  // namespace
+
+namespace h2 {
+int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
+  std::vector<double> e;
+  const int flags[4] = {0, h2k::IT_TRANS_A, h2k::IT_TRANS_B, h2k::IT_TRANS_A | h2k::IT_TRANS_B};
+  for (int f : flags) e.push_back(gemm_test<double>(s, f, 77, 45, 70, 3));
+  for (int f : flags) e.push_back(gemm_test<float>(s, f, 130, 64, 33, 2));
+  e.push_back(qr_test(s, 301, 20));
+  e.push_back(qr_test(s, 97, 64));
+  e.push_back(qr_test(s, 150, 128));
+  e.push_back(svd_test(s, 24, overflow));
+  e.push_back(svd_test(s, 64, overflow));
+  e.push_back(svd_test(s, 128, overflow));
+  e.push_back(chol_test(s, 12, 200));
+  e.push_back(chol_test(s, 32, 300));
+  for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
+  return (int)e.size();
+}
+}  // namespace h2

@@ -1,0 +1,238 @@
+"""Thin ctypes binding of the C ABI in ``include/h2.h`` (argument marshalling
+only; every step of the product runs in the HIP library ``libh2mul.so``).
+
+The library must have been built (``python -m paper_2403_01566_amd.build``);
+importing this module without it raises ``ImportError`` -- there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.environ.get("H2_LIBRARY", os.path.join(HERE, "libh2mul.so"))
+
+if not os.path.exists(LIBPATH):
+    raise ImportError(f"HIP library not built: {LIBPATH} (run python -m paper_2403_01566_amd.build)")
+_lib = C.CDLL(LIBPATH)
+
+H2_OK, H2_ERR_INVALID_ARG, H2_ERR_OUT_OF_MEMORY, H2_ERR_DEVICE = 0, 1, 2, 3
+H2_ERR_INCOMPATIBLE, H2_ERR_TOO_LARGE, H2_ERR_NOT_CONVERGED = 4, 5, 6
+KERNEL_NEG_LOG, KERNEL_LAPLACE_SLP, KERNEL_LAPLACE_DLP = 0, 1, 2
+DIAG_ZERO, DIAG_ROW_NEARFIELD_MEAN = 0, 1
+PREC_FP64, PREC_FP32_BULK = 0, 1
+
+EXPORTS = [
+    "h2_context_create", "h2_context_destroy", "h2_last_error", "h2_build_cluster_tree",
+    "h2_tree_permutation", "h2_tree_info", "h2_tree_clusters", "h2_tree_destroy",
+    "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
+    "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
+    "h2_selftest",
+]
+
+
+class MulOptions(C.Structure):
+    _fields_ = [("precision", C.c_int), ("theta", C.c_double), ("budget_coarse", C.c_double),
+                ("budget_row", C.c_double), ("budget_col", C.c_double), ("max_rank", C.c_int),
+                ("coarse_rank", C.c_int), ("timing", C.c_int)]
+
+
+class MulStats(C.Structure):
+    _fields_ = [("t_phase", C.c_double * 8), ("t_plan_ms", C.c_double), ("bytes_alg", C.c_double),
+                ("flops_alg", C.c_double), ("prec_used", C.c_int), ("rank_max_row", C.c_int),
+                ("rank_max_col", C.c_int), ("coarse_rank_max", C.c_int), ("n_adm", C.c_int64),
+                ("n_inadm", C.c_int64), ("launches", C.c_int64), ("t_kind", C.c_double * 8),
+                ("launches_kind", C.c_int64 * 8), ("bytes_kind", C.c_double * 8), ("flops_kind", C.c_double * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        for f in ("t_phase", "t_kind", "launches_kind", "bytes_kind", "flops_kind"):
+            d[f] = list(getattr(self, f))
+        return d
+
+
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_lp = C.POINTER(C.c_int64)
+_ip = C.POINTER(C.c_int)
+_sig = {
+    "h2_context_create": (C.c_int, [C.c_int, C.POINTER(_vp)]),
+    "h2_context_destroy": (None, [_vp]),
+    "h2_last_error": (C.c_char_p, []),
+    "h2_build_cluster_tree": (C.c_int, [_vp, _dp, C.c_int64, C.c_int, C.c_int, C.POINTER(_vp)]),
+    "h2_tree_permutation": (C.c_int, [_vp, _lp]),
+    "h2_tree_info": (C.c_int, [_vp, _lp, _ip, _ip, _ip]),
+    "h2_tree_clusters": (C.c_int, [_vp, _lp, _lp, _ip, _ip]),
+    "h2_tree_destroy": (None, [_vp]),
+    "h2_build_interpolated": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, C.c_int, C.c_double, C.c_int,
+                                        C.POINTER(_vp)]),
+    "h2_mul_default_options": (None, [C.POINTER(MulOptions)]),
+    "h2_mul": (C.c_int, [_vp, _vp, _vp, C.c_double, C.POINTER(MulOptions), C.POINTER(_vp),
+                         C.POINTER(MulStats)]),
+    "h2_to_dense": (C.c_int, [_vp, _dp, C.c_int64]),
+    "h2_block_dense": (C.c_int, [_vp, C.c_int64, _dp]),
+    "h2_matrix_info": (C.c_int, [_vp, _lp, _lp, _ip, _ip, _ip]),
+    "h2_matrix_blocks": (C.c_int, [_vp, _ip]),
+    "h2_matrix_ranks": (C.c_int, [_vp, _ip, _ip]),
+    "h2_matrix_storage": (C.c_int, [_vp, _lp]),
+    "h2_matrix_destroy": (None, [_vp]),
+    "h2_selftest": (C.c_int, [_vp, _dp, C.c_int, _ip]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class H2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"h2 status {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != H2_OK:
+        raise H2Error(code, _lib.h2_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = _vp()
+        _check(_lib.h2_context_create(device, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.h2_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Tree:
+    def __init__(self, ctx: Context, points, leaf_size: int):
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        h = _vp()
+        _check(_lib.h2_build_cluster_tree(ctx.h, _dptr(pts), pts.shape[0], pts.shape[1], leaf_size, C.byref(h)))
+        self.h, self.ctx = h, ctx
+        n, ncl, depth, nl = C.c_int64(), C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.h2_tree_info(h, C.byref(n), C.byref(ncl), C.byref(depth), C.byref(nl)))
+        self.n, self.ncl, self.depth, self.nleaves = n.value, ncl.value, depth.value, nl.value
+
+    def permutation(self):
+        p = np.empty(self.n, dtype=np.int64)
+        _check(_lib.h2_tree_permutation(self.h, p.ctypes.data_as(_lp)))
+        return p
+
+    def clusters(self):
+        b = np.empty(self.ncl, dtype=np.int64)
+        e = np.empty(self.ncl, dtype=np.int64)
+        par = np.empty(self.ncl, dtype=np.int32)
+        lev = np.empty(self.ncl, dtype=np.int32)
+        _check(_lib.h2_tree_clusters(self.h, b.ctypes.data_as(_lp), e.ctypes.data_as(_lp),
+                                     par.ctypes.data_as(_ip), lev.ctypes.data_as(_ip)))
+        return b, e, par, lev
+
+    def __del__(self):
+        try:
+            if self.h:
+                _lib.h2_tree_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Matrix:
+    def __init__(self, h, keep):
+        self.h = h
+        self._keep = keep  # trees/context kept alive
+
+    @classmethod
+    def interpolated(cls, ctx, rows: Tree, cols: Tree, kernel: int, order: int, eta: float,
+                     diag: int = DIAG_ZERO, normals=None):
+        nrm = None if normals is None else np.ascontiguousarray(normals, dtype=np.float64)
+        h = _vp()
+        _check(_lib.h2_build_interpolated(ctx.h, rows.h, cols.h, kernel, None if nrm is None else _dptr(nrm),
+                                          order, eta, diag, C.byref(h)))
+        return cls(h, (ctx, rows, cols))
+
+    def info(self):
+        a, i, kc, rr, rc = C.c_int64(), C.c_int64(), C.c_int(), C.c_int(), C.c_int()
+        _check(_lib.h2_matrix_info(self.h, C.byref(a), C.byref(i), C.byref(kc), C.byref(rr), C.byref(rc)))
+        return {"n_adm": a.value, "n_inadm": i.value, "kcap": kc.value, "rank_max_row": rr.value,
+                "rank_max_col": rc.value}
+
+    def blocks(self):
+        inf = self.info()
+        nb = inf["n_adm"] + inf["n_inadm"]
+        p = np.empty(2 * nb, dtype=np.int32)
+        _check(_lib.h2_matrix_blocks(self.h, p.ctypes.data_as(_ip)))
+        return p.reshape(nb, 2), inf["n_adm"]
+
+    def ranks(self, nrow_clusters, ncol_clusters):
+        a = np.empty(nrow_clusters, dtype=np.int32)
+        b = np.empty(ncol_clusters, dtype=np.int32)
+        _check(_lib.h2_matrix_ranks(self.h, a.ctypes.data_as(_ip), b.ctypes.data_as(_ip)))
+        return a, b
+
+    def storage_bytes(self):
+        b = C.c_int64()
+        _check(_lib.h2_matrix_storage(self.h, C.byref(b)))
+        return b.value
+
+    def to_dense(self, nrows, ncols):
+        out = np.zeros((nrows, ncols), dtype=np.float64)
+        _check(_lib.h2_to_dense(self.h, _dptr(out), ncols))
+        return out
+
+    def block_dense(self, b, m, n):
+        out = np.zeros((m, n), dtype=np.float64)
+        _check(_lib.h2_block_dense(self.h, int(b), _dptr(out)))
+        return out
+
+    def close(self):
+        if self.h:
+            _lib.h2_matrix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def selftest(ctx: Context):
+    """Errors of every device kernel against host evaluations of their definitions."""
+    err = np.zeros(64)
+    n = C.c_int()
+    _check(_lib.h2_selftest(ctx.h, _dptr(err), 64, C.byref(n)))
+    return err[: n.value]
+
+
+def default_options(**kw) -> MulOptions:
+    o = MulOptions()
+    _lib.h2_mul_default_options(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def mul(ctx: Context, X: Matrix, Y: Matrix, eps: float, options: MulOptions | None = None):
+    """C = X Y with the block-relative bound eps.  Returns (C, stats dict)."""
+    st = MulStats()
+    h = _vp()
+    opt = options if options is not None else default_options()
+    _check(_lib.h2_mul(ctx.h, X.h, Y.h, float(eps), C.byref(opt), C.byref(h), C.byref(st)))
+    return Matrix(h, (ctx,) + X._keep[1:2] + Y._keep[2:3]), st.as_dict()

@@ -1,0 +1,43 @@
+"""The C-ABI library loads and exports every entry point that include/h2.h
+declares (no compute calls: this runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "h2.h")
+LIB = os.path.join(ROOT, "paper_2403_01566_amd", "libh2mul.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(h2_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_four_calls():
+    names = declared()
+    for n in ("h2_build_cluster_tree", "h2_build_interpolated", "h2_mul", "h2_to_dense"):
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_lists_all_exports():
+    from paper_2403_01566_amd import h2
+    assert set(declared()) == set(h2.EXPORTS)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_options_defaults_without_gpu():
+    from paper_2403_01566_amd import h2
+    o = h2.default_options()
+    assert o.precision == h2.PREC_FP64 and o.max_rank == 0 and o.theta == 0.0

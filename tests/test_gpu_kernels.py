@@ -1,0 +1,20 @@
+"""Each device kernel against host evaluations of its definition (through the
+h2_selftest diagnostic entry point)."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ["gemm_f64_nn", "gemm_f64_tn", "gemm_f64_nt", "gemm_f64_tt",
+         "gemm_f32_nn", "gemm_f32_tn", "gemm_f32_nt", "gemm_f32_tt",
+         "qr_w20", "qr_w64", "qr_w128", "svd_w24", "svd_w64", "svd_w128", "chol_w12", "chol_w32"]
+TOL = [1e-14] * 4 + [3e-6] * 4 + [1e-13] * 3 + [1e-9] * 3 + [1e-12] * 2
+
+
+def test_kernel_selftest():
+    from paper_2403_01566_amd import h2
+    ctx = h2.Context(0)
+    err = h2.selftest(ctx)
+    print(dict(zip(NAMES, err)), flush=True)
+    assert len(err) == len(NAMES)
+    bad = {n: e for n, e, t in zip(NAMES, err, TOL) if not (e <= t)}
+    assert not bad, bad
