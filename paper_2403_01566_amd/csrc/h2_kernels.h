@@ -27,10 +27,16 @@ struct GemmItem {
 };
 
 // One output matrix C (m x n, row-major, ldc): C = (beta ? C : 0) + sum of items.
+// Optional device ints: m_dev / n_dev lower m / n to min(m, *m_dev) etc. and
+// coff_dev shifts the output by *coff_dev columns (sizes known only on the
+// device, e.g. truncation ranks).
 template <typename T>
 struct GemmTask {
   T* c;
-  int ldc, m, n, item0, nitem, beta, pad;
+  const int* m_dev;
+  const int* n_dev;
+  const int* coff_dev;
+  int ldc, m, n, item0, nitem, beta;
 };
 
 struct GemmTile {
@@ -40,9 +46,14 @@ struct GemmTile {
 // Streaming Householder QR, R factor only: A (m x w, row-major, lda) -> R (w x w).
 // R is upper triangular (rows >= min(m,w) are zero); with trans_r the kernel
 // stores R^T instead.
+// Only the first w_eff = (w_dev ? *w_dev : w) + (w_dev2 ? *w_dev2 : 0) columns
+// (at most w) are factored; rows that are zero in those columns are skipped;
+// R is written as w x w with zeros beyond w_eff.
 struct QrTask {
   const double* a;
   double* r;
+  const int* w_dev;
+  const int* w_dev2;
   int lda, ldr, m, w, trans_r, pad;
 };
 
@@ -55,14 +66,26 @@ struct QrTask {
 // frob == 0: keep sigma_i > tau (largest dropped value below tau);
 // frob == 1: keep the fewest values such that the Frobenius norm of the
 // dropped tail is at most tau.  Overflow sets bits `ovf_bit` in *overflow.
+// Square case with w_dev/w_dev2 as in QrTask: rows = cols = w_eff.  With u2,
+// the output rows are split at *split_dev: rows below go to u, the rest to u2
+// (each written as kcap_rows x kcap, zero elsewhere).
 struct SvdTask {
   const double* a;
   double* u;
+  double* u2;
   double* sigma;    // cols entries
   int* rank;        // 1 entry
   const double* tol_ptr;
+  const int* w_dev;
+  const int* w_dev2;
+  const int* split_dev;
   double tol_abs, tol_rel, tol_scale;
-  int lda, ldu, rows, cols, kcap, trans_a, frob, ovf_bit;
+  int lda, ldu, rows, cols, kcap, trans_a, frob, ovf_bit, urows;
+  // qrcp != 0 (square input, absolute threshold only): first a column-pivoted
+  // Householder QR of A^T that stops once the remaining Frobenius norm is at
+  // most tau/8; the Jacobi then runs on the r pivoted rows only, with the
+  // threshold 3 tau / 4.  The projection error of the result stays <= tau.
+  int qrcp;
 };
 
 // Lower bound of a block norm from the R factors of its pieces: for every

@@ -57,7 +57,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
   __shared__ T Bs[GBK][GBN + 4];
   typedef typename Mfma<T>::acc acc_t;
   const GemmTile tl = tiles[blockIdx.x];
-  const GemmTask<T> tk = tasks[tl.task];
+  GemmTask<T> tk = tasks[tl.task];
+  if (tk.m_dev) tk.m = min(tk.m, *tk.m_dev);
+  if (tk.n_dev) tk.n = min(tk.n, *tk.n_dev);
+  if (tk.coff_dev) tk.c += *tk.coff_dev;
+  if (tl.m0 >= tk.m || tl.n0 >= tk.n) return;  // whole tile outside the device-side size
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
@@ -150,65 +154,116 @@ void launch_gemm_f32(const GemmItem<float>* items, const GemmTask<float>* tasks,
 }
 
 // ---------------------------------------------------------------------------
-// Streaming Householder QR (R only).
+// Streaming Householder QR (R only), one wavefront per matrix.
 // ---------------------------------------------------------------------------
-template <int WMAX, int CH>
-__global__ __launch_bounds__(256) void qr_kernel(const QrTask* __restrict__ tasks) {
-  __shared__ double R[WMAX * WMAX];
+__device__ inline int eff_width(int w, const int* a, const int* b) {
+  if (!a && !b) return w;
+  int v = (a ? *a : 0) + (b ? *b : 0);
+  return v < w ? v : w;
+}
+
+// packed upper triangle of a w x w matrix, row by row
+__device__ inline int pk(int j, int l, int w) { return j * w - (j * (j - 1)) / 2 + (l - j); }
+
+template <int WMAX, int CH, int NT>
+__global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks, int wlo) {
+  constexpr int TPC = 2;                // threads per column (they split the chunk rows)
+  constexpr int CPP = NT / TPC;         // columns per pass
+  __shared__ double R[WMAX * (WMAX + 1) / 2];
   __shared__ double C[CH * WMAX];
+  __shared__ int dest[CH];
+  __shared__ int sh_cnt;
   __shared__ double sh_tau, sh_scal;
   const QrTask tk = tasks[blockIdx.x];
-  const int w = tk.w, m = tk.m, tid = threadIdx.x;
-  for (int e = tid; e < w * w; e += blockDim.x) R[e] = 0.0;
-  for (int row0 = 0; row0 < m; row0 += CH) {
-    const int cr = min(CH, m - row0);
-    __syncthreads();
-    for (int e = tid; e < cr * w; e += blockDim.x) {
-      int i = e / w, l = e - i * w;
-      C[i * w + l] = tk.a[(int64_t)(row0 + i) * tk.lda + l];
+  const int we = eff_width(tk.w, tk.w_dev, tk.w_dev2);
+  if (we <= wlo || we > WMAX) return;  // another launch handles this width class
+  const int m = tk.m, tid = threadIdx.x;
+  const int sub = tid % TPC, cgrp = tid / TPC;
+  for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
+  int next = 0;
+  for (;;) {
+    // gather up to CH rows that are not zero in the first `we` columns
+    int cr = 0;
+    while (cr < CH && next < m) {
+      const int nb = min(CH - cr, m - next);
+      __syncthreads();
+      for (int e = tid; e < nb * we; e += NT) {
+        int i = e / we, l = e - i * we;
+        C[(cr + i) * we + l] = tk.a[(int64_t)(next + i) * tk.lda + l];
+      }
+      __syncthreads();
+      for (int i = tid; i < nb; i += NT) {
+        int nz = 0;
+        for (int l = 0; l < we; ++l) nz |= C[(cr + i) * we + l] != 0.0;
+        dest[i] = nz;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int pos = cr;
+        for (int i = 0; i < nb; ++i) dest[i] = dest[i] ? pos++ : -1;
+        sh_cnt = pos;
+      }
+      __syncthreads();
+      // move kept rows down; each thread owns fixed columns, rows in increasing order
+      for (int i = 0; i < nb; ++i) {
+        const int d = dest[i];
+        if (d >= 0 && d != cr + i)
+          for (int l = tid; l < we; l += NT) C[d * we + l] = C[(cr + i) * we + l];
+      }
+      cr = sh_cnt;
+      next += nb;
     }
+    if (cr == 0) break;
     __syncthreads();
-    for (int j = 0; j < w; ++j) {
+    for (int j = 0; j < we; ++j) {
       if (tid < 64) {
         double x2 = 0.0;
         for (int i = tid; i < cr; i += 64) {
-          double x = C[i * w + j];
+          double x = C[i * we + j];
           x2 += x * x;
         }
         for (int off = 32; off > 0; off >>= 1) x2 += __shfl_xor(x2, off, 64);
         if (tid == 0) {
-          double alpha = R[j * w + j];
+          const double alpha = R[pk(j, j, we)];
           if (x2 == 0.0) {
             sh_tau = 0.0;
             sh_scal = 0.0;
           } else {
-            double nrm = sqrt(alpha * alpha + x2);
-            double beta = alpha >= 0.0 ? -nrm : nrm;
+            const double nrm = sqrt(alpha * alpha + x2);
+            const double beta = alpha >= 0.0 ? -nrm : nrm;
             sh_tau = (beta - alpha) / beta;
             sh_scal = 1.0 / (alpha - beta);
-            R[j * w + j] = beta;
+            R[pk(j, j, we)] = beta;
           }
         }
       }
       __syncthreads();
       const double tau = sh_tau, scal = sh_scal;
       if (tau != 0.0) {
-        for (int l = j + 1 + tid; l < w; l += blockDim.x) {
+        for (int l0 = j + 1; l0 < we; l0 += CPP) {
+          const int l = l0 + cgrp;
           double dot = 0.0;
-          for (int i = 0; i < cr; ++i) dot += C[i * w + j] * C[i * w + l];
-          dot = R[j * w + l] + scal * dot;
-          R[j * w + l] -= tau * dot;
-          const double f = tau * scal * dot;
-          for (int i = 0; i < cr; ++i) C[i * w + l] -= f * C[i * w + j];
+          if (l < we)
+            for (int i = sub; i < cr; i += TPC) dot += C[i * we + j] * C[i * we + l];
+          dot += __shfl_xor(dot, 1, 64);
+          if (l < we) {
+            const int p = pk(j, l, we);
+            const double full = R[p] + scal * dot;
+            const double f = tau * scal * full;
+            for (int i = sub; i < cr; i += TPC) C[i * we + l] -= f * C[i * we + j];
+            if (sub == 0) R[p] -= tau * full;
+          }
         }
       }
       __syncthreads();
     }
+    if (next >= m) break;
   }
   __syncthreads();
-  for (int e = tid; e < w * w; e += blockDim.x) {
+  const int w = tk.w;
+  for (int e = tid; e < w * w; e += NT) {
     int i = e / w, l = e - i * w;
-    double v = (l >= i) ? R[i * w + l] : 0.0;
+    double v = (i < we && l < we && l >= i) ? R[pk(i, l, we)] : 0.0;
     if (tk.trans_r) tk.r[(int64_t)l * tk.ldr + i] = v;
     else tk.r[(int64_t)i * tk.ldr + l] = v;
   }
@@ -216,98 +271,261 @@ __global__ __launch_bounds__(256) void qr_kernel(const QrTask* __restrict__ task
 
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
   if (ntasks <= 0) return;
-  if (wmax <= 32) hipLaunchKernelGGL((qr_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks);
-  else if (wmax <= 64) hipLaunchKernelGGL((qr_kernel<64, 64>), dim3(ntasks), dim3(64), 0, s, tasks);
-  else hipLaunchKernelGGL((qr_kernel<128, 16>), dim3(ntasks), dim3(128), 0, s, tasks);
+  // one launch per width class; each workgroup exits unless its task's
+  // effective width falls into the launch's class
+  hipLaunchKernelGGL((qr_kernel<32, 64, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
+  if (wmax > 32) hipLaunchKernelGGL((qr_kernel<64, 64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
+  if (wmax > 64) hipLaunchKernelGGL((qr_kernel<128, 16, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 64);
 }
 
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD (left vectors).
 // ---------------------------------------------------------------------------
-template <int WMAX>
-__global__ __launch_bounds__(256) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow) {
-  // M[c * WMAX + r] holds column c (contiguous rows)
-  __shared__ double M[WMAX * WMAX];
+// block-wide reductions over NT threads (result in every thread)
+template <int NT>
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  red[tid] = v;
+  __syncthreads();
+  for (int off = NT / 2; off > 0; off >>= 1) {
+    if (tid < off) red[tid] += red[tid + off];
+    __syncthreads();
+  }
+  return red[0];
+}
+
+template <int WMAX, int NT>
+__global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo) {
+  // M[c * LD + r] holds column c (contiguous rows); the odd stride keeps
+  // lanes that read different columns on different LDS banks
+  constexpr int LD = WMAX + 1;
+  constexpr int STAGE = (WMAX * WMAX + NT - 1) / NT;
+  __shared__ double M[WMAX * LD];
   __shared__ double nrm[WMAX];
   __shared__ int order[WMAX];
+  __shared__ int perm[WMAX];
+  __shared__ double red[NT];
+  __shared__ int redi[NT];
   __shared__ int sh_rot;
+  __shared__ double sh_tau, sh_scal;
   const SvdTask tk = tasks[blockIdx.x];
-  const int rows = tk.rows, cols = tk.cols, tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < cols * WMAX; e += nt) {
-    int c = e / WMAX, r = e - c * WMAX;
-    double v = 0.0;
-    if (r < rows) v = tk.trans_a ? tk.a[(int64_t)c * tk.lda + r] : tk.a[(int64_t)r * tk.lda + c];
-    M[e] = v;
+  const bool sq = tk.w_dev || tk.w_dev2;
+  const int we = eff_width(tk.cols, tk.w_dev, tk.w_dev2);
+  const int rows = sq ? we : tk.rows;
+  int cols = sq ? we : tk.cols;
+  const int wcls = rows > cols ? rows : cols;
+  if (wcls <= wlo || wcls > WMAX) return;  // another launch handles this size class
+  const int tid = threadIdx.x;
+  const double ref = tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0;
+  const bool qr = tk.qrcp && tk.tol_rel == 0.0 && rows == cols;
+  double ss = 0.0;
+  if (!qr) {
+    for (int e = tid; e < cols * WMAX; e += NT) {
+      int c = e / WMAX, r = e - c * WMAX;
+      double v = 0.0;
+      if (r < rows) v = tk.trans_a ? tk.a[(int64_t)c * tk.lda + r] : tk.a[(int64_t)r * tk.lda + c];
+      M[c * LD + r] = v;
+      ss += v * v;
+    }
+  } else {
+    // X = A^T in column layout: column l of X is row l of A
+    for (int e = tid; e < rows * WMAX; e += NT) {
+      int l = e / WMAX, i = e - l * WMAX;
+      double v = 0.0;
+      if (i < cols) v = tk.trans_a ? tk.a[(int64_t)i * tk.lda + l] : tk.a[(int64_t)l * tk.lda + i];
+      M[l * LD + i] = v;
+      ss += v * v;
+    }
   }
-  const int np = (cols + 1) & ~1;   // players incl. a dummy when cols is odd
-  const int npairs = np / 2;
-  // threads per pair: groups of G lanes inside one wave
-  const int G = (npairs * 4 <= nt) ? 4 : ((npairs * 2 <= nt) ? 2 : 1);
-  const int grp = tid / G, gl = tid % G;
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) sh_rot = 0;
-    __syncthreads();
-    for (int rnd = 0; rnd < np - 1; ++rnd) {
-      for (int g = grp; g < npairs; g += nt / G) {
-        int p, q;
-        if (g == 0) { p = np - 1; q = rnd; }
-        else { p = (rnd + g) % (np - 1); q = (rnd - g + (np - 1)) % (np - 1); }
-        bool valid = p < cols && q < cols;
-        double a = 0.0, b = 0.0, c = 0.0;
-        double* cp = M + (valid ? p : 0) * WMAX;
-        double* cq = M + (valid ? q : 0) * WMAX;
-        if (valid)
-          for (int r = gl; r < rows; r += G) {
-            double x = cp[r], y = cq[r];
-            a += x * x; b += y * y; c += x * y;
-          }
-        for (int off = 1; off < G; off <<= 1) {
-          a += __shfl_xor(a, off, 64);
-          b += __shfl_xor(b, off, 64);
-          c += __shfl_xor(c, off, 64);
+  const double fro = sqrt(block_sum<NT>(ss, red));
+  // every singular value is below the Frobenius norm: nothing survives an
+  // absolute threshold above it
+  const bool empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
+  double jthr_scale = 1.0;
+  if (!empty && qr) {
+    // column-pivoted Householder QR of X (w x w), stopped when the remaining
+    // columns have Frobenius norm <= tau/8
+    const int w = rows;
+    const double tq = 0.125 * (tk.tol_abs + ref);
+    for (int l = tid; l < w; l += NT) {
+      double v = 0.0;
+      for (int i = 0; i < w; ++i) v += M[l * LD + i] * M[l * LD + i];
+      nrm[l] = v;
+      perm[l] = l;
+    }
+    int r = 0;
+    for (int j = 0; j < w; ++j) {
+      // remaining Frobenius norm and pivot
+      double part = 0.0, best = -1.0;
+      int bi = j;
+      for (int l = j + tid; l < w; l += NT) {
+        part += nrm[l];
+        if (nrm[l] > best) { best = nrm[l]; bi = l; }
+      }
+      __syncthreads();
+      red[tid] = part;
+      redi[tid] = bi;
+      __syncthreads();
+      // reduce sum and argmax (ties: lower index)
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (tid < off) {
+          red[tid] += red[tid + off];
+          const int a = redi[tid], b = redi[tid + off];
+          const double va = (a < w) ? nrm[a] : -1.0, vb = (b < w) ? nrm[b] : -1.0;
+          if (vb > va || (vb == va && b < a)) redi[tid] = b;
         }
-        if (valid && c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
-          double zeta = (b - a) / (2.0 * c);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int r = gl; r < rows; r += G) {
-            double x = cp[r], y = cq[r];
-            cp[r] = cs * x - sn * y;
-            cq[r] = sn * x + cs * y;
-          }
-          if (gl == 0) sh_rot = 1;
+        __syncthreads();
+      }
+      if (red[0] <= tq * tq) break;
+      const int p = redi[0];
+      r = j + 1;
+      if (p != j) {  // swap columns j and p
+        for (int i = tid; i < w; i += NT) {
+          double t = M[j * LD + i];
+          M[j * LD + i] = M[p * LD + i];
+          M[p * LD + i] = t;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          double t = nrm[j]; nrm[j] = nrm[p]; nrm[p] = t;
+          int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
         }
       }
       __syncthreads();
+      // Householder reflector of column j, rows j..w-1
+      double x2p = 0.0;
+      for (int i = j + 1 + tid; i < w; i += NT) x2p += M[j * LD + i] * M[j * LD + i];
+      const double x2 = block_sum<NT>(x2p, red);
+      if (tid == 0) {
+        const double alpha = M[j * LD + j];
+        if (x2 == 0.0) {
+          sh_tau = 0.0;
+          sh_scal = 0.0;
+        } else {
+          const double nn = sqrt(alpha * alpha + x2);
+          const double beta = alpha >= 0.0 ? -nn : nn;
+          sh_tau = (beta - alpha) / beta;
+          sh_scal = 1.0 / (alpha - beta);
+          M[j * LD + j] = beta;
+        }
+      }
+      __syncthreads();
+      const double tau = sh_tau, scal = sh_scal;
+      // apply to the remaining columns (one column per thread) and update norms
+      for (int l = j + 1 + tid; l < w; l += NT) {
+        if (tau != 0.0) {
+          double d = M[l * LD + j];
+          for (int i = j + 1; i < w; ++i) d += scal * M[j * LD + i] * M[l * LD + i];
+          M[l * LD + j] -= tau * d;
+          const double f = tau * d * scal;
+          for (int i = j + 1; i < w; ++i) M[l * LD + i] -= f * M[j * LD + i];
+        }
+        double v = 0.0;
+        for (int i = j + 1; i < w; ++i) v += M[l * LD + i] * M[l * LD + i];
+        nrm[l] = v;
+      }
+      __syncthreads();
     }
-    if (!sh_rot) break;
+    __syncthreads();
+    // T = rows 0..r-1 of the factor, columns back in original order; the
+    // Jacobi matrix is T^T (w x r): column i, row perm[l] = T[i][l]
+    double stage[STAGE];
+#pragma unroll
+    for (int q = 0; q < STAGE; ++q) {
+      const int e = tid + q * NT;
+      stage[q] = 0.0;
+      if (e < r * w) {
+        const int i = e / w, l = e - i * w;
+        stage[q] = (l >= i) ? M[l * LD + i] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < STAGE; ++q) {
+      const int e = tid + q * NT;
+      if (e < r * w) {
+        const int i = e / w, l = e - i * w;
+        M[i * LD + perm[l]] = stage[q];
+      }
+    }
+    cols = r;
+    jthr_scale = 0.75;
     __syncthreads();
   }
-  // singular values and descending order
-  for (int c = tid; c < cols; c += nt) {
-    double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += M[c * WMAX + r] * M[c * WMAX + r];
-    nrm[c] = sqrt(s);
+  if (!empty) {
+    const int np = (cols + 1) & ~1;  // players incl. a dummy when cols is odd
+    const int npairs = np / 2;
+    // G threads (consecutive lanes of one wave) share a pair
+    int G = 64;
+    while (G > 1 && npairs * G > NT) G >>= 1;
+    const int grp = tid / G, gl = tid % G;
+    for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
+      if (tid == 0) sh_rot = 0;
+      __syncthreads();
+      for (int rnd = 0; rnd < np - 1; ++rnd) {
+        for (int g = grp; g < npairs; g += NT / G) {
+          int p, q;
+          if (g == 0) { p = np - 1; q = rnd; }
+          else { p = (rnd + g) % (np - 1); q = (rnd - g + (np - 1)) % (np - 1); }
+          const bool valid = p < cols && q < cols;
+          double a = 0.0, b = 0.0, c = 0.0;
+          double* cp = M + (valid ? p : 0) * LD;
+          double* cq = M + (valid ? q : 0) * LD;
+          if (valid)
+            for (int r = gl; r < rows; r += G) {
+              double x = cp[r], y = cq[r];
+              a += x * x; b += y * y; c += x * y;
+            }
+          for (int off = 1; off < G; off <<= 1) {
+            a += __shfl_xor(a, off, 64);
+            b += __shfl_xor(b, off, 64);
+            c += __shfl_xor(c, off, 64);
+          }
+          if (valid && c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+            double zeta = (b - a) / (2.0 * c);
+            double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+            for (int r = gl; r < rows; r += G) {
+              double x = cp[r], y = cq[r];
+              cp[r] = cs * x - sn * y;
+              cq[r] = sn * x + cs * y;
+            }
+            if (gl == 0) sh_rot = 1;
+          }
+        }
+        __syncthreads();
+      }
+      if (!sh_rot) break;
+      __syncthreads();
+    }
+  }
+  const int c_all = sq ? we : tk.cols;  // number of singular values reported
+  for (int c = tid; c < c_all; c += NT) {
+    double v = 0.0;
+    if (!empty && c < cols)
+      for (int r = 0; r < rows; ++r) v += M[c * LD + r] * M[c * LD + r];
+    nrm[c] = sqrt(v);
   }
   __syncthreads();
-  for (int c = tid; c < cols; c += nt) {
+  for (int c = tid; c < c_all; c += NT) {
     int rk = 0;
     double v = nrm[c];
-    for (int d = 0; d < cols; ++d) rk += (nrm[d] > v) || (nrm[d] == v && d < c);
+    for (int d = 0; d < c_all; ++d) rk += (nrm[d] > v) || (nrm[d] == v && d < c);
     order[rk] = c;
   }
   __syncthreads();
-  const double smax = cols > 0 ? nrm[order[0]] : 0.0;
-  const double thr = tk.tol_abs + tk.tol_rel * smax + (tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0);
+  const double smax = c_all > 0 ? nrm[order[0]] : 0.0;
+  const double thr = jthr_scale * (tk.tol_abs + tk.tol_rel * smax + ref);
   int keep = 0;
   if (!tk.frob) {
-    for (int i = 0; i < cols; ++i) keep += nrm[i] > thr;
+    for (int i = 0; i < c_all; ++i) keep += nrm[i] > thr;
   } else {
     // fewest kept values whose dropped tail has Frobenius norm <= thr
     double tail = 0.0;
-    keep = cols;
+    keep = c_all;
     const double thr2 = thr * thr;
-    for (int i = cols - 1; i >= 0; --i) {
+    for (int i = c_all - 1; i >= 0; --i) {
       double v = nrm[order[i]];
       if (tail + v * v > thr2) break;
       tail += v * v;
@@ -318,24 +536,35 @@ __global__ __launch_bounds__(256) void svd_kernel(const SvdTask* __restrict__ ta
     if (tid == 0 && overflow) atomicOr(overflow, tk.ovf_bit);
     keep = tk.kcap;
   }
-  for (int i = tid; i < cols; i += nt) tk.sigma[i] = nrm[order[i]];
+  const int sc = sq ? tk.cols : c_all;
+  for (int i = tid; i < sc; i += NT) tk.sigma[i] = i < c_all ? nrm[order[i]] : 0.0;
   if (tid == 0) *tk.rank = keep;
-  for (int e = tid; e < rows * tk.kcap; e += nt) {
-    int r = e / tk.kcap, i = e - r * tk.kcap;
-    double v = 0.0;
-    if (i < keep) {
-      int c = order[i];
-      v = M[c * WMAX + r] / nrm[c];
+  auto uval = [&](int r, int i) -> double {
+    if (i >= keep || r >= rows) return 0.0;
+    const int c = order[i];
+    return M[c * LD + r] / nrm[c];
+  };
+  if (!tk.u2) {
+    const int ur = sq ? tk.rows : rows;
+    for (int e = tid; e < ur * tk.kcap; e += NT) {
+      int r = e / tk.kcap, i = e - r * tk.kcap;
+      tk.u[(int64_t)r * tk.ldu + i] = uval(r, i);
     }
-    tk.u[(int64_t)r * tk.ldu + i] = v;
+  } else {
+    const int split = tk.split_dev ? *tk.split_dev : 0;
+    for (int e = tid; e < tk.urows * tk.kcap; e += NT) {
+      int r = e / tk.kcap, i = e - r * tk.kcap;
+      tk.u[(int64_t)r * tk.ldu + i] = r < split ? uval(r, i) : 0.0;
+      tk.u2[(int64_t)r * tk.ldu + i] = (split + r < rows) ? uval(split + r, i) : 0.0;
+    }
   }
 }
 
 void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s) {
   if (ntasks <= 0) return;
-  if (wmax <= 32) hipLaunchKernelGGL((svd_kernel<32>), dim3(ntasks), dim3(64), 0, s, tasks, overflow);
-  else if (wmax <= 64) hipLaunchKernelGGL((svd_kernel<64>), dim3(ntasks), dim3(128), 0, s, tasks, overflow);
-  else hipLaunchKernelGGL((svd_kernel<128>), dim3(ntasks), dim3(256), 0, s, tasks, overflow);
+  hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
+  if (wmax > 32) hipLaunchKernelGGL((svd_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, overflow, 32);
+  if (wmax > 64) hipLaunchKernelGGL((svd_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 64);
 }
 
 // ---------------------------------------------------------------------------
@@ -367,20 +596,21 @@ __global__ __launch_bounds__(64) void chol_kernel(const CholTask* __restrict__ t
     Ri[i][l] = 0.0;
   }
   __syncthreads();
-  // right-looking Cholesky, upper factor stored in the upper triangle of H
-  for (int j = 0; j < w; ++j) {
+  // right-looking Cholesky of the leading we x we block (identity beyond),
+  // upper factor stored in the upper triangle of H
+  for (int j = 0; j < we; ++j) {
     if (tid == 0) H[j][j] = sqrt(fmax(H[j][j], 1e-300));
     __syncthreads();
-    for (int l = j + 1 + tid; l < w; l += 64) H[j][l] /= H[j][j];
+    for (int l = j + 1 + tid; l < we; l += 64) H[j][l] /= H[j][j];
     __syncthreads();
-    for (int e = tid; e < (w - j - 1) * (w - j - 1); e += 64) {
-      int i = j + 1 + e / (w - j - 1), l = j + 1 + e % (w - j - 1);
+    for (int e = tid; e < (we - j - 1) * (we - j - 1); e += 64) {
+      int i = j + 1 + e / (we - j - 1), l = j + 1 + e % (we - j - 1);
       if (l >= i) H[i][l] -= H[j][i] * H[j][l];
     }
     __syncthreads();
   }
   // inverse of the upper factor, one column per thread (back substitution)
-  for (int l = tid; l < w; l += 64) {
+  for (int l = tid; l < we; l += 64) {
     for (int i = l; i >= 0; --i) {
       double s = (i == l) ? 1.0 : 0.0;
       for (int k2 = i + 1; k2 <= l; ++k2) s -= H[i][k2] * Ri[k2][l];

@@ -39,6 +39,9 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <deque>
+#include <cstdio>
+#include <cstdlib>
 
 #include "h2_core.h"
 
@@ -79,14 +82,19 @@ template <typename T>
 struct PTask {
   DRef<T> c;
   int ldc, m, n, item0, nitem, beta;
+  DRef<int> m_dev, n_dev, coff_dev;
 };
 struct PQr {
   DRef<double> a, r;
   int lda, ldr, m, w, trans_r;
+  DRef<int> w_dev, w_dev2;
 };
 struct PSvd {
   DRef<double> a, u, sigma;
   DRef<int> rank;
+  DRef<double> u2;
+  DRef<int> w_dev, w_dev2, split_dev;
+  int urows = 0;
   DRef<double> tolref;  // coarsening: per-block absolute reference (times delta_c)
   int tolkind;          // 0: coarsening (Frobenius tail), 1: row, 2: column (largest dropped value)
   double tolfactor;
@@ -139,7 +147,7 @@ struct Step {
 };
 
 struct Plan {
-  std::vector<Step> steps;
+  std::deque<Step> steps;  // deque: references to earlier steps stay valid
   int64_t wsd = 0, wsf = 0, wsi = 0;
   DevBuf bufd, buff, bufi, desc;
   std::vector<char> hdesc;
@@ -155,6 +163,7 @@ struct Plan {
   bool f32 = false;
   double eps_set = -1;
   double theta = 0.25, sigma_br = 2.0;
+  int qrcp = 1;  // pivoted-QR rank reveal before the Jacobi (square SVDs)
   double budget[3] = {0.25, 0.25, 0.25};
   int64_t launches = 0;
   int max_coarse_K = 0;
@@ -196,6 +205,42 @@ struct Builder {
   }
 };
 
+#ifndef H2_QR_SPLIT_ROWS
+#define H2_QR_SPLIT_ROWS 2048
+#endif
+
+// Streaming QR of a tall matrix (R only).  Matrices with many rows are cut
+// into row blocks factored in parallel (stage 1); their R factors are stacked
+// and factored again (stage 2), which gives the R factor of the whole matrix.
+struct QrSplit {
+  Builder& B;
+  Step* s1;
+  Step* s2 = nullptr;
+  static constexpr int kRows = H2_QR_SPLIT_ROWS;
+  QrSplit(Builder& b, int wmax) : B(b) {
+    s1 = &B.step(SK_QR);
+    s1->wmax = wmax;
+  }
+  void add(DRef<double> a, int lda, int m, int w, DRef<double> r, int ldr, int trans_r,
+           DRef<int> w1 = DRef<int>(), DRef<int> w2 = DRef<int>()) {
+    if (m <= kRows) {
+      s1->qr.push_back({a, r, lda, ldr, m, w, trans_r, w1, w2});
+      return;
+    }
+    if (!s2) {
+      s2 = &B.step(SK_QR);
+      s2->wmax = s1->wmax;
+    }
+    const int parts = (m + kRows - 1) / kRows;
+    DRef<double> stack = B.wd((int64_t)parts * w * w);
+    for (int p = 0; p < parts; ++p) {
+      const int r0 = p * kRows, rows = std::min(kRows, m - r0);
+      s1->qr.push_back({a + (int64_t)r0 * lda, stack + (int64_t)p * w * w, lda, w, rows, w, 0, w1, w2});
+    }
+    s2->qr.push_back({stack, r, w, ldr, parts * w, w, trans_r, w1, w2});
+  }
+};
+
 template <typename T>
 struct WS;
 template <>
@@ -229,6 +274,13 @@ struct GW {
     t.nitem = 0;
     t.beta = beta;
     WS<T>::tasks(*s).push_back(t);
+  }
+  // sizes / column offset of the last task known only on the device
+  void dev(DRef<int> n_dev, DRef<int> coff_dev = DRef<int>(), DRef<int> m_dev = DRef<int>()) {
+    auto& t = WS<T>::tasks(*s).back();
+    t.n_dev = n_dev;
+    t.coff_dev = coff_dev;
+    t.m_dev = m_dev;
   }
   void mm(DRef<T> a, int lda, DRef<T> b, int ldb, int k, int flags = 0, double alpha = 1.0,
           DRef<double> scale = DRef<double>()) {
@@ -955,7 +1007,7 @@ void Planner::coarsen() {
     int t = 0, r = 0, m = 0, n = 0, K = 0, height = 0, below = -1, unode = -1;
     int c0 = -1, c1 = -1;  // merged children (MNode indices), -1 for leaves
     int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
-            Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1;
+            Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
   };
   std::vector<MNode> mn;
   std::vector<int> of_un(un.size(), -1);
@@ -1036,6 +1088,7 @@ void Planner::coarsen() {
         fs.fill.push_back({Dw(x.U), x.K, x.m, x.K, 0, 0.0});
         fs.fill.push_back({Dw(x.Z), x.K, x.n, x.K, 0, 0.0});
       }
+      // children's columns packed: [0, kappa_a) from a, [kappa_a, kappa_a + kappa_b) from b
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
@@ -1043,9 +1096,12 @@ void Planner::coarsen() {
         for (int c = 0; c < 2; ++c) {
           const MNode& ch = mn[kid[c]];
           const int64_t ro = TI.begin[ch.t] - TI.begin[x.t], co = TK.begin[ch.r] - TK.begin[x.r];
-          g.task(Dw(x.U) + ro * x.K + c * kcap, x.K, ch.m, kcap);
-          g.mm(Dw(ch.Uh), kcap, Dw(ch.Sb), kcap, kcap);
-          g.task(Dw(x.Z) + co * x.K + c * kcap, x.K, ch.n, kcap);
+          const DRef<int> off = c == 0 ? DRef<int>() : Iw(mn[x.c0].Kap);
+          g.task(Dw(x.U) + ro * x.K, x.K, ch.m, kcap);
+          g.dev(Iw(ch.Kap), off);
+          g.copy(Dw(ch.Wc), kcap);
+          g.task(Dw(x.Z) + co * x.K, x.K, ch.n, kcap);
+          g.dev(Iw(ch.Kap), off);
           g.copy(Dw(ch.Vh), kcap);
         }
       }
@@ -1087,13 +1143,16 @@ void Planner::coarsen() {
       x.R2 = B.wd((int64_t)kcap * kcap).off;
       x.Vh = B.wd((int64_t)x.n * kcap).off;
       x.Sb = B.wd((int64_t)kcap * kcap).off;
+      x.Wc = B.wd((int64_t)x.m * kcap).off;
     }
+    // effective width of a merge: kappa of the two children (device side)
+    auto wd1 = [&](const MNode& x) { return x.c0 >= 0 ? Iw(mn[x.c0].Kap) : DRef<int>(); };
+    auto wd2 = [&](const MNode& x) { return x.c1 >= 0 ? Iw(mn[x.c1].Kap) : DRef<int>(); };
     {  // R_Z: R factor of Z
-      Step& st = B.step(SK_QR);
-      st.wmax = wmax;
+      QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
-        st.qr.push_back({Dw(x.Z), Dw(x.RZ), x.K, x.K, x.n, x.K, 0});
+        q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
       }
     }
     {  // condensed block G^ = U R_Z^* (same singular values as U Z^*)
@@ -1105,11 +1164,10 @@ void Planner::coarsen() {
       }
     }
     {  // R factor of G^, stored transposed
-      Step& st = B.step(SK_QR);
-      st.wmax = wmax;
+      QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
-        st.qr.push_back({Dw(x.Gh), Dw(x.RGt), x.K, x.K, x.m, x.K, 1});
+        q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
       }
     }
     if (h == 0) {  // lower bounds of the block norms: largest column norm of the leaves' condensed factors
@@ -1139,6 +1197,8 @@ void Planner::coarsen() {
         s.tolref = Dw(tau[x.below]);
         s.tolkind = 0;
         s.tolfactor = 1.0;
+        s.w_dev = wd1(x);
+        s.w_dev2 = wd2(x);
         s.lda = x.K;
         s.ldu = kcap;
         s.rows = x.K;
@@ -1221,6 +1281,14 @@ void Planner::coarsen() {
         g.copy(Dw(x.R2), kcap, h2k::IT_TRANS_A);
       }
     }
+    {  // W = U^ S, the row factor handed to the parent merge
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        g.task(Dw(x.Wc), kcap, x.m, kcap);
+        g.mm(Dw(x.Uh), kcap, Dw(x.Sb), kcap, kcap);
+      }
+    }
   }
   // outputs of each block's root merge, used by the basis construction
   for (size_t li = 0; li < C.adm.size(); ++li) {
@@ -1286,38 +1354,51 @@ void Planner::basis(bool rows) {
             g.task(out, w, kcap, w);
             g.mm(Dw(u.Sb), kcap, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
           } else {
+            // children's coefficients packed: [0, k_c0) and [k_c0, k_c0 + k_c1)
             const int c0 = T.children[s][0], c1 = T.children[s][1];
             g.task(out, w, kcap, kc);
+            g.dev(rankout + c0);
             g.mm(Dw(u.Sb), kcap, Dw(proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
-            g.task(out + kc, w, kcap, kc);
+            g.task(out, w, kcap, kc);
+            g.dev(rankout + c1, rankout + c0);
             g.mm(Dw(u.Sb), kcap, Dw(proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
           }
         }
       }
     }
-    for (int pass = 0; pass < 2; ++pass) {  // QR: one launch per width class
-      Step& st = B.step(SK_QR);
+    {  // R^* of the weighted matrix (the launcher picks the width class per task)
+      int wmax = 0;
+      for (int s : cl) wmax = std::max(wmax, wcol[s]);
+      if (wmax > 128) throw Error(H2_ERR_TOO_LARGE, "leaf size above 128");
+      QrSplit q(B, wmax);
       for (int s : cl) {
         const int w = wcol[s];
-        if (w > 128) throw Error(H2_ERR_TOO_LARGE, "leaf size above 128");
-        if ((w > 64) != (pass == 1)) continue;
-        st.wmax = std::max(st.wmax, w);
         rt[s] = B.wd((int64_t)w * w).off;
-        st.qr.push_back({Dw(gst[s]), Dw(rt[s]), w, w, (int)star[s].size() * kcap, w, 1});
+        DRef<int> w1, w2;
+        if (!T.leaf(s)) {
+          w1 = rankout + T.children[s][0];
+          w2 = rankout + T.children[s][1];
+        }
+        q.add(Dw(gst[s]), w, (int)star[s].size() * kcap, w, Dw(rt[s]), w, 1, w1, w2);
       }
     }
-    for (int pass = 0; pass < 2; ++pass) {  // left singular vectors of the weighted matrix
+    {  // left singular vectors of the weighted matrix
       Step& st = B.step(SK_SVD);
       for (int s : cl) {
         const int w = wcol[s];
-        if ((w > 64) != (pass == 1)) continue;
         st.wmax = std::max(st.wmax, w);
         PSvd v;
         v.a = Dw(rt[s]);
         if (T.leaf(s)) v.u = leafout + T.begin[s] * kc;
         else {
-          vhat[s] = B.wd((int64_t)w * kc).off;
-          v.u = Dw(vhat[s]);
+          // stacked transfers: rows [0, k_c0) give E_c0, the rest E_c1
+          const int c0 = T.children[s][0], c1 = T.children[s][1];
+          v.u = trout + (int64_t)c0 * kk;
+          v.u2 = trout + (int64_t)c1 * kk;
+          v.split_dev = rankout + c0;
+          v.w_dev = rankout + c0;
+          v.w_dev2 = rankout + c1;
+          v.urows = kc;
         }
         v.sigma = Dw(B.wd(w).off);
         v.rank = rankout + s;
@@ -1346,14 +1427,10 @@ void Planner::basis(bool rows) {
           }
         } else {
           const int c0 = T.children[s][0], c1 = T.children[s][1];
-          g.task(trout + (int64_t)c0 * kk, kc, kc, kc);
-          g.copy(Dw(vhat[s]), kc);
-          g.task(trout + (int64_t)c1 * kk, kc, kc, kc);
-          g.copy(Dw(vhat[s]) + (int64_t)kc * kc, kc);
           for (int li : star[s]) {
             g.task(Dw(proj[s][li]), kcap, kc, kcap);
-            g.mm(Dw(vhat[s]), kc, Dw(proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
-            g.mm(Dw(vhat[s]) + (int64_t)kc * kc, kc, Dw(proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
+            g.mm(trout + (int64_t)c0 * kk, kc, Dw(proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
+            g.mm(trout + (int64_t)c1 * kk, kc, Dw(proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
           }
         }
       }
@@ -1423,13 +1500,15 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
   std::vector<GemmTile> tiles;
   for (size_t i = 0; i < tk.size(); ++i) {
     tasks[i].c = res(tk[i].c, P);
+    tasks[i].m_dev = res(tk[i].m_dev, P);
+    tasks[i].n_dev = res(tk[i].n_dev, P);
+    tasks[i].coff_dev = res(tk[i].coff_dev, P);
     tasks[i].ldc = tk[i].ldc;
     tasks[i].m = tk[i].m;
     tasks[i].n = tk[i].n;
     tasks[i].item0 = tk[i].item0;
     tasks[i].nitem = tk[i].nitem;
     tasks[i].beta = tk[i].beta;
-    tasks[i].pad = 0;
     for (int m0 = 0; m0 < tk[i].m; m0 += 64)
       for (int n0 = 0; n0 < tk[i].n; n0 += 64) tiles.push_back({(int)i, m0, n0, 0});
   }
@@ -1449,6 +1528,12 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     const PSvd& s = st.svd[i];
     v[i].a = res(s.a, P);
     v[i].u = res(s.u, P);
+    v[i].u2 = res(s.u2, P);
+    v[i].w_dev = res(s.w_dev, P);
+    v[i].w_dev2 = res(s.w_dev2, P);
+    v[i].split_dev = res(s.split_dev, P);
+    v[i].urows = s.urows;
+    v[i].qrcp = P.qrcp;
     v[i].sigma = res(s.sigma, P);
     v[i].rank = res(s.rank, P);
     v[i].tol_abs = 0.0;
@@ -1497,7 +1582,7 @@ static void finalize(Plan& P, double eps) {
         align(64);
         st.desc_off = blob.size();
         for (auto& q : st.qr) {
-          h2k::QrTask t{res(q.a, P), res(q.r, P), q.lda, q.ldr, q.m, q.w, q.trans_r, 0};
+          h2k::QrTask t{res(q.a, P), res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), q.lda, q.ldr, q.m, q.w, q.trans_r, 0};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.qr.size();
@@ -1654,10 +1739,18 @@ static void execute(Context* ctx, Plan& P, bool timing, bool per_kind, double* t
   mark(99);
   if (per_step) {
     H2_HIP(hipEventSynchronize(sev.back()));
+    static const char* trace = std::getenv("H2_TRACE");
+    static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref"};
     for (size_t i = 0; i < P.steps.size(); ++i) {
       float ms = 0;
       H2_HIP(hipEventElapsedTime(&ms, sev[2 * i], sev[2 * i + 1]));
       P.t_kind[(int)P.steps[i].kind] += ms;
+      if (trace) {
+        const Step& st = P.steps[i];
+        std::fprintf(stderr, "[h2 step %3zu] phase %d %-6s tasks %7d tiles %8d wmax %4d  %9.3f ms  %.3g GF %.3g GB\n",
+                     i, st.phase, kname[(int)st.kind], st.ndesc, st.ntiles, st.wmax, ms, st.flops * 1e-9,
+                     st.bytes * 1e-9);
+      }
     }
     for (auto& e : sev) (void)hipEventDestroy(e);
   }

@@ -59,7 +59,7 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
   std::vector<T> c0((size_t)m * n);
   for (auto& x : c0) x = (T)g.next();
   T* dc = up(c0, keep);
-  h2k::GemmTask<T> task{dc, n, m, n, 0, nitem, 1, 0};
+  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1};
   std::vector<h2k::GemmTile> tiles;
   for (int i = 0; i < m; i += 64)
     for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
@@ -99,7 +99,7 @@ double qr_test(hipStream_t s, int m, int w) {
   double* da = up(A, keep);
   std::vector<double> R0((size_t)w * w, 0.0);
   double* dr = up(R0, keep);
-  h2k::QrTask t{da, dr, w, w, m, w, 0, 0};
+  h2k::QrTask t{da, dr, nullptr, nullptr, w, w, m, w, 0, 0};
   auto* dt = up(std::vector<h2k::QrTask>{t}, keep);
   h2k::launch_qr(dt, 1, w, s);
   H2_HIP(hipStreamSynchronize(s));
@@ -118,7 +118,12 @@ double qr_test(hipStream_t s, int m, int w) {
   return err / ref;
 }
 
-double svd_test(hipStream_t s, int w, int* overflow) {
+// qrcp == 0: relative spectral threshold 1e-6; singular values, rank and the
+// leading singular vectors are checked.  qrcp == 1: pivoted-QR rank reveal
+// with an absolute Frobenius threshold tau; checked are the orthonormality of
+// the kept basis, the projection error ||A - U U^T A||_F <= tau and that the
+// rank is no more than the one of the exact SVD at tau / 2.
+double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0) {
   std::vector<void*> keep;
   Lcg g(7 + w);
   // A = U diag(sig) V^T with decaying singular values, formed densely
@@ -153,7 +158,9 @@ double svd_test(hipStream_t s, int w, int* overflow) {
   double* ds = up(S0, keep);
   std::vector<int> rk0(1, 0);
   int* dk = up(rk0, keep);
-  h2k::SvdTask t{da, du, ds, dk, nullptr, 0.0, 1e-6, 0.0, w, w, w, w, w, 0, 0, 1};
+  const double tau = 1e-5;
+  h2k::SvdTask t{da, du, nullptr, ds, dk, nullptr, nullptr, nullptr, nullptr, qrcp ? tau : 0.0, qrcp ? 0.0 : 1e-6, 0.0,
+                 w, w, w, w, w, 0, qrcp, 1, 0, qrcp};
   auto* dt = up(std::vector<h2k::SvdTask>{t}, keep);
   h2k::launch_svd(dt, 1, w, overflow, s);
   H2_HIP(hipStreamSynchronize(s));
@@ -161,6 +168,38 @@ double svd_test(hipStream_t s, int w, int* overflow) {
   auto S = down(ds, S0.size());
   auto rk = down(dk, 1);
   double err = 0;
+  if (qrcp) {
+    const int k = rk[0];
+    for (int a = 0; a < k; ++a)
+      for (int b = 0; b < k; ++b) {
+        double d = 0;
+        for (int r = 0; r < w; ++r) d += U[(size_t)r * w + a] * U[(size_t)r * w + b];
+        err = std::max(err, std::fabs(d - (a == b)));
+      }
+    // P = U^T A (k x w), residual A - U P
+    double res = 0;
+    for (int j = 0; j < w; ++j) {
+      std::vector<double> pj(k, 0.0);
+      for (int a = 0; a < k; ++a)
+        for (int r = 0; r < w; ++r) pj[a] += U[(size_t)r * w + a] * A[(size_t)r * w + j];
+      for (int r = 0; r < w; ++r) {
+        double v = A[(size_t)r * w + j];
+        for (int a = 0; a < k; ++a) v -= U[(size_t)r * w + a] * pj[a];
+        res += v * v;
+      }
+    }
+    if (std::sqrt(res) > tau) err = 1.0;
+    double tail = 0;
+    int kmax = w;
+    for (int i = w - 1; i >= 0; --i) {
+      if (tail + sig[i] * sig[i] > 0.25 * tau * tau) break;
+      tail += sig[i] * sig[i];
+      kmax = i;
+    }
+    if (k > kmax || k < 1) err = 1.0;
+    for (void* p : keep) (void)hipFree(p);
+    return err;
+  }
   for (int i = 0; i < w; ++i) err = std::max(err, std::fabs(S[i] - sig[i]) / sig[0]);
   int expect = 0;
   for (int i = 0; i < w; ++i) expect += sig[i] > 1e-6 * sig[0];
@@ -237,6 +276,8 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(svd_test(s, 24, overflow));
   e.push_back(svd_test(s, 64, overflow));
   e.push_back(svd_test(s, 128, overflow));
+  e.push_back(svd_test(s, 40, overflow, 1));
+  e.push_back(svd_test(s, 128, overflow, 1));
   e.push_back(chol_test(s, 12, 200));
   e.push_back(chol_test(s, 32, 300));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
