@@ -167,7 +167,8 @@ __device__ inline int pk(int j, int l, int w) { return j * w - (j * (j - 1)) / 2
 
 template <int WMAX, int CH, int NT>
 __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks, int wlo) {
-  constexpr int TPC = 2;                // threads per column (they split the chunk rows)
+  constexpr int TPC = NT / WMAX;        // threads per column (they split the chunk rows)
+  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 64, "threads per column");
   constexpr int CPP = NT / TPC;         // columns per pass
   __shared__ double R[WMAX * (WMAX + 1) / 2];
   __shared__ double C[CH * WMAX];
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
           double dot = 0.0;
           if (l < we)
             for (int i = sub; i < cr; i += TPC) dot += C[i * we + j] * C[i * we + l];
-          dot += __shfl_xor(dot, 1, 64);
+          for (int off = 1; off < TPC; off <<= 1) dot += __shfl_xor(dot, off, 64);
           if (l < we) {
             const int p = pk(j, l, we);
             const double full = R[p] + scal * dot;
@@ -275,7 +276,7 @@ void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
   // effective width falls into the launch's class
   hipLaunchKernelGGL((qr_kernel<32, 64, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
   if (wmax > 32) hipLaunchKernelGGL((qr_kernel<64, 64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
-  if (wmax > 64) hipLaunchKernelGGL((qr_kernel<128, 16, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 64);
+  if (wmax > 64) hipLaunchKernelGGL((qr_kernel<128, 64, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
 }
 
 // ---------------------------------------------------------------------------

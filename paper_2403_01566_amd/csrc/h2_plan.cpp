@@ -39,6 +39,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <tuple>
 #include <deque>
 #include <cstdio>
 #include <cstdlib>
@@ -1006,6 +1007,9 @@ void Planner::coarsen() {
   struct MNode {
     int t = 0, r = 0, m = 0, n = 0, K = 0, height = 0, below = -1, unode = -1;
     int c0 = -1, c1 = -1;  // merged children (MNode indices), -1 for leaves
+    // dense leaf forms: U = I (uI) or Z = I (zI); the identity factor is never
+    // formed and the steps that would multiply by it are skipped
+    bool uI = false, zI = false;
     int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
             Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
   };
@@ -1058,6 +1062,14 @@ void Planner::coarsen() {
   for (size_t li = 0; li < C.adm.size(); ++li) make(bnode[li]);
   int maxh = 0;
   for (auto& x : mn) maxh = std::max(maxh, x.height);
+  if (std::getenv("H2_TRACE")) {  // shape summary of the merge tree
+    std::map<std::tuple<int, int, int, int>, int> hist;  // (height, m bucket, n bucket, K)
+    auto bk = [](int v) { int b = 16; while (b < v) b *= 2; return b; };
+    for (auto& x : mn) hist[std::make_tuple(x.height, bk(x.m), bk(x.n), x.c0 >= 0 ? -1 : x.K)]++;
+    for (auto& kv : hist)
+      std::fprintf(stderr, "[h2 merge] height %d m<=%d n<=%d K %d count %d\n", std::get<0>(kv.first),
+                   std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
+  }
   // Truncation errors of all merges of a block add up exactly; merges of equal
   // height act on disjoint sub-blocks, so with a Frobenius tail <= tau at every
   // merge the total error is at most tau * sum_h sqrt(n_h).  tau_b = delta_c *
@@ -1106,17 +1118,10 @@ void Planner::coarsen() {
         }
       }
     } else {
-      Step& fs = B.step(SK_FILL);
       for (int i : lv) {
         MNode& x = mn[i];
-        if (x.U == -2) {
-          x.U = B.wd((int64_t)x.m * x.K).off;
-          fs.fill.push_back({Dw(x.U), x.K, x.m, x.K, 1, 1.0});
-        }
-        if (x.Z == -2) {
-          x.Z = B.wd((int64_t)x.n * x.K).off;
-          fs.fill.push_back({Dw(x.Z), x.K, x.n, x.K, 1, 1.0});
-        }
+        x.uI = x.U == -2;
+        x.zI = x.Z == -2;
       }
     }
     int wmax = 0;
@@ -1125,9 +1130,9 @@ void Planner::coarsen() {
       wmax = std::max(wmax, x.K);
       P.max_coarse_K = std::max(P.max_coarse_K, x.K);
       if (x.K > 128) throw Error(H2_ERR_TOO_LARGE, "coarsening width above 128");
-      x.RZ = B.wd((int64_t)x.K * x.K).off;
-      x.Gh = B.wd((int64_t)x.m * x.K).off;
-      x.RGt = B.wd((int64_t)x.K * x.K).off;
+      if (!x.zI) x.RZ = B.wd((int64_t)x.K * x.K).off;
+      if (!x.zI && !x.uI) x.Gh = B.wd((int64_t)x.m * x.K).off;
+      if (!x.uI) x.RGt = B.wd((int64_t)x.K * x.K).off;
       x.Vk = B.wd((int64_t)x.K * kcap).off;
       x.Sig = B.wd(x.K).off;
       x.Kap = B.wi(1).off;
@@ -1136,8 +1141,8 @@ void Planner::coarsen() {
       x.T1 = B.wd((int64_t)kcap * kcap).off;
       x.R1 = B.wd((int64_t)kcap * kcap).off;
       x.Uh = B.wd((int64_t)x.m * kcap).off;
-      x.Tm = B.wd((int64_t)x.K * kcap).off;
-      x.Zh = B.wd((int64_t)x.n * kcap).off;
+      if (!x.uI) x.Tm = B.wd((int64_t)x.K * kcap).off;
+      if (!x.zI) x.Zh = B.wd((int64_t)x.n * kcap).off;
       x.Gz = B.wd((int64_t)kcap * kcap).off;
       x.T2 = B.wd((int64_t)kcap * kcap).off;
       x.R2 = B.wd((int64_t)kcap * kcap).off;
@@ -1148,25 +1153,36 @@ void Planner::coarsen() {
     // effective width of a merge: kappa of the two children (device side)
     auto wd1 = [&](const MNode& x) { return x.c0 >= 0 ? Iw(mn[x.c0].Kap) : DRef<int>(); };
     auto wd2 = [&](const MNode& x) { return x.c1 >= 0 ? Iw(mn[x.c1].Kap) : DRef<int>(); };
-    {  // R_Z: R factor of Z
+    {  // R_Z: R factor of Z (Z = I: R_Z = I, skipped)
       QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
-        q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
+        if (!x.zI) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
       }
     }
-    {  // condensed block G^ = U R_Z^* (same singular values as U Z^*)
+    {  // condensed block G^ = U R_Z^* (same singular values as U Z^*);
+       // Z = I: G^ = U;  U = I: G^ = R_Z^*, used through a transposed operand
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.zI) {
+          x.Gh = x.U;
+          continue;
+        }
+        if (x.uI) continue;
         g.task(Dw(x.Gh), x.K, x.m, x.K);
         g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
       }
     }
-    {  // R factor of G^, stored transposed
+    {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
+       // vectors of G^ = R_Z^* as its left ones and replaces R_G^*
       QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.uI) {
+          x.RGt = x.RZ;
+          continue;
+        }
         q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
       }
     }
@@ -1212,7 +1228,8 @@ void Planner::coarsen() {
       for (int i : lv) {
         MNode& x = mn[i];
         g.task(Dw(x.Yk), kcap, x.m, kcap);
-        g.mm(Dw(x.Gh), x.K, Dw(x.Vk), kcap, x.K);
+        if (x.uI) g.mm(Dw(x.RZ), x.K, Dw(x.Vk), kcap, x.K, h2k::IT_TRANS_A);
+        else g.mm(Dw(x.Gh), x.K, Dw(x.Vk), kcap, x.K);
       }
     }
     {
@@ -1239,18 +1256,26 @@ void Planner::coarsen() {
         g.mm(Dw(x.Yk), kcap, Dw(x.T1), kcap, kcap);
       }
     }
-    {
+    {  // T = U^* U^  (U = I: T = U^)
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.uI) {
+          x.Tm = x.Uh;
+          continue;
+        }
         g.task(Dw(x.Tm), kcap, x.K, kcap);
         g.mm(Dw(x.U), x.K, Dw(x.Uh), kcap, x.m, h2k::IT_TRANS_A);
       }
     }
-    {  // Z^ = Z (U^* U^) = G^* U^:  G~ = U^ U^^* G = U^ Z^^*
+    {  // Z^ = Z (U^* U^) = G^* U^:  G~ = U^ U^^* G = U^ Z^^*  (Z = I: Z^ = T)
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.zI) {
+          x.Zh = x.Tm;
+          continue;
+        }
         g.task(Dw(x.Zh), kcap, x.n, kcap);
         g.mm(Dw(x.Z), x.K, Dw(x.Tm), kcap, x.K);
       }
