@@ -81,17 +81,18 @@ struct SvdTask {
   const int* split_dev;
   double tol_abs, tol_rel, tol_scale;
   int lda, ldu, rows, cols, kcap, trans_a, frob, ovf_bit, urows;
-  // qrcp != 0 (square input, absolute threshold only): first a column-pivoted
-  // Householder QR of A^T that stops once the remaining Frobenius norm is at
-  // most tau/8; the Jacobi then runs on the r pivoted rows only, with the
-  // threshold 3 tau / 4.  The projection error of the result stays <= tau.
+  // qrcp != 0 (absolute threshold only): first a column-pivoted Householder
+  // QR of A^T that stops once the remaining Frobenius norm is at most tau/8;
+  // the Jacobi then runs on the rows x r factor only, with the threshold
+  // 3 tau / 4.  The projection error of the result stays <= tau; sigma holds
+  // the singular values of the factor (within tau/8 of those of A).
   int qrcp;
 };
 
-// Lower bound of a block norm from the R factors of its pieces: for every
-// group, tau[g] = factor[g] * max over its matrices of the largest row norm
-// (row j of R^T = column j of R, whose norm is that of column j of the
-// condensed block, a lower bound of its spectral norm).
+// Lower bound of a block norm from factors of its pieces: for every group,
+// out = factor * max over its matrices of the largest row or column norm
+// (every row and column norm of a matrix is at most its spectral norm; the
+// matrices are pieces of the block or factors with the same Gram matrix).
 struct RefMat {
   const double* a;
   int lda, rows, cols;

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   if (wcls <= wlo || wcls > WMAX) return;  // another launch handles this size class
   const int tid = threadIdx.x;
   const double ref = tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0;
-  const bool qr = tk.qrcp && tk.tol_rel == 0.0 && rows == cols;
+  const bool qr = tk.qrcp && tk.tol_rel == 0.0;
   double ss = 0.0;
   if (!qr) {
     for (int e = tid; e < cols * WMAX; e += NT) {
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       ss += v * v;
     }
   } else {
-    // X = A^T in column layout: column l of X is row l of A
+    // X = A^T (cols x rows) in column layout: column l of X is row l of A
     for (int e = tid; e < rows * WMAX; e += NT) {
       int l = e / WMAX, i = e - l * WMAX;
       double v = 0.0;
@@ -345,22 +345,23 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   const bool empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
   double jthr_scale = 1.0;
   if (!empty && qr) {
-    // column-pivoted Householder QR of X (w x w), stopped when the remaining
+    // column-pivoted Householder QR of X (ni x nl), stopped when the remaining
     // columns have Frobenius norm <= tau/8
-    const int w = rows;
+    const int nl = rows, ni = cols;
     const double tq = 0.125 * (tk.tol_abs + ref);
-    for (int l = tid; l < w; l += NT) {
+    for (int l = tid; l < nl; l += NT) {
       double v = 0.0;
-      for (int i = 0; i < w; ++i) v += M[l * LD + i] * M[l * LD + i];
+      for (int i = 0; i < ni; ++i) v += M[l * LD + i] * M[l * LD + i];
       nrm[l] = v;
       perm[l] = l;
     }
     int r = 0;
-    for (int j = 0; j < w; ++j) {
+    const int jmax = nl < ni ? nl : ni;
+    for (int j = 0; j < jmax; ++j) {
       // remaining Frobenius norm and pivot
       double part = 0.0, best = -1.0;
       int bi = j;
-      for (int l = j + tid; l < w; l += NT) {
+      for (int l = j + tid; l < nl; l += NT) {
         part += nrm[l];
         if (nrm[l] > best) { best = nrm[l]; bi = l; }
       }
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
         if (tid < off) {
           red[tid] += red[tid + off];
           const int a = redi[tid], b = redi[tid + off];
-          const double va = (a < w) ? nrm[a] : -1.0, vb = (b < w) ? nrm[b] : -1.0;
+          const double va = (a < nl) ? nrm[a] : -1.0, vb = (b < nl) ? nrm[b] : -1.0;
           if (vb > va || (vb == va && b < a)) redi[tid] = b;
         }
         __syncthreads();
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       const int p = redi[0];
       r = j + 1;
       if (p != j) {  // swap columns j and p
-        for (int i = tid; i < w; i += NT) {
+        for (int i = tid; i < ni; i += NT) {
           double t = M[j * LD + i];
           M[j * LD + i] = M[p * LD + i];
           M[p * LD + i] = t;
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       __syncthreads();
       // Householder reflector of column j, rows j..w-1
       double x2p = 0.0;
-      for (int i = j + 1 + tid; i < w; i += NT) x2p += M[j * LD + i] * M[j * LD + i];
+      for (int i = j + 1 + tid; i < ni; i += NT) x2p += M[j * LD + i] * M[j * LD + i];
       const double x2 = block_sum<NT>(x2p, red);
       if (tid == 0) {
         const double alpha = M[j * LD + j];
@@ -414,30 +415,30 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       __syncthreads();
       const double tau = sh_tau, scal = sh_scal;
       // apply to the remaining columns (one column per thread) and update norms
-      for (int l = j + 1 + tid; l < w; l += NT) {
+      for (int l = j + 1 + tid; l < nl; l += NT) {
         if (tau != 0.0) {
           double d = M[l * LD + j];
-          for (int i = j + 1; i < w; ++i) d += scal * M[j * LD + i] * M[l * LD + i];
+          for (int i = j + 1; i < ni; ++i) d += scal * M[j * LD + i] * M[l * LD + i];
           M[l * LD + j] -= tau * d;
           const double f = tau * d * scal;
-          for (int i = j + 1; i < w; ++i) M[l * LD + i] -= f * M[j * LD + i];
+          for (int i = j + 1; i < ni; ++i) M[l * LD + i] -= f * M[j * LD + i];
         }
         double v = 0.0;
-        for (int i = j + 1; i < w; ++i) v += M[l * LD + i] * M[l * LD + i];
+        for (int i = j + 1; i < ni; ++i) v += M[l * LD + i] * M[l * LD + i];
         nrm[l] = v;
       }
       __syncthreads();
     }
     __syncthreads();
     // T = rows 0..r-1 of the factor, columns back in original order; the
-    // Jacobi matrix is T^T (w x r): column i, row perm[l] = T[i][l]
+    // Jacobi matrix is T^T (nl x r): column i, row perm[l] = T[i][l]
     double stage[STAGE];
 #pragma unroll
     for (int q = 0; q < STAGE; ++q) {
       const int e = tid + q * NT;
       stage[q] = 0.0;
-      if (e < r * w) {
-        const int i = e / w, l = e - i * w;
+      if (e < r * nl) {
+        const int i = e / nl, l = e - i * nl;
         stage[q] = (l >= i) ? M[l * LD + i] : 0.0;
       }
     }
@@ -445,8 +446,8 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
 #pragma unroll
     for (int q = 0; q < STAGE; ++q) {
       const int e = tid + q * NT;
-      if (e < r * w) {
-        const int i = e / w, l = e - i * w;
+      if (e < r * nl) {
+        const int i = e / nl, l = e - i * nl;
         M[i * LD + perm[l]] = stage[q];
       }
     }
@@ -650,6 +651,14 @@ __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ ta
     for (int r = threadIdx.x; r < m.rows; r += blockDim.x) {
       double s = 0.0;
       for (int c = 0; c < m.cols; ++c) {
+        double x = m.a[(int64_t)r * m.lda + c];
+        s += x * x;
+      }
+      best = fmax(best, s);
+    }
+    for (int c = threadIdx.x; c < m.cols; c += blockDim.x) {
+      double s = 0.0;
+      for (int r = 0; r < m.rows; ++r) {
         double x = m.a[(int64_t)r * m.lda + c];
         s += x * x;
       }

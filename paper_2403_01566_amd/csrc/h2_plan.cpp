@@ -100,6 +100,7 @@ struct PSvd {
   int tolkind;          // 0: coarsening (Frobenius tail), 1: row, 2: column (largest dropped value)
   double tolfactor;
   int lda, ldu, rows, cols, kcap;
+  int trans_a = 0;
 };
 struct PRef {
   int first, count;
@@ -1010,6 +1011,9 @@ void Planner::coarsen() {
     // dense leaf forms: U = I (uI) or Z = I (zI); the identity factor is never
     // formed and the steps that would multiply by it are skipped
     bool uI = false, zI = false;
+    // dense leaf block of at most 128 x 128: the left singular vectors U^ of
+    // G come straight from the SVD of G (no QR, no Y = G^ V_k orthonormalisation)
+    bool direct = false;
     int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
             Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
   };
@@ -1122,6 +1126,7 @@ void Planner::coarsen() {
         MNode& x = mn[i];
         x.uI = x.U == -2;
         x.zI = x.Z == -2;
+        x.direct = (x.uI || x.zI) && std::max(x.m, x.n) <= 128;
       }
     }
     int wmax = 0;
@@ -1130,16 +1135,18 @@ void Planner::coarsen() {
       wmax = std::max(wmax, x.K);
       P.max_coarse_K = std::max(P.max_coarse_K, x.K);
       if (x.K > 128) throw Error(H2_ERR_TOO_LARGE, "coarsening width above 128");
-      if (!x.zI) x.RZ = B.wd((int64_t)x.K * x.K).off;
-      if (!x.zI && !x.uI) x.Gh = B.wd((int64_t)x.m * x.K).off;
-      if (!x.uI) x.RGt = B.wd((int64_t)x.K * x.K).off;
-      x.Vk = B.wd((int64_t)x.K * kcap).off;
-      x.Sig = B.wd(x.K).off;
+      if (!x.direct) {
+        if (!x.zI) x.RZ = B.wd((int64_t)x.K * x.K).off;
+        if (!x.zI && !x.uI) x.Gh = B.wd((int64_t)x.m * x.K).off;
+        if (!x.uI) x.RGt = B.wd((int64_t)x.K * x.K).off;
+        x.Vk = B.wd((int64_t)x.K * kcap).off;
+        x.Yk = B.wd((int64_t)x.m * kcap).off;
+        x.Gy = B.wd((int64_t)kcap * kcap).off;
+        x.T1 = B.wd((int64_t)kcap * kcap).off;
+        x.R1 = B.wd((int64_t)kcap * kcap).off;
+      }
+      x.Sig = B.wd(std::max(x.K, x.n)).off;
       x.Kap = B.wi(1).off;
-      x.Yk = B.wd((int64_t)x.m * kcap).off;
-      x.Gy = B.wd((int64_t)kcap * kcap).off;
-      x.T1 = B.wd((int64_t)kcap * kcap).off;
-      x.R1 = B.wd((int64_t)kcap * kcap).off;
       x.Uh = B.wd((int64_t)x.m * kcap).off;
       if (!x.uI) x.Tm = B.wd((int64_t)x.K * kcap).off;
       if (!x.zI) x.Zh = B.wd((int64_t)x.n * kcap).off;
@@ -1157,7 +1164,7 @@ void Planner::coarsen() {
       QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
-        if (!x.zI) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
+        if (!x.zI && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
       }
     }
     {  // condensed block G^ = U R_Z^* (same singular values as U Z^*);
@@ -1165,11 +1172,11 @@ void Planner::coarsen() {
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct || x.uI) continue;
         if (x.zI) {
           x.Gh = x.U;
           continue;
         }
-        if (x.uI) continue;
         g.task(Dw(x.Gh), x.K, x.m, x.K);
         g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
       }
@@ -1179,6 +1186,7 @@ void Planner::coarsen() {
       QrSplit q(B, wmax);
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct) continue;
         if (x.uI) {
           x.RGt = x.RZ;
           continue;
@@ -1196,7 +1204,13 @@ void Planner::coarsen() {
         r.count = (int)kv.second.size();
         r.factor = 1.0 / hsum[kv.first];
         r.out = Dw(tau[kv.first]);
-        for (int i : kv.second) st.refmat.push_back({Dw(mn[i].RGt), mn[i].K, mn[i].K, mn[i].K});
+        for (int i : kv.second) {
+          const MNode& x = mn[i];
+          // any row norm of G (or of a factor with the same Gram matrix) is a lower bound of its norm
+          if (!x.direct) st.refmat.push_back({Dw(x.RGt), x.K, x.K, x.K});
+          else if (x.zI) st.refmat.push_back({Dw(x.U), x.K, x.m, x.n});
+          else st.refmat.push_back({Dw(x.Z), x.K, x.n, x.m});
+        }
         st.ref.push_back(r);
       }
     }
@@ -1220,6 +1234,14 @@ void Planner::coarsen() {
         s.rows = x.K;
         s.cols = x.K;
         s.kcap = kcap;
+        if (x.direct) {  // left singular vectors of G (m x n) itself
+          s.a = x.zI ? Dw(x.U) : Dw(x.Z);
+          s.trans_a = x.zI ? 0 : 1;
+          s.u = Dw(x.Uh);
+          s.rows = x.m;
+          s.cols = x.n;
+          st.wmax = std::max(st.wmax, std::max(x.m, x.n));
+        }
         st.svd.push_back(s);
       }
     }
@@ -1227,6 +1249,7 @@ void Planner::coarsen() {
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct) continue;
         g.task(Dw(x.Yk), kcap, x.m, kcap);
         if (x.uI) g.mm(Dw(x.RZ), x.K, Dw(x.Vk), kcap, x.K, h2k::IT_TRANS_A);
         else g.mm(Dw(x.Gh), x.K, Dw(x.Vk), kcap, x.K);
@@ -1236,6 +1259,7 @@ void Planner::coarsen() {
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct) continue;
         g.task(Dw(x.Gy), kcap, kcap, kcap);
         g.mm(Dw(x.Yk), kcap, Dw(x.Yk), kcap, x.m, h2k::IT_TRANS_A);
       }
@@ -1245,6 +1269,7 @@ void Planner::coarsen() {
       st.wmax = kcap;
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct) continue;
         st.chol.push_back({Dw(x.Gy), Dw(x.T1), Dw(x.R1), Iw(x.Kap), kcap, kcap, kcap, kcap});
       }
     }
@@ -1252,6 +1277,7 @@ void Planner::coarsen() {
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
+        if (x.direct) continue;
         g.task(Dw(x.Uh), kcap, x.m, kcap);
         g.mm(Dw(x.Yk), kcap, Dw(x.T1), kcap, kcap);
       }
@@ -1579,7 +1605,7 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     v[i].rows = s.rows;
     v[i].cols = s.cols;
     v[i].kcap = s.kcap;
-    v[i].trans_a = 0;
+    v[i].trans_a = s.trans_a;
   }
   if (!inplace) {
     while (blob.size() % 64) blob.push_back(0);
