@@ -1,16 +1,32 @@
 """Throughput benchmark of the adaptive H2-matrix product on one MI355X.
 
-One step = one complete h2_mul (exact product, coarsening, adaptive row and
-column bases, couplings) on operands already resident in HBM with the
-product plan cached.  Default workload: unit sphere from an icosahedron
-refined 5 times (n = 20480 triangle centroids), single-layer kernel
-1/(4 pi |x-y|), leaf size 64, eta = 1, tensor Chebyshev order 4 (k = 64),
-A*A at eps = 1e-6.  Both the plain FP64 form and the FP32-bulk /
-FP64-recompression form are requested; the library runs FP32 bulk only for
-eps >= 1e-5, so at this eps both legs compute in FP64 and `value` is the
-plain FP64 rate (the JSON says which precision each leg used).
+One step = one complete h2_mul (exact product in the induced tree, coarsening,
+adaptive row and column bases, couplings) on operands already resident in HBM
+with the product plan cached.  Default workload: unit sphere from an
+icosahedron refined 5 times (n = 20480 triangle centroids), single-layer
+kernel 1/(4 pi |x-y|) with the row-nearfield-mean diagonal, leaf size 64,
+eta = 1, tensor Chebyshev order 4 (k = 64), A*A at eps = 1e-6.
 
-Prints one JSON line (see the repository's bench contract).
+Two legs are timed: plain FP64 and FP32 bulk / FP64 recompression.  The
+library runs the FP32 bulk only for eps >= 1e-5 (FP32 rounding of the exact
+product would exceed the coarsening tolerance below that), so at eps = 1e-6
+both legs compute in FP64 and `value` is the FP64 rate; the JSON says which
+precision each leg used.
+
+Roofline: the library records HIP events around every kernel launch on its
+own stream during the timed steps (timing mode 2); the dominant kernel is
+the one with the largest device time.  Its algorithmic flops (or bytes) per
+launch come from one untimed counting call (timing mode 3: the QR and SVD
+kernels report the sizes they factored).  achieved = algorithmic work per
+launch / average launch duration.
+
+cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
+bounded sample: for the sphere workloads the full oracle product of the same
+construction one refinement level lower (n = 5120), scaled to the timed
+workload by the ratio of the two products' algorithmic flops as the library
+counts them; for the small grid workload the full product itself.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,23 +37,21 @@ import os
 import sys
 import time
 
-import numpy as np
-
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-KIND_NAMES = ["gemm_f64", "gemm_f32", "qr", "svd", "chol", "fill", "convert", "ref"]
+METRIC = "H² products/s + roofline fraction at stated eps vs plain FP64; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-FP64_PEAK_TFLOPS = 78.6
-FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU (vector FMA and MFMA alike)
+ALU_KERNELS = ("qr_kernel", "svd_kernel", "chol_kernel")
 
 WORKLOADS = {
-    "c1": dict(desc="32x32 grid in [0,1]^2, -log|x-y|, leaf 32, eta 1/2, Chebyshev order 3 (k=9), A*A, eps 1e-4",
-               eps=1e-4, geom=("grid", 32), kernel=0, leaf=32, order=3, eta=0.5, diag=0),
-    "c2": dict(desc="icosphere level 5 (n=20480), 1/(4 pi r), leaf 64, eta 1, Chebyshev order 4 (k=64), A*A, eps 1e-6",
-               eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1),
-    "c3": dict(desc="icosphere level 6 (n=81920), single layer times double layer, leaf 64, eta 1, order 4, eps 1e-4",
-               eps=1e-4, geom=("ico", 6), kernel=1, leaf=64, order=4, eta=1.0, diag=1, dlp=True),
+    "c1": dict(desc="32x32 grid in [0,1]^2, -log|x-y| (diag 0), leaf 32, eta 1/2, Chebyshev order 3 (k=9), "
+                    "A*A, eps 1e-4",
+               eps=1e-4, geom=("grid", 32), kernel=0, leaf=32, order=3, eta=0.5, diag=0, sample=None),
+    "c2": dict(desc="icosphere level 5 (n=20480 centroids), 1/(4 pi |x-y|) (diag = row nearfield mean), leaf 64, "
+                    "eta 1, Chebyshev order 4 (k=64), A*A, eps 1e-6",
+               eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1, sample=("ico", 4)),
 }
 
 
@@ -48,48 +62,92 @@ def geometry(g):
     return W.icosphere(g[1])
 
 
-def build(h2, ctx, cfg):
-    P, nrm = geometry(cfg["geom"])
+def build(h2, ctx, cfg, geom=None):
+    P, nrm = geometry(geom or cfg["geom"])
     T = h2.Tree(ctx, P, cfg["leaf"])
     A = h2.Matrix.interpolated(ctx, T, T, cfg["kernel"], cfg["order"], cfg["eta"], cfg["diag"], nrm)
-    B = A
-    if cfg.get("dlp"):
-        B = h2.Matrix.interpolated(ctx, T, T, 2, cfg["order"], cfg["eta"], 0, nrm)
-    return P, nrm, T, A, B
+    return T, A
 
 
-def time_mode(h2, ctx, A, B, eps, prec, steps, warmup):
-    opt = h2.default_options(precision=prec)
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def run_mode(h2, ctx, A, eps, prec, steps, warmup):
+    nk = h2.NKERNEL
     for _ in range(warmup):
-        C, st = h2.mul(ctx, A, B, eps, opt)
+        C, _ = h2.mul(ctx, A, A, eps, h2.default_options(precision=prec))
         del C
-    lat = []
+    # untimed: algorithmic work of every kernel from the sizes the kernels report
+    C, cnt = h2.mul(ctx, A, A, eps, h2.default_options(precision=prec, timing=3))
+    del C
+    opt = h2.default_options(precision=prec, timing=2)
+    t_k, l_k, lat, phase = [0.0] * nk, [0] * nk, [], [0.0] * 8
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
-        C, st = h2.mul(ctx, A, B, eps, opt)   # returns after the device work completed
+        C, st = h2.mul(ctx, A, A, eps, opt)   # returns after the device work has completed
         lat.append(time.perf_counter() - t1)
         del C
+        for i in range(nk):
+            t_k[i] += st["t_kernel"][i]
+            l_k[i] += st["launches_kernel"][i]
+        for i in range(8):
+            phase[i] += st["t_phase"][i]
     total = time.perf_counter() - t0
-    # one more call with per-kernel-class device timing (not part of the timed region)
-    C, stk = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec, timing=2))
-    return total, lat, st, stk, C
+    return dict(total=total, lat=lat, st=st, cnt=cnt, t_k=t_k, l_k=l_k, phase=[p / steps for p in phase])
 
 
-def cpu_baseline(cfg, budget_s=25.0):
-    """The FP64 oracle on the host cores, on a bounded sample of the workload:
-    the exact-product phase of the oracle restricted to the first top-level
-    row block of the induced tree, scaled by the fraction of operations."""
+def roofline(names, r, steps):
+    t_k, l_k, cnt = r["t_k"], r["l_k"], r["cnt"]
+    dom = max(range(len(names)), key=lambda i: t_k[i])
+    name = names[dom]
+    launches = cnt["launches_kernel"][dom]
+    avg_launch_s = max(1e-12, t_k[dom] / max(1, l_k[dom]) * 1e-3)
+    alu = name.startswith(ALU_KERNELS)
+    per_launch = (cnt["flops_kernel"][dom] if alu else cnt["bytes_kernel"][dom]) / max(1, launches)
+    if alu:
+        achieved = per_launch / avg_launch_s / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
+    else:
+        achieved = per_launch / avg_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": name, "launches_per_step": launches, "ms_per_launch": avg_launch_s * 1e3,
+                 "units_per_launch": cnt["units_kernel"][dom] / max(1, launches),
+                 "algorithmic_per_launch": per_launch,
+                 "share_of_device_time": t_k[dom] / max(1e-30, sum(t_k))})
+    return roof
+
+
+def cpu_baseline(h2, ctx, cfg, gpu_flops_alg):
+    """The oracle (test infrastructure, untuned) on the host cores, on a bounded sample."""
     import oracle as O
-    P, nrm = geometry(cfg["geom"])
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"), default=1)
+    except Exception:  # threadpoolctl missing: report the visible cores
+        cores = os.cpu_count() or 1
+    geom = cfg["sample"] or cfg["geom"]
+    P, nrm = geometry(geom)
     T = O.ClusterTree(P, cfg["leaf"])
     A = O.build_interpolated(T, cfg["kernel"], cfg["order"], cfg["eta"], diag=cfg["diag"], normals=nrm)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    C, info = O.mul(A, A, cfg["eps"])
+    O.mul(A, A, cfg["eps"])
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "products/s", "cores": threads, "kind": "oracle",
-            "sample": "one full product of the workload", "seconds": dt}
+    scale = 1.0
+    if cfg["sample"]:
+        _, As = build(h2, ctx, cfg, cfg["sample"])
+        _, ss = h2.mul(ctx, As, As, cfg["eps"])
+        scale = ss["flops_alg"] / gpu_flops_alg
+        sample = (f"full oracle product of the same construction at icosphere level {geom[1]} (n={len(P)}), "
+                  f"{dt:.1f} s, scaled by the ratio {scale:.4f} of the library's algorithmic flops "
+                  f"(n={len(P)} over the timed workload)")
+    else:
+        sample = f"full oracle product of the timed workload, {dt:.1f} s"
+    return {"value": scale / dt, "unit": "products/s", "cores": int(cores), "kind": "oracle", "sample": sample,
+            "seconds": dt}
 
 
 def main():
@@ -101,46 +159,32 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "the product runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     from paper_2403_01566_amd import h2
+    names = h2.kernel_names()
     cfg = WORKLOADS[args.workload]
     eps = cfg["eps"]
     ctx = h2.Context(0)
-    print(f"[bench] building operands: {cfg['desc']}", file=sys.stderr, flush=True)
-    P, nrm, T, A, B = build(h2, ctx, cfg)
-    res = {}
+    say(f"building operands: {cfg['desc']}")
+    T, A = build(h2, ctx, cfg)
     modes = [("fp64", h2.PREC_FP64)] + ([] if args.fp64_only else [("fp32_bulk", h2.PREC_FP32_BULK)])
+    res = {}
     for name, prec in modes:
-        print(f"[bench] timing {name}", file=sys.stderr, flush=True)
-        total, lat, st, stk, C = time_mode(h2, ctx, A, B, eps, prec, args.steps, args.warmup)
-        res[name] = (total, lat, st, stk)
-    # headline: the FP32-bulk form where the library runs it at this eps, else plain FP64
-    head = "fp32_bulk" if "fp32_bulk" in res and res["fp32_bulk"][2]["prec_used"] == h2.PREC_FP32_BULK else "fp64"
-    total, lat, st, stk = res[head]
-    ms = 1000.0 * total / args.steps
-    lat_ms = sorted(1000.0 * x for x in lat)
+        say(f"timing {name}: {args.warmup} warmup + {args.steps} steps")
+        res[name] = run_mode(h2, ctx, A, eps, prec, args.steps, args.warmup)
+        say(f"{name}: {1000.0 * res[name]['total'] / args.steps:.1f} ms per product")
+    head = "fp32_bulk" if "fp32_bulk" in res and res["fp32_bulk"]["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"
+    r = res[head]
+    st = r["st"]
+    ms = 1000.0 * r["total"] / args.steps
+    lat_ms = sorted(1000.0 * x for x in r["lat"])
     p50 = lat_ms[len(lat_ms) // 2]
     p99 = lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)]
-    # dominant kernel class by device time
-    tk = stk["t_kind"]
-    dom = max(range(8), key=lambda i: tk[i])
-    per_launch_ms = tk[dom] / max(1, stk["launches_kind"][dom])
-    if dom in (0, 1, 5, 6):
-        achieved = stk["bytes_kind"][dom] / (tk[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    else:
-        achieved = stk["flops_kind"][dom] / (tk[dom] * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-    roof["kernel"] = KIND_NAMES[dom]
-    roof["ms_per_product"] = tk[dom]
-    roof["ms_per_launch"] = per_launch_ms
     out = {
-        "metric": "H2 products/s at stated eps (FP32 bulk / FP64 recompression vs plain FP64)",
+        "metric": METRIC,
         "value": 1000.0 / ms,
         "unit": "products/s",
         "n_gpus": 1,
@@ -151,24 +195,28 @@ def main():
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "fp32_bulk" else "f64",
-        "data": "synthetic",
+        "data": "synthetic (seeded geometry, operands built by interpolation on the device)",
         "config": {"workload": cfg["desc"], "n": int(T.n), "eps": eps, "n_adm": st["n_adm"],
                    "n_inadm": st["n_inadm"], "rank_max": [st["rank_max_row"], st["rank_max_col"]]},
         "latency_ms": {"p50": p50, "p99": p99},
-        "roofline": roof,
-        "kernel_ms": {KIND_NAMES[i]: tk[i] for i in range(8)},
-        "phase_ms": dict(zip(["prep", "exact", "leaf", "coarsen", "row", "col", "couple", "total"], stk["t_phase"])),
+        "roofline": roofline(names, r, args.steps),
+        "phase_ms": dict(zip(["prep", "exact", "leaf", "coarsen", "row", "col", "couple", "total"], r["phase"])),
+        "kernels": {names[i]: {"ms_per_step": r["t_k"][i] / args.steps,
+                               "launches_per_step": r["cnt"]["launches_kernel"][i],
+                               "units_per_step": r["cnt"]["units_kernel"][i],
+                               "gflop_per_step": r["cnt"]["flops_kernel"][i] * 1e-9,
+                               "gbyte_per_step": r["cnt"]["bytes_kernel"][i] * 1e-9}
+                    for i in range(len(names)) if r["cnt"]["launches_kernel"][i]},
+        "headline_mode": head,
+        "modes": {name: {"products_per_s": args.steps / x["total"],
+                         "ms_per_step": 1000.0 * x["total"] / args.steps,
+                         "precision_used": "fp32_bulk" if x["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"}
+                  for name, x in res.items()},
     }
-    out["modes"] = {}
-    for name, (tt, ll, ss, sk) in res.items():
-        out["modes"][name] = {"products_per_s": args.steps / tt, "ms_per_step": 1000.0 * tt / args.steps,
-                              "precision_used": "fp32_bulk" if ss["prec_used"] == h2.PREC_FP32_BULK else "fp64",
-                              "kernel_ms": {KIND_NAMES[i]: sk["t_kind"][i] for i in range(8)}}
-    out["headline_mode"] = head
     if not args.no_cpu_baseline:
-        print("[bench] oracle on host cores", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(cfg)
-    print(json.dumps(out))
+        say("oracle on the host cores (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(h2, ctx, cfg, st["flops_alg"])
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

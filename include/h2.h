@@ -102,29 +102,49 @@ typedef struct {
   double budget_col;
   int max_rank;        /* rank cap of the result bases (<= 64; 0 => default)          */
   int coarse_rank;     /* rank cap of a coarsened block (<= 64; 0 => default 64)       */
-  int timing;          /* 1: per-phase device times; 2: also per-kernel-class times     */
+  int timing;          /* 1: per-phase device times; 2: also device times of every kernel
+                          launch (events around each); 3: as 2, plus the algorithmic work of
+                          every kernel from the sizes the kernels report (one extra
+                          device-to-host copy after the product)                         */
 } h2_mul_options;
+
+/* Number of kernels in the per-kernel statistics; h2_kernel_name(i) names kernel i. */
+#define H2_NKERNEL 12
 
 typedef struct {
   double t_phase[8];   /* device ms: 0 operand prep, 1 exact product, 2 leaf assembly,
                           3 coarsening, 4 row basis, 5 column basis, 6 couplings, 7 total */
   double t_plan_ms;    /* host planning time of this call (0 when the plan was cached)   */
-  double bytes_alg;    /* algorithmic bytes moved by the product (see DESIGN notes)      */
-  double flops_alg;
+  double bytes_alg;    /* algorithmic bytes of the product from the planned sizes          */
+  double flops_alg;    /* algorithmic flops of the product from the planned sizes          */
   int prec_used;       /* h2_precision actually used for the bulk                        */
   int rank_max_row, rank_max_col, coarse_rank_max;
   int64_t n_adm, n_inadm;
-  int64_t launches;
-  /* per kernel class (0 gemm fp64, 1 gemm fp32, 2 qr, 3 svd, 4 chol, 5 fill, 6 convert):
-     device ms (timing == 2 only), launches, algorithmic bytes and flops of one product */
-  double t_kind[8];
-  int64_t launches_kind[8];
-  double bytes_kind[8];
-  double flops_kind[8];
+  int64_t launches;    /* kernel launches of the product                                  */
+  /* per kernel i < H2_NKERNEL:
+     t_kernel        device ms summed over the kernel's launches (timing >= 2)
+     launches_kernel launches of the kernel
+     units_kernel    matrices (tasks) the kernel processed (timing == 3)
+     flops_kernel    algorithmic flops: QR 2mw^2 - 2w^3/3 of each factored m x w
+                     matrix (2wm^2 - 2m^3/3 when m < w), SVD the pivoted QR steps and
+                     Jacobi rotations it ran,
+                     GEMM 2mnk of the planned (upper bound) sizes (timing == 3)
+     bytes_kernel    algorithmic bytes: each input read once, each output written
+                     once (timing == 3)                                                  */
+  double t_kernel[H2_NKERNEL];
+  int64_t launches_kernel[H2_NKERNEL];
+  double units_kernel[H2_NKERNEL];
+  double flops_kernel[H2_NKERNEL];
+  double bytes_kernel[H2_NKERNEL];
 } h2_mul_stats;
 
 /* Default options (all fields as documented above). */
 void h2_mul_default_options(h2_mul_options* opt);
+
+/* Name of kernel i of the per-kernel statistics (the kernel's template
+ * instantiation as a profiler lists it); "" for i out of range.  The string
+ * is static. */
+const char* h2_kernel_name(int i);
 
 /* C = X Y with the block-relative bound eps (0 < eps < 1), see the header
  * comment.  X and Y are read-only and stay resident.  The product plan

@@ -4,6 +4,7 @@
 #include <string>
 
 #include "h2_core.h"
+#include "h2_kernels.h"
 
 struct h2_context_s {
   std::shared_ptr<h2::Context> core;
@@ -160,6 +161,8 @@ void h2_mul_default_options(h2_mul_options* opt) {
   std::memset(opt, 0, sizeof(*opt));
   opt->precision = H2_PREC_FP64;
 }
+
+const char* h2_kernel_name(int i) { return h2k::kernel_name(i); }
 
 h2_status h2_mul(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opt, h2_matrix* C,
                  h2_mul_stats* stats) {

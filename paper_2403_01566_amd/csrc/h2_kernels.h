@@ -48,12 +48,14 @@ struct GemmTile {
 // stores R^T instead.
 // Only the first w_eff = (w_dev ? *w_dev : w) + (w_dev2 ? *w_dev2 : 0) columns
 // (at most w) are factored; rows that are zero in those columns are skipped;
-// R is written as w x w with zeros beyond w_eff.
+// R is written as w x w with zeros beyond w_eff.  Optional stat (2 ints):
+// the number of rows factored and w_eff.
 struct QrTask {
   const double* a;
   double* r;
   const int* w_dev;
   const int* w_dev2;
+  int* stat;
   int lda, ldr, m, w, trans_r, pad;
 };
 
@@ -79,6 +81,7 @@ struct SvdTask {
   const int* w_dev;
   const int* w_dev2;
   const int* split_dev;
+  int* stat;  // optional, 4 ints: rows, cols, columns after the rank reveal, Jacobi sweeps
   double tol_abs, tol_rel, tol_scale;
   int lda, ldu, rows, cols, kcap, trans_a, frob, ovf_bit, urows;
   // qrcp != 0 (absolute threshold only): first a column-pivoted Householder
@@ -128,6 +131,19 @@ void launch_gemm_f32(const GemmItem<float>* items, const GemmTask<float>* tasks,
                      int ntiles, hipStream_t s);
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s);
 void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s);
+// The QR and SVD launchers run one kernel per size class (widths <= 32, <= 64,
+// <= 128); the class-wise forms serve per-kernel timing.
+int size_classes(int wmax);
+void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s);
+void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, hipStream_t s);
+
+// Kernel identities for per-kernel statistics (the names are the template
+// instantiations a profiler shows).
+enum KernelId {
+  K_GEMM_F64, K_GEMM_F32, K_QR32, K_QR64, K_QR128, K_SVD32, K_SVD64, K_SVD128,
+  K_CHOL, K_FILL, K_CVT, K_REF, K_COUNT
+};
+const char* kernel_name(int id);
 void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s);
 void launch_ref(const RefTask* tasks, const RefMat* mats, int ntasks, hipStream_t s);
 void launch_fill(const FillTask* tasks, int ntasks, hipStream_t s);

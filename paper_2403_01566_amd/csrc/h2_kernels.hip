@@ -181,7 +181,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
   const int m = tk.m, tid = threadIdx.x;
   const int sub = tid % TPC, cgrp = tid / TPC;
   for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
-  int next = 0;
+  int next = 0, mtot = 0;
   for (;;) {
     // gather up to CH rows that are not zero in the first `we` columns
     int cr = 0;
@@ -215,6 +215,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
       next += nb;
     }
     if (cr == 0) break;
+    mtot += cr;
     __syncthreads();
     for (int j = 0; j < we; ++j) {
       if (tid < 64) {
@@ -268,15 +269,24 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
     if (tk.trans_r) tk.r[(int64_t)l * tk.ldr + i] = v;
     else tk.r[(int64_t)i * tk.ldr + l] = v;
   }
+  if (tk.stat && tid == 0) {
+    tk.stat[0] = mtot;
+    tk.stat[1] = we;
+  }
+}
+
+int size_classes(int wmax) { return wmax > 64 ? 3 : (wmax > 32 ? 2 : 1); }
+
+void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s) {
+  if (ntasks <= 0) return;
+  // each workgroup exits unless its task's effective width falls into the class
+  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 64, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
+  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
+  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 64, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
 }
 
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
-  if (ntasks <= 0) return;
-  // one launch per width class; each workgroup exits unless its task's
-  // effective width falls into the launch's class
-  hipLaunchKernelGGL((qr_kernel<32, 64, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
-  if (wmax > 32) hipLaunchKernelGGL((qr_kernel<64, 64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
-  if (wmax > 64) hipLaunchKernelGGL((qr_kernel<128, 64, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
+  for (int c = 0; c < size_classes(wmax); ++c) launch_qr_class(tasks, ntasks, c, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -344,6 +354,8 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   // absolute threshold above it
   const bool empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
   double jthr_scale = 1.0;
+  const int cols_in = cols;
+  int sweeps = 0;
   if (!empty && qr) {
     // column-pivoted Householder QR of X (ni x nl), stopped when the remaining
     // columns have Frobenius norm <= tau/8
@@ -498,9 +510,16 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
         }
         __syncthreads();
       }
+      ++sweeps;
       if (!sh_rot) break;
       __syncthreads();
     }
+  }
+  if (tk.stat && tid == 0) {
+    tk.stat[0] = rows;
+    tk.stat[1] = cols_in;
+    tk.stat[2] = empty ? 0 : cols;
+    tk.stat[3] = sweeps;
   }
   const int c_all = sq ? we : tk.cols;  // number of singular values reported
   for (int c = tid; c < c_all; c += NT) {
@@ -562,11 +581,15 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   }
 }
 
-void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s) {
+void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, hipStream_t s) {
   if (ntasks <= 0) return;
-  hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
-  if (wmax > 32) hipLaunchKernelGGL((svd_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, overflow, 32);
-  if (wmax > 64) hipLaunchKernelGGL((svd_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 64);
+  if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
+  if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, overflow, 32);
+  if (cls == 2) hipLaunchKernelGGL((svd_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 64);
+}
+
+void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s) {
+  for (int c = 0; c < size_classes(wmax); ++c) launch_svd_class(tasks, ntasks, c, overflow, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -714,6 +737,15 @@ void launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStrea
 }
 void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(cvt_f2d, dim3(1024), dim3(256), 0, s, in, out, n);
+}
+
+const char* kernel_name(int id) {
+  static const char* names[K_COUNT] = {
+      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64, 64>",
+      "qr_kernel<64, 64, 128>",    "qr_kernel<128, 64, 512>",    "svd_kernel<32, 64>",
+      "svd_kernel<64, 128>",       "svd_kernel<128, 256>",       "chol_kernel",
+      "fill_kernel",               "convert kernels",            "ref_kernel"};
+  return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 
 }  // namespace h2k

@@ -146,6 +146,7 @@ struct Step {
   size_t desc_off = 0, desc2_off = 0, tiles_off = 0;
   int ndesc = 0, ntiles = 0;
   double flops = 0, bytes = 0;
+  int64_t stat_off = -1;  // QR / SVD: per-task size reports (int workspace)
 };
 
 struct Plan {
@@ -169,8 +170,10 @@ struct Plan {
   double budget[3] = {0.25, 0.25, 0.25};
   int64_t launches = 0;
   int max_coarse_K = 0;
-  double t_kind[8] = {0}, bytes_kind[8] = {0}, flops_kind[8] = {0};
-  int64_t launches_kind[8] = {0};
+  // per kernel (h2k::KernelId): device ms, launches; algorithmic units, flops, bytes
+  double t_k[h2k::K_COUNT] = {0}, units_k[h2k::K_COUNT] = {0}, flops_k[h2k::K_COUNT] = {0},
+         bytes_k[h2k::K_COUNT] = {0};
+  int64_t launches_k[h2k::K_COUNT] = {0};
 };
 
 // ------------------------------------------------------------------ plan builder
@@ -1583,6 +1586,7 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     v[i].w_dev = res(s.w_dev, P);
     v[i].w_dev2 = res(s.w_dev2, P);
     v[i].split_dev = res(s.split_dev, P);
+    v[i].stat = P.bufi.as<int>() + st.stat_off + 4 * i;
     v[i].urows = s.urows;
     v[i].qrcp = P.qrcp;
     v[i].sigma = res(s.sigma, P);
@@ -1618,6 +1622,13 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
 }
 
 static void finalize(Plan& P, double eps) {
+  for (auto& st : P.steps) {
+    const int per = st.kind == SK_QR ? 2 : (st.kind == SK_SVD ? 4 : 0);
+    const size_t n = st.kind == SK_QR ? st.qr.size() : st.svd.size();
+    if (!per || !n) continue;
+    st.stat_off = P.wsi;
+    P.wsi += ((int64_t)(per * n) + 63) & ~int64_t(63);
+  }
   P.bufd.alloc(std::max<int64_t>(P.wsd, 1) * sizeof(double));
   P.buff.alloc(std::max<int64_t>(P.wsf, 1) * sizeof(float));
   P.bufi.alloc(std::max<int64_t>(P.wsi, 1) * sizeof(int));
@@ -1632,8 +1643,11 @@ static void finalize(Plan& P, double eps) {
       case SK_QR: {
         align(64);
         st.desc_off = blob.size();
-        for (auto& q : st.qr) {
-          h2k::QrTask t{res(q.a, P), res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), q.lda, q.ldr, q.m, q.w, q.trans_r, 0};
+        for (size_t i = 0; i < st.qr.size(); ++i) {
+          const PQr& q = st.qr[i];
+          int* stat = P.bufi.as<int>() + st.stat_off + 2 * i;
+          h2k::QrTask t{res(q.a, P), res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), stat, q.lda, q.ldr, q.m, q.w,
+                        q.trans_r, 0};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.qr.size();
@@ -1703,7 +1717,14 @@ static void set_eps(Plan& P, double eps) {
   P.eps_set = eps;
 }
 
-static void execute(Context* ctx, Plan& P, bool timing, bool per_kind, double* t_phase) {
+// Algorithmic flops of a Householder QR (R only) of an m x w matrix.
+static double qr_flops(double m, double w) {
+  return m >= w ? 2.0 * m * w * w - 2.0 / 3.0 * w * w * w : 2.0 * w * m * m - 2.0 / 3.0 * m * m * m;
+}
+
+// timing: 0 none, 1 per-phase events, 2 also events around every kernel launch,
+// 3 also the algorithmic work from the sizes the QR / SVD kernels report.
+static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
   hipStream_t s = ctx->stream;
   char* base = (char*)P.desc.p;
   std::vector<hipEvent_t> ev;
@@ -1721,89 +1742,164 @@ static void execute(Context* ctx, Plan& P, bool timing, bool per_kind, double* t
     ++nev;
   };
   P.launches = 0;
-  for (int i = 0; i < 8; ++i) {
-    P.t_kind[i] = 0;
-    P.bytes_kind[i] = 0;
-    P.flops_kind[i] = 0;
-    P.launches_kind[i] = 0;
+  for (int i = 0; i < h2k::K_COUNT; ++i) {
+    P.t_k[i] = P.units_k[i] = P.flops_k[i] = P.bytes_k[i] = 0;
+    P.launches_k[i] = 0;
   }
-  const bool per_step = timing && per_kind;
-  std::vector<hipEvent_t> sev;
-  if (per_step) {
-    sev.resize(2 * P.steps.size());
-    for (auto& e : sev) H2_HIP(hipEventCreate(&e));
-  }
+  const bool per_kernel = timing >= 2;
+  struct KEv {
+    int kid;
+    size_t step;
+    hipEvent_t a, b;
+  };
+  std::vector<KEv> kev;
+  auto timed = [&](int kid, size_t step, auto&& launch) {
+    ++P.launches;
+    ++P.launches_k[kid];
+    if (!per_kernel) {
+      launch();
+      return;
+    }
+    KEv e{kid, step, nullptr, nullptr};
+    H2_HIP(hipEventCreate(&e.a));
+    H2_HIP(hipEventCreate(&e.b));
+    H2_HIP(hipEventRecord(e.a, s));
+    launch();
+    H2_HIP(hipEventRecord(e.b, s));
+    kev.push_back(e);
+  };
   size_t si = 0;
   for (auto& st : P.steps) {
     if (st.phase != cur_phase) {
       mark(st.phase);
       cur_phase = st.phase;
     }
-    if (per_step) H2_HIP(hipEventRecord(sev[2 * si], s));
     switch (st.kind) {
       case SK_GEMM_D:
-        h2k::launch_gemm_f64((const GemmItem<double>*)(base + st.desc_off), (const GemmTask<double>*)(base + st.desc2_off),
-                             (const GemmTile*)(base + st.tiles_off), st.ntiles, s);
-        P.launches += st.ntiles > 0;
+        if (st.ntiles > 0)
+          timed(h2k::K_GEMM_F64, si, [&] {
+            h2k::launch_gemm_f64((const GemmItem<double>*)(base + st.desc_off),
+                                 (const GemmTask<double>*)(base + st.desc2_off), (const GemmTile*)(base + st.tiles_off),
+                                 st.ntiles, s);
+          });
         break;
       case SK_GEMM_F:
-        h2k::launch_gemm_f32((const GemmItem<float>*)(base + st.desc_off), (const GemmTask<float>*)(base + st.desc2_off),
-                             (const GemmTile*)(base + st.tiles_off), st.ntiles, s);
-        P.launches += st.ntiles > 0;
+        if (st.ntiles > 0)
+          timed(h2k::K_GEMM_F32, si, [&] {
+            h2k::launch_gemm_f32((const GemmItem<float>*)(base + st.desc_off),
+                                 (const GemmTask<float>*)(base + st.desc2_off), (const GemmTile*)(base + st.tiles_off),
+                                 st.ntiles, s);
+          });
         break;
       case SK_QR:
-        h2k::launch_qr((const h2k::QrTask*)(base + st.desc_off), st.ndesc, st.wmax, s);
-        P.launches += st.ndesc > 0;
+        if (st.ndesc > 0)
+          for (int c = 0; c < h2k::size_classes(st.wmax); ++c)
+            timed(h2k::K_QR32 + c, si,
+                  [&] { h2k::launch_qr_class((const h2k::QrTask*)(base + st.desc_off), st.ndesc, c, s); });
         break;
       case SK_SVD:
-        h2k::launch_svd((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, st.wmax, ctx->overflow, s);
-        P.launches += st.ndesc > 0;
+        if (st.ndesc > 0)
+          for (int c = 0; c < h2k::size_classes(st.wmax); ++c)
+            timed(h2k::K_SVD32 + c, si, [&] {
+              h2k::launch_svd_class((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, c, ctx->overflow, s);
+            });
         break;
       case SK_CHOL:
-        h2k::launch_chol((const h2k::CholTask*)(base + st.desc_off), st.ndesc, st.wmax, s);
-        P.launches += st.ndesc > 0;
+        if (st.ndesc > 0)
+          timed(h2k::K_CHOL, si,
+                [&] { h2k::launch_chol((const h2k::CholTask*)(base + st.desc_off), st.ndesc, st.wmax, s); });
         break;
       case SK_FILL:
-        h2k::launch_fill((const h2k::FillTask*)(base + st.desc_off), st.ndesc, s);
-        P.launches += st.ndesc > 0;
+        if (st.ndesc > 0)
+          timed(h2k::K_FILL, si, [&] { h2k::launch_fill((const h2k::FillTask*)(base + st.desc_off), st.ndesc, s); });
         break;
       case SK_CVT_F2D:
-        h2k::launch_convert_f32_to_f64(res(st.cvt_in, P), res(st.cvt_out, P), st.cvt_n, s);
-        P.launches += 1;
+        if (st.cvt_n > 0)
+          timed(h2k::K_CVT, si,
+                [&] { h2k::launch_convert_f32_to_f64(res(st.cvt_in, P), res(st.cvt_out, P), st.cvt_n, s); });
         break;
       case SK_REF:
-        h2k::launch_ref((const h2k::RefTask*)(base + st.desc_off), (const h2k::RefMat*)(base + st.desc2_off),
-                        st.ndesc, s);
-        P.launches += st.ndesc > 0;
+        if (st.ndesc > 0)
+          timed(h2k::K_REF, si, [&] {
+            h2k::launch_ref((const h2k::RefTask*)(base + st.desc_off), (const h2k::RefMat*)(base + st.desc2_off),
+                            st.ndesc, s);
+          });
         break;
     }
     H2_HIP(hipGetLastError());
-    if (per_step) H2_HIP(hipEventRecord(sev[2 * si + 1], s));
-    const int kind = (int)st.kind;
-    P.bytes_kind[kind] += st.bytes;
-    P.flops_kind[kind] += st.flops;
-    bool launched = (st.kind == SK_GEMM_D || st.kind == SK_GEMM_F) ? st.ntiles > 0
-                    : (st.kind == SK_CVT_F2D ? st.cvt_n > 0 : st.ndesc > 0);
-    P.launches_kind[kind] += launched;
     ++si;
   }
   mark(99);
-  if (per_step) {
-    H2_HIP(hipEventSynchronize(sev.back()));
+  if (per_kernel) {
+    if (!kev.empty()) H2_HIP(hipEventSynchronize(kev.back().b));
+    std::vector<double> step_ms(P.steps.size(), 0.0);
     static const char* trace = std::getenv("H2_TRACE");
-    static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref"};
-    for (size_t i = 0; i < P.steps.size(); ++i) {
+    for (auto& e : kev) {
       float ms = 0;
-      H2_HIP(hipEventElapsedTime(&ms, sev[2 * i], sev[2 * i + 1]));
-      P.t_kind[(int)P.steps[i].kind] += ms;
-      if (trace) {
+      H2_HIP(hipEventElapsedTime(&ms, e.a, e.b));
+      P.t_k[e.kid] += ms;
+      step_ms[e.step] += ms;
+      if (trace && ms > 0.5)
+        std::fprintf(stderr, "[h2 launch] step %3zu phase %d %-24s %8.3f ms\n", e.step, P.steps[e.step].phase,
+                     h2k::kernel_name(e.kid), ms);
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+    }
+    if (trace) {
+      static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref"};
+      for (size_t i = 0; i < P.steps.size(); ++i) {
         const Step& st = P.steps[i];
         std::fprintf(stderr, "[h2 step %3zu] phase %d %-6s tasks %7d tiles %8d wmax %4d  %9.3f ms  %.3g GF %.3g GB\n",
-                     i, st.phase, kname[(int)st.kind], st.ndesc, st.ntiles, st.wmax, ms, st.flops * 1e-9,
+                     i, st.phase, kname[(int)st.kind], st.ndesc, st.ntiles, st.wmax, step_ms[i], st.flops * 1e-9,
                      st.bytes * 1e-9);
       }
     }
-    for (auto& e : sev) (void)hipEventDestroy(e);
+  }
+  if (timing >= 3) {
+    // algorithmic work: QR / SVD from the sizes the kernels reported, the
+    // other kernels from the planned sizes
+    H2_HIP(hipStreamSynchronize(s));
+    std::vector<int> stat;
+    for (auto& st : P.steps) {
+      const int kind = (int)st.kind;
+      if (kind == SK_QR || kind == SK_SVD) {
+        const int per = kind == SK_QR ? 2 : 4;
+        const size_t n = kind == SK_QR ? st.qr.size() : st.svd.size();
+        stat.resize(per * n);
+        if (n)
+          H2_HIP(hipMemcpy(stat.data(), P.bufi.as<int>() + st.stat_off, per * n * sizeof(int),
+                           hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) {
+          if (kind == SK_QR) {
+            const double m = stat[2 * i], w = stat[2 * i + 1];
+            if (w <= 0) continue;
+            const int kid = h2k::K_QR32 + (w > 64 ? 2 : (w > 32 ? 1 : 0));
+            P.units_k[kid] += 1;
+            P.flops_k[kid] += qr_flops(m, w);
+            P.bytes_k[kid] += 8.0 * (m * w + (double)st.qr[i].w * st.qr[i].w);
+          } else {
+            const double rows = stat[4 * i], cols = stat[4 * i + 1], r = stat[4 * i + 2], sw = stat[4 * i + 3];
+            const double wc = std::max(rows, cols);
+            if (wc <= 0) continue;
+            const int kid = h2k::K_SVD32 + (wc > 64 ? 2 : (wc > 32 ? 1 : 0));
+            double fl = 0;
+            if (P.qrcp)  // pivoted QR of the cols x rows transpose, stopped after r steps
+              for (int j = 0; j < (int)r; ++j) fl += 4.0 * (rows - j) * (cols - j);
+            fl += sw * r * (r - 1) / 2.0 * 12.0 * rows;  // Jacobi: 3 dots and a rotation per pair
+            P.units_k[kid] += 1;
+            P.flops_k[kid] += fl;
+            P.bytes_k[kid] += 8.0 * (rows * cols + rows * st.svd[i].kcap + cols);
+          }
+        }
+      } else {
+        static const int kmap[] = {h2k::K_GEMM_F64, h2k::K_GEMM_F32, -1, -1, h2k::K_CHOL, h2k::K_FILL, h2k::K_CVT,
+                                   h2k::K_REF};
+        const int kid = kmap[kind];
+        P.units_k[kid] += kind == SK_CVT_F2D ? (st.cvt_n > 0) : st.ndesc;
+        P.flops_k[kid] += st.flops;
+        P.bytes_k[kid] += st.bytes;
+      }
+    }
   }
   if (timing) {
     H2_HIP(hipEventSynchronize(ev[nev - 1]));
@@ -1927,7 +2023,7 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
   double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
   double tph[8] = {0};
-  execute(ctx, *P, opt.timing != 0, opt.timing >= 2, tph);
+  execute(ctx, *P, opt.timing, tph);
   int ovf = 0;
   H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   H2_HIP(hipStreamSynchronize(ctx->stream));
@@ -1984,11 +2080,13 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
     stats->n_adm = P->n_adm;
     stats->n_inadm = P->n_inadm;
     stats->launches = P->launches;
-    for (int i = 0; i < 8; ++i) {
-      stats->t_kind[i] = P->t_kind[i];
-      stats->launches_kind[i] = P->launches_kind[i];
-      stats->bytes_kind[i] = P->bytes_kind[i];
-      stats->flops_kind[i] = P->flops_kind[i];
+    static_assert(h2k::K_COUNT == H2_NKERNEL, "kernel count");
+    for (int i = 0; i < h2k::K_COUNT; ++i) {
+      stats->t_kernel[i] = P->t_k[i];
+      stats->launches_kernel[i] = P->launches_k[i];
+      stats->units_kernel[i] = P->units_k[i];
+      stats->flops_kernel[i] = P->flops_k[i];
+      stats->bytes_kernel[i] = P->bytes_k[i];
     }
   }
   return Cm;

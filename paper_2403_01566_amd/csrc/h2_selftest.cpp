@@ -99,7 +99,7 @@ double qr_test(hipStream_t s, int m, int w) {
   double* da = up(A, keep);
   std::vector<double> R0((size_t)w * w, 0.0);
   double* dr = up(R0, keep);
-  h2k::QrTask t{da, dr, nullptr, nullptr, w, w, m, w, 0, 0};
+  h2k::QrTask t{da, dr, nullptr, nullptr, nullptr, w, w, m, w, 0, 0};
   auto* dt = up(std::vector<h2k::QrTask>{t}, keep);
   h2k::launch_qr(dt, 1, w, s);
   H2_HIP(hipStreamSynchronize(s));
@@ -159,7 +159,7 @@ double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0) {
   std::vector<int> rk0(1, 0);
   int* dk = up(rk0, keep);
   const double tau = 1e-5;
-  h2k::SvdTask t{da, du, nullptr, ds, dk, nullptr, nullptr, nullptr, nullptr, qrcp ? tau : 0.0, qrcp ? 0.0 : 1e-6, 0.0,
+  h2k::SvdTask t{da, du, nullptr, ds, dk, nullptr, nullptr, nullptr, nullptr, nullptr, qrcp ? tau : 0.0, qrcp ? 0.0 : 1e-6, 0.0,
                  w, w, w, w, w, 0, qrcp, 1, 0, qrcp};
   auto* dt = up(std::vector<h2k::SvdTask>{t}, keep);
   h2k::launch_svd(dt, 1, w, overflow, s);

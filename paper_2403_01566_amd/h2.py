@@ -30,8 +30,9 @@ EXPORTS = [
     "h2_tree_permutation", "h2_tree_info", "h2_tree_clusters", "h2_tree_destroy",
     "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
-    "h2_selftest",
+    "h2_selftest", "h2_kernel_name",
 ]
+NKERNEL = 12
 
 
 class MulOptions(C.Structure):
@@ -44,12 +45,13 @@ class MulStats(C.Structure):
     _fields_ = [("t_phase", C.c_double * 8), ("t_plan_ms", C.c_double), ("bytes_alg", C.c_double),
                 ("flops_alg", C.c_double), ("prec_used", C.c_int), ("rank_max_row", C.c_int),
                 ("rank_max_col", C.c_int), ("coarse_rank_max", C.c_int), ("n_adm", C.c_int64),
-                ("n_inadm", C.c_int64), ("launches", C.c_int64), ("t_kind", C.c_double * 8),
-                ("launches_kind", C.c_int64 * 8), ("bytes_kind", C.c_double * 8), ("flops_kind", C.c_double * 8)]
+                ("n_inadm", C.c_int64), ("launches", C.c_int64), ("t_kernel", C.c_double * NKERNEL),
+                ("launches_kernel", C.c_int64 * NKERNEL), ("units_kernel", C.c_double * NKERNEL),
+                ("flops_kernel", C.c_double * NKERNEL), ("bytes_kernel", C.c_double * NKERNEL)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_}
-        for f in ("t_phase", "t_kind", "launches_kind", "bytes_kind", "flops_kind"):
+        for f in ("t_phase", "t_kernel", "launches_kernel", "units_kernel", "flops_kernel", "bytes_kernel"):
             d[f] = list(getattr(self, f))
         return d
 
@@ -80,6 +82,7 @@ _sig = {
     "h2_matrix_storage": (C.c_int, [_vp, _lp]),
     "h2_matrix_destroy": (None, [_vp]),
     "h2_selftest": (C.c_int, [_vp, _dp, C.c_int, _ip]),
+    "h2_kernel_name": (C.c_char_p, [C.c_int]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -236,3 +239,8 @@ def mul(ctx: Context, X: Matrix, Y: Matrix, eps: float, options: MulOptions | No
     opt = options if options is not None else default_options()
     _check(_lib.h2_mul(ctx.h, X.h, Y.h, float(eps), C.byref(opt), C.byref(h), C.byref(st)))
     return Matrix(h, (ctx,) + X._keep[1:2] + Y._keep[2:3]), st.as_dict()
+
+
+def kernel_names():
+    """Names of the kernels in the per-kernel statistics (index = kernel id)."""
+    return [_lib.h2_kernel_name(i).decode() for i in range(NKERNEL)]

@@ -41,3 +41,15 @@ def test_options_defaults_without_gpu():
     from paper_2403_01566_amd import h2
     o = h2.default_options()
     assert o.precision == h2.PREC_FP64 and o.max_rank == 0 and o.theta == 0.0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_kernel_statistics_layout_matches_header():
+    """The per-kernel arrays of h2_mul_stats have H2_NKERNEL entries in the
+    header and in the binding, and every kernel id has a name."""
+    from paper_2403_01566_amd import h2
+    n = int(re.search(r"#define\s+H2_NKERNEL\s+(\d+)", open(HEADER).read()).group(1))
+    assert n == h2.NKERNEL
+    names = h2.kernel_names()
+    assert len(names) == n and all(names) and len(set(names)) == n
+    assert h2._lib.h2_kernel_name(n) == b"" and h2._lib.h2_kernel_name(-1) == b""
