@@ -45,18 +45,21 @@ struct GemmTile {
 
 // Streaming Householder QR, R factor only: A (m x w, row-major, lda) -> R (w x w).
 // R is upper triangular (rows >= min(m,w) are zero); with trans_r the kernel
-// stores R^T instead.
-// Only the first w_eff = (w_dev ? *w_dev : w) + (w_dev2 ? *w_dev2 : 0) columns
-// (at most w) are factored; rows that are zero in those columns are skipped;
-// R is written as w x w with zeros beyond w_eff.  Optional stat (2 ints):
+// stores R^T instead.  Only the first w_eff = (w_dev ? *w_dev : w) +
+// (w_dev2 ? *w_dev2 : 0) columns (at most w) are factored, R is written as
+// w x w with zeros beyond w_eff.  Rows: the first m, lowered to *m_dev when
+// m_dev is set and to mul_we * w_eff when mul_we > 0.  part >= 0 writes the
+// w_eff x w upper part only, at row offset part * w_eff (row-major, ldr; for
+// stacking the R factors of row blocks compactly).  Optional stat (2 ints):
 // the number of rows factored and w_eff.
 struct QrTask {
   const double* a;
   double* r;
   const int* w_dev;
   const int* w_dev2;
+  const int* m_dev;
   int* stat;
-  int lda, ldr, m, w, trans_r, pad;
+  int lda, ldr, m, w, trans_r, mul_we, part;
 };
 
 // One-sided Jacobi on a small matrix A (rows x cols, row-major, lda), rotating

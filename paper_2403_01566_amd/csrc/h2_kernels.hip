@@ -154,7 +154,7 @@ void launch_gemm_f32(const GemmItem<float>* items, const GemmTask<float>* tasks,
 }
 
 // ---------------------------------------------------------------------------
-// Streaming Householder QR (R only), one wavefront per matrix.
+// Streaming Householder QR (R only), one workgroup per matrix.
 // ---------------------------------------------------------------------------
 __device__ inline int eff_width(int w, const int* a, const int* b) {
   if (!a && !b) return w;
@@ -165,112 +165,107 @@ __device__ inline int eff_width(int w, const int* a, const int* b) {
 // packed upper triangle of a w x w matrix, row by row
 __device__ inline int pk(int j, int l, int w) { return j * w - (j * (j - 1)) / 2 + (l - j); }
 
-template <int WMAX, int CH, int NT>
+// The rows arrive in chunks of CH = RPT * TPC.  Column l of a chunk lives in
+// the registers of the TPC consecutive lanes of group l (lane `sub` holds rows
+// sub, sub + TPC, ...); R (packed upper triangle) stays in LDS across chunks.
+// Column step j applies the reflector of column j to every column l > j (a
+// dot product over the group's registers, one shuffle reduction, an update of
+// the registers and of R's row j).  The group of column j + 1 then builds the
+// next reflector at once from its updated registers and publishes it (the
+// vector's chunk part and tau) in a double-buffered LDS slot, so every column
+// step costs one barrier.
+template <int WMAX, int NT>
 __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks, int wlo) {
-  constexpr int TPC = NT / WMAX;        // threads per column (they split the chunk rows)
-  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 64, "threads per column");
-  constexpr int CPP = NT / TPC;         // columns per pass
+  constexpr int TPC = NT / WMAX;  // lanes per column
+  constexpr int RPT = 32;         // chunk rows per lane
+  constexpr int CH = RPT * TPC;   // chunk rows
+  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 64, "lanes per column");
   __shared__ double R[WMAX * (WMAX + 1) / 2];
-  __shared__ double C[CH * WMAX];
-  __shared__ int dest[CH];
-  __shared__ int sh_cnt;
-  __shared__ double sh_tau, sh_scal;
+  __shared__ double vb[2][CH];
+  __shared__ double tb[2][2];
   const QrTask tk = tasks[blockIdx.x];
   const int we = eff_width(tk.w, tk.w_dev, tk.w_dev2);
   if (we <= wlo || we > WMAX) return;  // another launch handles this width class
-  const int m = tk.m, tid = threadIdx.x;
-  const int sub = tid % TPC, cgrp = tid / TPC;
+  int m = tk.m;
+  if (tk.m_dev) m = min(m, *tk.m_dev);
+  if (tk.mul_we > 0) m = min(m, tk.mul_we * we);
+  const int tid = threadIdx.x, sub = tid % TPC, l = tid / TPC;
   for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
-  int next = 0, mtot = 0;
-  for (;;) {
-    // gather up to CH rows that are not zero in the first `we` columns
-    int cr = 0;
-    while (cr < CH && next < m) {
-      const int nb = min(CH - cr, m - next);
-      __syncthreads();
-      for (int e = tid; e < nb * we; e += NT) {
-        int i = e / we, l = e - i * we;
-        C[(cr + i) * we + l] = tk.a[(int64_t)(next + i) * tk.lda + l];
-      }
-      __syncthreads();
-      for (int i = tid; i < nb; i += NT) {
-        int nz = 0;
-        for (int l = 0; l < we; ++l) nz |= C[(cr + i) * we + l] != 0.0;
-        dest[i] = nz;
-      }
-      __syncthreads();
-      if (tid == 0) {
-        int pos = cr;
-        for (int i = 0; i < nb; ++i) dest[i] = dest[i] ? pos++ : -1;
-        sh_cnt = pos;
-      }
-      __syncthreads();
-      // move kept rows down; each thread owns fixed columns, rows in increasing order
-      for (int i = 0; i < nb; ++i) {
-        const int d = dest[i];
-        if (d >= 0 && d != cr + i)
-          for (int l = tid; l < we; l += NT) C[d * we + l] = C[(cr + i) * we + l];
-      }
-      cr = sh_cnt;
-      next += nb;
+
+  // reflector of column c from (alpha = R[c][c], the group's chunk registers)
+  auto reflect = [&](const double* c, int col, int slot) {
+    double x2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) x2 += c[q] * c[q];
+    for (int off = 1; off < TPC; off <<= 1) x2 += __shfl_xor(x2, off, 64);
+    const int pd = pk(col, col, we);
+    const double alpha = R[pd];
+    double tau = 0.0, scal = 0.0;
+    if (x2 != 0.0) {
+      const double nrm = sqrt(alpha * alpha + x2);
+      const double beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+      if (sub == 0) R[pd] = beta;
     }
-    if (cr == 0) break;
-    mtot += cr;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) vb[slot][sub + TPC * q] = c[q];
+    if (sub == 0) {
+      tb[slot][0] = tau;
+      tb[slot][1] = scal;
+    }
+  };
+
+  double c[RPT];
+  for (int r0 = 0; r0 < m; r0 += CH) {
+    const int cr = min(CH, m - r0);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      const int i = sub + TPC * q;
+      c[q] = (i < cr && l < we) ? tk.a[(int64_t)(r0 + i) * tk.lda + l] : 0.0;
+    }
+    __syncthreads();  // R of the previous chunk complete, both slots free
+    if (l == 0) reflect(c, 0, 0);
     __syncthreads();
     for (int j = 0; j < we; ++j) {
-      if (tid < 64) {
-        double x2 = 0.0;
-        for (int i = tid; i < cr; i += 64) {
-          double x = C[i * we + j];
-          x2 += x * x;
-        }
-        for (int off = 32; off > 0; off >>= 1) x2 += __shfl_xor(x2, off, 64);
-        if (tid == 0) {
-          const double alpha = R[pk(j, j, we)];
-          if (x2 == 0.0) {
-            sh_tau = 0.0;
-            sh_scal = 0.0;
-          } else {
-            const double nrm = sqrt(alpha * alpha + x2);
-            const double beta = alpha >= 0.0 ? -nrm : nrm;
-            sh_tau = (beta - alpha) / beta;
-            sh_scal = 1.0 / (alpha - beta);
-            R[pk(j, j, we)] = beta;
-          }
-        }
-      }
-      __syncthreads();
-      const double tau = sh_tau, scal = sh_scal;
-      if (tau != 0.0) {
-        for (int l0 = j + 1; l0 < we; l0 += CPP) {
-          const int l = l0 + cgrp;
+      const int b = j & 1;
+      if (l > j && l < we) {
+        const double tau = tb[b][0], scal = tb[b][1];
+        if (tau != 0.0) {
           double dot = 0.0;
-          if (l < we)
-            for (int i = sub; i < cr; i += TPC) dot += C[i * we + j] * C[i * we + l];
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) dot += vb[b][sub + TPC * q] * c[q];
           for (int off = 1; off < TPC; off <<= 1) dot += __shfl_xor(dot, off, 64);
-          if (l < we) {
-            const int p = pk(j, l, we);
-            const double full = R[p] + scal * dot;
-            const double f = tau * scal * full;
-            for (int i = sub; i < cr; i += TPC) C[i * we + l] -= f * C[i * we + j];
-            if (sub == 0) R[p] -= tau * full;
-          }
+          const int p = pk(j, l, we);
+          const double full = R[p] + scal * dot;
+          const double f = tau * scal * full;
+#pragma unroll
+          for (int q = 0; q < RPT; ++q) c[q] -= f * vb[b][sub + TPC * q];
+          if (sub == 0) R[p] -= tau * full;
         }
+        if (l == j + 1) reflect(c, j + 1, b ^ 1);
       }
       __syncthreads();
     }
-    if (next >= m) break;
   }
   __syncthreads();
   const int w = tk.w;
-  for (int e = tid; e < w * w; e += NT) {
-    int i = e / w, l = e - i * w;
-    double v = (i < we && l < we && l >= i) ? R[pk(i, l, we)] : 0.0;
-    if (tk.trans_r) tk.r[(int64_t)l * tk.ldr + i] = v;
-    else tk.r[(int64_t)i * tk.ldr + l] = v;
+  if (tk.part >= 0) {  // compact output: rows [0, we) at row offset part * we
+    double* out = tk.r + (int64_t)tk.part * we * tk.ldr;
+    for (int e = tid; e < we * w; e += NT) {
+      int i = e / w, ll = e - i * w;
+      out[(int64_t)i * tk.ldr + ll] = (ll < we && ll >= i) ? R[pk(i, ll, we)] : 0.0;
+    }
+  } else {
+    for (int e = tid; e < w * w; e += NT) {
+      int i = e / w, ll = e - i * w;
+      double v = (i < we && ll < we && ll >= i) ? R[pk(i, ll, we)] : 0.0;
+      if (tk.trans_r) tk.r[(int64_t)ll * tk.ldr + i] = v;
+      else tk.r[(int64_t)i * tk.ldr + ll] = v;
+    }
   }
   if (tk.stat && tid == 0) {
-    tk.stat[0] = mtot;
+    tk.stat[0] = m;
     tk.stat[1] = we;
   }
 }
@@ -280,9 +275,9 @@ int size_classes(int wmax) { return wmax > 64 ? 3 : (wmax > 32 ? 2 : 1); }
 void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s) {
   if (ntasks <= 0) return;
   // each workgroup exits unless its task's effective width falls into the class
-  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 64, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
-  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
-  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 64, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
+  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
+  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
+  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 64);
 }
 
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
@@ -741,8 +736,8 @@ void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStrea
 
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
-      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64, 64>",
-      "qr_kernel<64, 64, 128>",    "qr_kernel<128, 64, 512>",    "svd_kernel<32, 64>",
+      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64>",
+      "qr_kernel<64, 128>",        "qr_kernel<128, 256>",    "svd_kernel<32, 64>",
       "svd_kernel<64, 128>",       "svd_kernel<128, 256>",       "chol_kernel",
       "fill_kernel",               "convert kernels",            "ref_kernel"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "";

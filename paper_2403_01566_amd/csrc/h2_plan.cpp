@@ -89,6 +89,8 @@ struct PQr {
   DRef<double> a, r;
   int lda, ldr, m, w, trans_r;
   DRef<int> w_dev, w_dev2;
+  DRef<int> m_dev;
+  int mul_we = 0, part = -1;
 };
 struct PSvd {
   DRef<double> a, u, sigma;
@@ -236,13 +238,19 @@ struct QrSplit {
       s2 = &B.step(SK_QR);
       s2->wmax = s1->wmax;
     }
+    // stage 1: the R factor of every row block, stacked compactly (w_eff rows
+    // each); stage 2: the R factor of the stack (parts * w_eff rows)
     const int parts = (m + kRows - 1) / kRows;
     DRef<double> stack = B.wd((int64_t)parts * w * w);
     for (int p = 0; p < parts; ++p) {
       const int r0 = p * kRows, rows = std::min(kRows, m - r0);
-      s1->qr.push_back({a + (int64_t)r0 * lda, stack + (int64_t)p * w * w, lda, w, rows, w, 0, w1, w2});
+      PQr q{a + (int64_t)r0 * lda, stack, lda, w, rows, w, 0, w1, w2};
+      q.part = p;
+      s1->qr.push_back(q);
     }
-    s2->qr.push_back({stack, r, w, ldr, parts * w, w, trans_r, w1, w2});
+    PQr q{stack, r, w, ldr, parts * w, w, trans_r, w1, w2};
+    q.mul_we = parts;
+    s2->qr.push_back(q);
   }
 };
 
@@ -1646,8 +1654,9 @@ static void finalize(Plan& P, double eps) {
         for (size_t i = 0; i < st.qr.size(); ++i) {
           const PQr& q = st.qr[i];
           int* stat = P.bufi.as<int>() + st.stat_off + 2 * i;
-          h2k::QrTask t{res(q.a, P), res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), stat, q.lda, q.ldr, q.m, q.w,
-                        q.trans_r, 0};
+          h2k::QrTask t{res(q.a, P),  res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), res(q.m_dev, P), stat,
+                        q.lda,        q.ldr,       q.m,               q.w,                q.trans_r,         q.mul_we,
+                        q.part};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.qr.size();

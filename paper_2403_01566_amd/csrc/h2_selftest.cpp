@@ -99,7 +99,7 @@ double qr_test(hipStream_t s, int m, int w) {
   double* da = up(A, keep);
   std::vector<double> R0((size_t)w * w, 0.0);
   double* dr = up(R0, keep);
-  h2k::QrTask t{da, dr, nullptr, nullptr, nullptr, w, w, m, w, 0, 0};
+  h2k::QrTask t{da, dr, nullptr, nullptr, nullptr, nullptr, w, w, m, w, 0, 0, -1};
   auto* dt = up(std::vector<h2k::QrTask>{t}, keep);
   h2k::launch_qr(dt, 1, w, s);
   H2_HIP(hipStreamSynchronize(s));
@@ -123,6 +123,48 @@ double qr_test(hipStream_t s, int m, int w) {
 // with an absolute Frobenius threshold tau; checked are the orthonormality of
 // the kept basis, the projection error ||A - U U^T A||_F <= tau and that the
 // rank is no more than the one of the exact SVD at tau / 2.
+// Two-stage form: the R factors of the two row halves of A, restricted to the
+// first we < w columns (device-side width), stacked compactly (part), then the
+// R factor of the stack (mul_we).  Checked: R^T R = A_we^T A_we and zeros
+// beyond we.
+double qr_split_test(hipStream_t s, int m, int w, int we) {
+  std::vector<void*> keep;
+  Lcg g(7 + m + w + we);
+  std::vector<double> A((size_t)m * w);
+  for (auto& x : A) x = g.next();
+  double* da = up(A, keep);
+  std::vector<double> S0((size_t)2 * w * w, 7.0), R0((size_t)w * w, 7.0);
+  double* dst = up(S0, keep);
+  double* dr = up(R0, keep);
+  int* dwe = up(std::vector<int>{we}, keep);
+  const int h = m / 2;
+  h2k::QrTask t1{da, dst, dwe, nullptr, nullptr, nullptr, w, w, h, w, 0, 0, 0};
+  h2k::QrTask t2{da + (size_t)h * w, dst, dwe, nullptr, nullptr, nullptr, w, w, m - h, w, 0, 0, 1};
+  h2k::QrTask t3{dst, dr, dwe, nullptr, nullptr, nullptr, w, w, 2 * w, w, 0, 2, -1};
+  auto* d1 = up(std::vector<h2k::QrTask>{t1, t2}, keep);
+  auto* d3 = up(std::vector<h2k::QrTask>{t3}, keep);
+  h2k::launch_qr(d1, 2, w, s);
+  h2k::launch_qr(d3, 1, w, s);
+  H2_HIP(hipStreamSynchronize(s));
+  auto R = down(dr, R0.size());
+  double err = 0, ref = 0;
+  for (int i = 0; i < w; ++i)
+    for (int j = 0; j < w; ++j) {
+      if (i >= we || j >= we) {
+        if (R[(size_t)i * w + j] != 0.0) err = 1.0;
+        continue;
+      }
+      double g1 = 0, g2 = 0;
+      for (int r = 0; r < m; ++r) g1 += A[(size_t)r * w + i] * A[(size_t)r * w + j];
+      for (int r = 0; r < w; ++r) g2 += R[(size_t)r * w + i] * R[(size_t)r * w + j];
+      err = std::max(err, std::fabs(g1 - g2));
+      ref = std::max(ref, std::fabs(g1));
+      if (i > j && R[(size_t)i * w + j] != 0.0) err = 1.0;
+    }
+  for (void* p : keep) (void)hipFree(p);
+  return err / ref;
+}
+
 double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0) {
   std::vector<void*> keep;
   Lcg g(7 + w);
@@ -273,6 +315,8 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(qr_test(s, 301, 20));
   e.push_back(qr_test(s, 97, 64));
   e.push_back(qr_test(s, 150, 128));
+  e.push_back(qr_split_test(s, 333, 100, 77));
+  e.push_back(qr_split_test(s, 130, 48, 40));
   e.push_back(svd_test(s, 24, overflow));
   e.push_back(svd_test(s, 64, overflow));
   e.push_back(svd_test(s, 128, overflow));
