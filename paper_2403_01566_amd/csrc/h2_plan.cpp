@@ -24,9 +24,11 @@
 //
 // Coarsening (Section 5.1): below each admissible result leaf the exact
 // blocks are agglomerated pairwise along the induced tree; every merge is a
-// truncated SVD (QR of the factors, one-sided Jacobi on the small core) with
-// relative tolerance delta_c / (number of merges of that block), so the
-// accumulated error stays below delta_c ||G_b|| (Remark 13).
+// truncated SVD (QR of the factors, pivoted-QR rank reveal and one-sided
+// Jacobi on the small core) whose dropped tail has Frobenius norm at most
+// tau_b = delta_c nu_b / sum_h sqrt(n_h) (n_h merges at height h, nu_b a lower
+// bound of ||G_b||).  Merges of one height act on disjoint sub-blocks, so the
+// accumulated error stays below delta_c ||G_b|| (the bound of Remark 13).
 //
 // Adaptive bases (Sections 5.2, 5.3): row basis bottom-up with weights
 // omega = theta^{(level s - level t)/2} ||G_b||, leaf SVD of the weighted
