@@ -287,32 +287,55 @@ void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // One-sided Jacobi SVD (left vectors).
 // ---------------------------------------------------------------------------
-// block-wide reductions over NT threads (result in every thread)
+// Sum over the workgroup (result in every thread): wave shuffles, then one
+// exchange of the per-wave sums through LDS.
 template <int NT>
 __device__ inline double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
   __syncthreads();
-  red[tid] = v;
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int off = NT / 2; off > 0; off >>= 1) {
-    if (tid < off) red[tid] += red[tid + off];
-    __syncthreads();
-  }
-  return red[0];
+  double t = 0.0;
+  for (int w = 0; w < NT / 64; ++w) t += red[w];
+  return t;
 }
 
+// Sum over the G consecutive lanes of a group (G a power of two <= 64).
+template <int G>
+__device__ inline double group_sum(double v) {
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Truncated SVD (left singular vectors) of a small matrix A (rows x cols).
+//
+// With an absolute threshold tau (coarsening and basis truncations) the rank
+// is revealed first by a column-pivoted Householder QR of X = A^T, stopped
+// once the remaining columns have Frobenius norm <= tau/8.  Column l of X
+// (row l of A) lives in the registers of the TPC consecutive lanes of group l
+// (lane `sub` holds rows sub, sub + TPC, ...), so pivoting moves no data: a
+// pivoted column is only marked done.  Each step costs two barriers (the
+// pivot reduction and the publication of the reflector).  The r x cols factor
+// R, transposed to rows x r, then goes to one-sided Jacobi at threshold
+// 3 tau / 4; the projection error stays below tau (tau/8 + 3 tau/4).
+// Without such a threshold A itself goes to the Jacobi.
+//
+// Jacobi: M[c * LD + r] holds column c (contiguous rows); the odd stride keeps
+// lanes that read different columns on different LDS banks.  Round-robin
+// pairs, G lanes per pair, one barrier per round.
 template <int WMAX, int NT>
 __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo) {
-  // M[c * LD + r] holds column c (contiguous rows); the odd stride keeps
-  // lanes that read different columns on different LDS banks
   constexpr int LD = WMAX + 1;
-  constexpr int STAGE = (WMAX * WMAX + NT - 1) / NT;
+  constexpr int TPC = NT / WMAX;  // lanes per column of A^T in the rank reveal
+  constexpr int RPL = WMAX / TPC; // rows per lane
+  constexpr int NW = NT / 64;
+  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && NT % 64 == 0, "launch shape");
   __shared__ double M[WMAX * LD];
   __shared__ double nrm[WMAX];
   __shared__ int order[WMAX];
-  __shared__ int perm[WMAX];
-  __shared__ double red[NT];
-  __shared__ int redi[NT];
+  __shared__ double vb[WMAX];
+  __shared__ double red[NW], wmx[NW];
+  __shared__ int widx[NW];
   __shared__ int sh_rot;
   __shared__ double sh_tau, sh_scal;
   const SvdTask tk = tasks[blockIdx.x];
@@ -322,11 +345,15 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   int cols = sq ? we : tk.cols;
   const int wcls = rows > cols ? rows : cols;
   if (wcls <= wlo || wcls > WMAX) return;  // another launch handles this size class
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double ref = tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0;
   const bool qr = tk.qrcp && tk.tol_rel == 0.0;
-  double ss = 0.0;
+  const int cols_in = cols;
+  int sweeps = 0;
+  double jthr_scale = 1.0;
+  bool empty;
   if (!qr) {
+    double ss = 0.0;
     for (int e = tid; e < cols * WMAX; e += NT) {
       int c = e / WMAX, r = e - c * WMAX;
       double v = 0.0;
@@ -334,132 +361,136 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       M[c * LD + r] = v;
       ss += v * v;
     }
+    const double fro = sqrt(block_sum<NT>(ss, red));
+    // every singular value is below the Frobenius norm: nothing survives an
+    // absolute threshold above it
+    empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
   } else {
-    // X = A^T (cols x rows) in column layout: column l of X is row l of A
-    for (int e = tid; e < rows * WMAX; e += NT) {
-      int l = e / WMAX, i = e - l * WMAX;
-      double v = 0.0;
-      if (i < cols) v = tk.trans_a ? tk.a[(int64_t)i * tk.lda + l] : tk.a[(int64_t)l * tk.lda + i];
-      M[l * LD + i] = v;
-      ss += v * v;
-    }
-  }
-  const double fro = sqrt(block_sum<NT>(ss, red));
-  // every singular value is below the Frobenius norm: nothing survives an
-  // absolute threshold above it
-  const bool empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
-  double jthr_scale = 1.0;
-  const int cols_in = cols;
-  int sweeps = 0;
-  if (!empty && qr) {
-    // column-pivoted Householder QR of X (ni x nl), stopped when the remaining
-    // columns have Frobenius norm <= tau/8
     const int nl = rows, ni = cols;
-    const double tq = 0.125 * (tk.tol_abs + ref);
-    for (int l = tid; l < nl; l += NT) {
+    const int l = tid / TPC, sub = tid % TPC;
+    double x[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const int i = sub + TPC * q;
       double v = 0.0;
-      for (int i = 0; i < ni; ++i) v += M[l * LD + i] * M[l * LD + i];
-      nrm[l] = v;
-      perm[l] = l;
+      if (l < nl && i < ni) v = tk.trans_a ? tk.a[(int64_t)i * tk.lda + l] : tk.a[(int64_t)l * tk.lda + i];
+      x[q] = v;
     }
-    int r = 0;
-    const int jmax = nl < ni ? nl : ni;
-    for (int j = 0; j < jmax; ++j) {
-      // remaining Frobenius norm and pivot
-      double part = 0.0, best = -1.0;
-      int bi = j;
-      for (int l = j + tid; l < nl; l += NT) {
-        part += nrm[l];
-        if (nrm[l] > best) { best = nrm[l]; bi = l; }
-      }
-      __syncthreads();
-      red[tid] = part;
-      redi[tid] = bi;
-      __syncthreads();
-      // reduce sum and argmax (ties: lower index)
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (tid < off) {
-          red[tid] += red[tid + off];
-          const int a = redi[tid], b = redi[tid + off];
-          const double va = (a < nl) ? nrm[a] : -1.0, vb = (b < nl) ? nrm[b] : -1.0;
-          if (vb > va || (vb == va && b < a)) redi[tid] = b;
+    double ss = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) ss += x[q] * x[q];
+    const double cn0 = group_sum<TPC>(ss);  // squared norm of this column
+    const double fro = sqrt(block_sum<NT>(ss, red));
+    empty = fro <= tk.tol_abs + ref;
+    if (!empty) {
+      const double tq = 0.125 * (tk.tol_abs + ref);
+      double cn = cn0;   // squared norm of the rows below the current step
+      int done = -1;     // step at which this column was the pivot
+      int r = 0;
+      const int jmax = nl < ni ? nl : ni;
+      for (int j = 0; j < jmax; ++j) {
+        // remaining Frobenius norm and pivot (largest column, lowest index on ties)
+        const bool act = l < nl && done < 0;
+        double v = act ? cn : -1.0, sv = (act && sub == 0) ? cn : 0.0;
+        int id = act ? l : WMAX;
+        for (int off = 1; off < 64; off <<= 1) {
+          sv += __shfl_xor(sv, off, 64);
+          const double ov = __shfl_xor(v, off, 64);
+          const int oi = __shfl_xor(id, off, 64);
+          if (ov > v || (ov == v && oi < id)) {
+            v = ov;
+            id = oi;
+          }
+        }
+        if (lane == 0) {
+          red[wv] = sv;
+          wmx[wv] = v;
+          widx[wv] = id;
         }
         __syncthreads();
-      }
-      if (red[0] <= tq * tq) break;
-      const int p = redi[0];
-      r = j + 1;
-      if (p != j) {  // swap columns j and p
-        for (int i = tid; i < ni; i += NT) {
-          double t = M[j * LD + i];
-          M[j * LD + i] = M[p * LD + i];
-          M[p * LD + i] = t;
+        double tot = 0.0, bv = -1.0;
+        int p = WMAX;
+        for (int w = 0; w < NW; ++w) {
+          tot += red[w];
+          if (wmx[w] > bv || (wmx[w] == bv && widx[w] < p)) {
+            bv = wmx[w];
+            p = widx[w];
+          }
+        }
+        if (tot <= tq * tq) break;
+        r = j + 1;
+        if (l == p) {  // reflector of the pivot column on rows >= j
+          double xj = 0.0, x2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) {
+            const int i = sub + TPC * q;
+            if (i == j) xj = x[q];
+            if (i > j) x2 += x[q] * x[q];
+          }
+          xj = group_sum<TPC>(xj);
+          x2 = group_sum<TPC>(x2);
+          double tau = 0.0, scal = 0.0;
+          if (x2 != 0.0) {
+            const double nn = sqrt(xj * xj + x2);
+            const double beta = xj >= 0.0 ? -nn : nn;
+            tau = (beta - xj) / beta;
+            scal = 1.0 / (xj - beta);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+              if (sub + TPC * q == j) x[q] = beta;
+          }
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) {
+            const int i = sub + TPC * q;
+            vb[i] = i > j ? x[q] : 0.0;
+          }
+          if (sub == 0) {
+            sh_tau = tau;
+            sh_scal = scal;
+          }
+          done = j;
         }
         __syncthreads();
-        if (tid == 0) {
-          double t = nrm[j]; nrm[j] = nrm[p]; nrm[p] = t;
-          int q = perm[j]; perm[j] = perm[p]; perm[p] = q;
-        }
-      }
-      __syncthreads();
-      // Householder reflector of column j, rows j..w-1
-      double x2p = 0.0;
-      for (int i = j + 1 + tid; i < ni; i += NT) x2p += M[j * LD + i] * M[j * LD + i];
-      const double x2 = block_sum<NT>(x2p, red);
-      if (tid == 0) {
-        const double alpha = M[j * LD + j];
-        if (x2 == 0.0) {
-          sh_tau = 0.0;
-          sh_scal = 0.0;
-        } else {
-          const double nn = sqrt(alpha * alpha + x2);
-          const double beta = alpha >= 0.0 ? -nn : nn;
-          sh_tau = (beta - alpha) / beta;
-          sh_scal = 1.0 / (alpha - beta);
-          M[j * LD + j] = beta;
-        }
-      }
-      __syncthreads();
-      const double tau = sh_tau, scal = sh_scal;
-      // apply to the remaining columns (one column per thread) and update norms
-      for (int l = j + 1 + tid; l < nl; l += NT) {
-        if (tau != 0.0) {
-          double d = M[l * LD + j];
-          for (int i = j + 1; i < ni; ++i) d += scal * M[j * LD + i] * M[l * LD + i];
-          M[l * LD + j] -= tau * d;
-          const double f = tau * d * scal;
-          for (int i = j + 1; i < ni; ++i) M[l * LD + i] -= f * M[j * LD + i];
-        }
-        double v = 0.0;
-        for (int i = j + 1; i < ni; ++i) v += M[l * LD + i] * M[l * LD + i];
-        nrm[l] = v;
-      }
-      __syncthreads();
-    }
-    __syncthreads();
-    // T = rows 0..r-1 of the factor, columns back in original order; the
-    // Jacobi matrix is T^T (nl x r): column i, row perm[l] = T[i][l]
-    double stage[STAGE];
+        if (l < nl && done < 0) {  // apply to the remaining columns
+          const double tau = sh_tau, scal = sh_scal;
+          if (tau != 0.0) {
+            double xj = 0.0, dot = 0.0;
 #pragma unroll
-    for (int q = 0; q < STAGE; ++q) {
-      const int e = tid + q * NT;
-      stage[q] = 0.0;
-      if (e < r * nl) {
-        const int i = e / nl, l = e - i * nl;
-        stage[q] = (l >= i) ? M[l * LD + i] : 0.0;
-      }
-    }
-    __syncthreads();
+            for (int q = 0; q < RPL; ++q) {
+              const int i = sub + TPC * q;
+              if (i == j) xj = x[q];
+              dot += vb[i] * x[q];
+            }
+            xj = group_sum<TPC>(xj);
+            dot = group_sum<TPC>(dot);
+            const double full = xj + scal * dot;
+            const double f = tau * scal * full;
 #pragma unroll
-    for (int q = 0; q < STAGE; ++q) {
-      const int e = tid + q * NT;
-      if (e < r * nl) {
-        const int i = e / nl, l = e - i * nl;
-        M[i * LD + perm[l]] = stage[q];
+            for (int q = 0; q < RPL; ++q) {
+              const int i = sub + TPC * q;
+              x[q] -= f * vb[i];
+              if (i == j) x[q] -= tau * full;
+            }
+          }
+          double c2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q)
+            if (sub + TPC * q > j) c2 += x[q] * x[q];
+          cn = group_sum<TPC>(c2);
+        }
       }
+      // Jacobi matrix (nl x r): column i, row l = R[i][l]; a pivoted column
+      // keeps its reflector below its step, which is not part of R
+      if (l < nl) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int i = sub + TPC * q;
+          if (i < r) M[i * LD + l] = (done < 0 || i <= done) ? x[q] : 0.0;
+        }
+      }
+      cols = r;
+      jthr_scale = 0.75;
     }
-    cols = r;
-    jthr_scale = 0.75;
     __syncthreads();
   }
   if (!empty) {
@@ -580,7 +611,7 @@ void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, 
   if (ntasks <= 0) return;
   if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
   if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, overflow, 32);
-  if (cls == 2) hipLaunchKernelGGL((svd_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 64);
+  if (cls == 2) hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
 }
 
 void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s) {
@@ -738,7 +769,7 @@ const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
       "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64>",
       "qr_kernel<64, 128>",        "qr_kernel<128, 256>",    "svd_kernel<32, 64>",
-      "svd_kernel<64, 128>",       "svd_kernel<128, 256>",       "chol_kernel",
+      "svd_kernel<64, 128>",       "svd_kernel<128, 512>",       "chol_kernel",
       "fill_kernel",               "convert kernels",            "ref_kernel"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
