@@ -49,12 +49,24 @@ constexpr int GBM = 64, GBN = 64, GBK = 16;
 //   B operand: lane l supplies B[k0 + l / 16][l % 16]
 //   D: lane l, register v holds D[row][l % 16] with row = 4 (l / 16) + v for
 //      f32 and row = l / 16 + 4 v for f64 (Mfma<T>::row).
+//
+// One workgroup (4 waves, each a 32 x 32 quarter) per 64 x 64 output tile.
+// The K dimension of all items of the task is walked as one sequence of
+// 16-wide slices: while the MFMAs consume slice s from one LDS buffer, the
+// global loads of slice s + 1 are in flight into registers and then land in
+// the other buffer, so each slice costs one barrier.  A wave whose quarter
+// lies outside the task's (device-side) size skips its MFMAs.
+template <typename T>
+struct GemmSlice {
+  T a[4], b[4];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
                                                    const GemmTask<T>* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles) {
-  __shared__ T As[GBK][GBM + 4];
-  __shared__ T Bs[GBK][GBN + 4];
+  __shared__ T As[2][GBK][GBM + 4];
+  __shared__ T Bs[2][GBK][GBN + 4];
   typedef typename Mfma<T>::acc acc_t;
   const GemmTile tl = tiles[blockIdx.x];
   GemmTask<T> tk = tasks[tl.task];
@@ -66,13 +78,20 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
   const int lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
   const int m0 = tl.m0, n0 = tl.n0;
+  const bool active = m0 + wm * 32 < tk.m && n0 + wn * 32 < tk.n;
   acc_t acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
 
+  // copies (IT_COPY items) go straight into the accumulators
+  int nmm = 0;  // product items
   for (int it = 0; it < tk.nitem; ++it) {
     const GemmItem<T> item = items[tk.item0 + it];
+    if (!(item.flags & IT_COPY)) {
+      ++nmm;
+      continue;
+    }
     double alpha = item.alpha;
     if (item.scale) {
       double s = *item.scale;
@@ -80,24 +99,45 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
       else alpha *= s;
     }
     const T al = T(alpha);
-    const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
-    if (item.flags & IT_COPY) {
-      for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
-          for (int v = 0; v < 4; ++v) {
-            int row = m0 + wm * 32 + a * 16 + Mfma<T>::row(lane, v);
-            int col = n0 + wn * 32 + b * 16 + (lane & 15);
-            if (row < tk.m && col < tk.n) {
-              T x = ta ? item.a[(int64_t)col * item.lda + row] : item.a[(int64_t)row * item.lda + col];
-              acc[a][b][v] += al * x;
-            }
+    const bool ta = item.flags & IT_TRANS_A;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int v = 0; v < 4; ++v) {
+          int row = m0 + wm * 32 + a * 16 + Mfma<T>::row(lane, v);
+          int col = n0 + wn * 32 + b * 16 + (lane & 15);
+          if (row < tk.m && col < tk.n) {
+            T x = ta ? item.a[(int64_t)col * item.lda + row] : item.a[(int64_t)row * item.lda + col];
+            acc[a][b][v] += al * x;
           }
-      continue;
-    }
-    const int K = item.k;
-    for (int k0 = 0; k0 < K; k0 += GBK) {
-      __syncthreads();
-      // A tile: op(A)[m0+i][k0+kk], i < 64, kk < 16
+        }
+  }
+
+  if (nmm > 0) {
+    // slice cursor over the product items
+    int it = -1, k0 = 0, kend = 0;
+    GemmItem<T> item{};
+    T al = T(0);
+    auto advance = [&]() -> bool {  // move to the next slice; false at the end
+      k0 += GBK;
+      while (k0 >= kend) {
+        ++it;
+        while (it < tk.nitem && (items[tk.item0 + it].flags & IT_COPY)) ++it;
+        if (it >= tk.nitem) return false;
+        item = items[tk.item0 + it];
+        double alpha = item.alpha;
+        if (item.scale) {
+          double s = *item.scale;
+          if (item.flags & IT_SCALE_INV) alpha = (s != 0.0) ? alpha / s : 0.0;
+          else alpha *= s;
+        }
+        al = T(alpha);
+        k0 = 0;
+        kend = item.k;
+      }
+      return true;
+    };
+    auto load = [&](GemmSlice<T>& g) {
+      const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
@@ -105,11 +145,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
         if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
         int gi = m0 + i, gk = k0 + kk;
         T x = T(0);
-        if (gi < tk.m && gk < K)
+        if (gi < tk.m && gk < kend)
           x = ta ? item.a[(int64_t)gk * item.lda + gi] : item.a[(int64_t)gi * item.lda + gk];
-        As[kk][i] = al * x;
+        g.a[q] = al * x;
       }
-      // B tile: op(B)[k0+kk][n0+j]
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
@@ -117,19 +156,53 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
         if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
         int gj = n0 + j, gk = k0 + kk;
         T x = T(0);
-        if (gj < tk.n && gk < K)
+        if (gj < tk.n && gk < kend)
           x = tb ? item.b[(int64_t)gj * item.ldb + gk] : item.b[(int64_t)gk * item.ldb + gj];
-        Bs[kk][j] = x;
+        g.b[q] = x;
       }
-      __syncthreads();
+    };
+    auto store = [&](const GemmSlice<T>& g, int buf) {
+      const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
 #pragma unroll
-      for (int kk = 0; kk < GBK; kk += 4) {
-        T av[2], bv[2];
-        for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][wm * 32 + a * 16 + (lane & 15)];
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
-        for (int a = 0; a < 2; ++a)
-          for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+      for (int q = 0; q < 4; ++q) {
+        int e = tid + 256 * q;
+        int i, kk;
+        if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
+        As[buf][kk][i] = g.a[q];
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int e = tid + 256 * q;
+        int j, kk;
+        if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
+        Bs[buf][kk][j] = g.b[q];
+      }
+    };
+    k0 = -GBK;
+    kend = 0;
+    advance();
+    GemmSlice<T> g;
+    load(g);
+    store(g, 0);
+    __syncthreads();
+    int buf = 0;
+    for (;;) {
+      const bool more = advance();
+      if (more) load(g);  // next slice in flight during the MFMAs below
+      if (active) {
+#pragma unroll
+        for (int kk = 0; kk < GBK; kk += 4) {
+          T av[2], bv[2];
+          for (int a = 0; a < 2; ++a) av[a] = As[buf][kk + (lane >> 4)][wm * 32 + a * 16 + (lane & 15)];
+          for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk + (lane >> 4)][wn * 32 + b * 16 + (lane & 15)];
+          for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+        }
+      }
+      if (!more) break;
+      store(g, buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
     }
   }
   for (int a = 0; a < 2; ++a)
