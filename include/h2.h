@@ -109,7 +109,7 @@ typedef struct {
 } h2_mul_options;
 
 /* Number of kernels in the per-kernel statistics; h2_kernel_name(i) names kernel i. */
-#define H2_NKERNEL 12
+#define H2_NKERNEL 13
 
 typedef struct {
   double t_phase[8];   /* device ms: 0 operand prep, 1 exact product, 2 leaf assembly,

@@ -27,15 +27,16 @@ struct GemmItem {
 };
 
 // One output matrix C (m x n, row-major, ldc): C = (beta ? C : 0) + sum of items.
-// Optional device ints: m_dev / n_dev lower m / n to min(m, *m_dev) etc. and
-// coff_dev shifts the output by *coff_dev columns (sizes known only on the
-// device, e.g. truncation ranks).
+// Optional device ints: m_dev / n_dev lower m / n to min(m, *m_dev) etc.,
+// coff_dev shifts the output by *coff_dev columns and roff_dev by *roff_dev
+// rows (sizes known only on the device, e.g. truncation ranks).
 template <typename T>
 struct GemmTask {
   T* c;
   const int* m_dev;
   const int* n_dev;
   const int* coff_dev;
+  const int* roff_dev;
   int ldc, m, n, item0, nitem, beta;
 };
 
@@ -50,8 +51,10 @@ struct GemmTile {
 // w x w with zeros beyond w_eff.  Rows: the first m, lowered to *m_dev when
 // m_dev is set and to mul_we * w_eff when mul_we > 0.  part >= 0 writes the
 // w_eff x w upper part only, at row offset part * w_eff (row-major, ldr; for
-// stacking the R factors of row blocks compactly).  Optional stat (2 ints):
-// the number of rows factored and w_eff.
+// stacking the R factors of row blocks compactly).  With m_dev the row count
+// is min(m, *m_dev - m_off) (a row block of a matrix whose height is known
+// on the device).  Optional stat (2 ints): the number of rows factored and
+// w_eff.
 struct QrTask {
   const double* a;
   double* r;
@@ -59,7 +62,7 @@ struct QrTask {
   const int* w_dev2;
   const int* m_dev;
   int* stat;
-  int lda, ldr, m, w, trans_r, mul_we, part;
+  int lda, ldr, m, w, trans_r, mul_we, part, m_off;
 };
 
 // One-sided Jacobi on a small matrix A (rows x cols, row-major, lda), rotating
@@ -121,6 +124,14 @@ struct CholTask {
   int ldg, ldt, ldr, w;
 };
 
+// Exclusive prefix sums of device ints: offs[i] = sum_{j<i} *src[first + j],
+// *total = the full sum.
+struct ScanTask {
+  int first, count;
+  int* offs;
+  int* total;
+};
+
 struct FillTask {
   void* p;
   int ld, m, n, pad;
@@ -144,12 +155,13 @@ void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, 
 // instantiations a profiler shows).
 enum KernelId {
   K_GEMM_F64, K_GEMM_F32, K_QR32, K_QR64, K_QR128, K_SVD32, K_SVD64, K_SVD128,
-  K_CHOL, K_FILL, K_CVT, K_REF, K_COUNT
+  K_CHOL, K_FILL, K_CVT, K_REF, K_SCAN, K_COUNT
 };
 const char* kernel_name(int id);
 void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s);
 void launch_ref(const RefTask* tasks, const RefMat* mats, int ntasks, hipStream_t s);
 void launch_fill(const FillTask* tasks, int ntasks, hipStream_t s);
+void launch_scan(const ScanTask* tasks, const int* const* src, int ntasks, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
 

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
   if (tk.m_dev) tk.m = min(tk.m, *tk.m_dev);
   if (tk.n_dev) tk.n = min(tk.n, *tk.n_dev);
   if (tk.coff_dev) tk.c += *tk.coff_dev;
+  if (tk.roff_dev) tk.c += (int64_t)*tk.roff_dev * tk.ldc;
   if (tl.m0 >= tk.m || tl.n0 >= tk.n) return;  // whole tile outside the device-side size
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -260,8 +261,9 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
   const int we = eff_width(tk.w, tk.w_dev, tk.w_dev2);
   if (we <= wlo || we > WMAX) return;  // another launch handles this width class
   int m = tk.m;
-  if (tk.m_dev) m = min(m, *tk.m_dev);
+  if (tk.m_dev) m = min(m, *tk.m_dev - tk.m_off);
   if (tk.mul_we > 0) m = min(m, tk.mul_we * we);
+  m = max(m, 0);
   const int tid = threadIdx.x, sub = tid % TPC, l = tid / TPC;
   for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
 
@@ -838,12 +840,28 @@ void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStrea
   if (n > 0) hipLaunchKernelGGL(cvt_f2d, dim3(1024), dim3(256), 0, s, in, out, n);
 }
 
+__global__ void scan_kernel(const ScanTask* __restrict__ tasks, const int* const* __restrict__ src, int ntasks) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntasks) return;
+  const ScanTask tk = tasks[t];
+  int acc = 0;
+  for (int i = 0; i < tk.count; ++i) {
+    tk.offs[i] = acc;
+    acc += *src[tk.first + i];
+  }
+  *tk.total = acc;
+}
+void launch_scan(const ScanTask* tasks, const int* const* src, int ntasks, hipStream_t s) {
+  if (ntasks > 0) hipLaunchKernelGGL(scan_kernel, dim3((ntasks + 63) / 64), dim3(64), 0, s, tasks, src, ntasks);
+}
+
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
       "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64>",
       "qr_kernel<64, 128>",        "qr_kernel<128, 256>",    "svd_kernel<32, 64>",
       "svd_kernel<64, 128>",       "svd_kernel<128, 512>",       "chol_kernel",
-      "fill_kernel",               "convert kernels",            "ref_kernel"};
+      "fill_kernel",               "convert kernels",            "ref_kernel",
+      "scan_kernel"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "";
 }
 

@@ -85,14 +85,14 @@ template <typename T>
 struct PTask {
   DRef<T> c;
   int ldc, m, n, item0, nitem, beta;
-  DRef<int> m_dev, n_dev, coff_dev;
+  DRef<int> m_dev, n_dev, coff_dev, roff_dev;
 };
 struct PQr {
   DRef<double> a, r;
   int lda, ldr, m, w, trans_r;
   DRef<int> w_dev, w_dev2;
   DRef<int> m_dev;
-  int mul_we = 0, part = -1;
+  int mul_we = 0, part = -1, m_off = 0;
 };
 struct PSvd {
   DRef<double> a, u, sigma;
@@ -115,6 +115,10 @@ struct PRefMat {
   DRef<double> a;
   int lda, rows, cols;
 };
+struct PScan {
+  int first, count;
+  DRef<int> offs, total;
+};
 struct PChol {
   DRef<double> g, t, r;
   DRef<int> weff;
@@ -126,7 +130,7 @@ struct PFill {
   double value;
 };
 
-enum StepKind { SK_GEMM_D, SK_GEMM_F, SK_QR, SK_SVD, SK_CHOL, SK_FILL, SK_CVT_F2D, SK_REF };
+enum StepKind { SK_GEMM_D, SK_GEMM_F, SK_QR, SK_SVD, SK_CHOL, SK_FILL, SK_CVT_F2D, SK_REF, SK_SCAN };
 
 enum Phase { PH_PREP = 0, PH_EXACT = 1, PH_LEAF = 2, PH_COARSE = 3, PH_ROW = 4, PH_COL = 5, PH_COUPLE = 6 };
 
@@ -143,6 +147,8 @@ struct Step {
   std::vector<PFill> fill;
   std::vector<PRef> ref;
   std::vector<PRefMat> refmat;
+  std::vector<PScan> scan;
+  std::vector<DRef<int>> scansrc;
   DRef<float> cvt_in;
   DRef<double> cvt_out;
   int64_t cvt_n = 0;
@@ -230,10 +236,13 @@ struct QrSplit {
     s1 = &B.step(SK_QR);
     s1->wmax = wmax;
   }
+  // m_dev: optional device-side row count (at most m)
   void add(DRef<double> a, int lda, int m, int w, DRef<double> r, int ldr, int trans_r,
-           DRef<int> w1 = DRef<int>(), DRef<int> w2 = DRef<int>()) {
+           DRef<int> w1 = DRef<int>(), DRef<int> w2 = DRef<int>(), DRef<int> m_dev = DRef<int>()) {
     if (m <= kRows) {
-      s1->qr.push_back({a, r, lda, ldr, m, w, trans_r, w1, w2});
+      PQr q{a, r, lda, ldr, m, w, trans_r, w1, w2};
+      q.m_dev = m_dev;
+      s1->qr.push_back(q);
       return;
     }
     if (!s2) {
@@ -248,6 +257,8 @@ struct QrSplit {
       const int r0 = p * kRows, rows = std::min(kRows, m - r0);
       PQr q{a + (int64_t)r0 * lda, stack, lda, w, rows, w, 0, w1, w2};
       q.part = p;
+      q.m_dev = m_dev;
+      q.m_off = r0;
       s1->qr.push_back(q);
     }
     PQr q{stack, r, w, ldr, parts * w, w, trans_r, w1, w2};
@@ -291,11 +302,13 @@ struct GW {
     WS<T>::tasks(*s).push_back(t);
   }
   // sizes / column offset of the last task known only on the device
-  void dev(DRef<int> n_dev, DRef<int> coff_dev = DRef<int>(), DRef<int> m_dev = DRef<int>()) {
+  void dev(DRef<int> n_dev, DRef<int> coff_dev = DRef<int>(), DRef<int> m_dev = DRef<int>(),
+           DRef<int> roff_dev = DRef<int>()) {
     auto& t = WS<T>::tasks(*s).back();
     t.n_dev = n_dev;
     t.coff_dev = coff_dev;
     t.m_dev = m_dev;
+    t.roff_dev = roff_dev;
   }
   void mm(DRef<T> a, int lda, DRef<T> b, int ldb, int k, int flags = 0, double alpha = 1.0,
           DRef<double> scale = DRef<double>()) {
@@ -1394,9 +1407,23 @@ void Planner::basis(bool rows) {
     for (int s = 0; s < T.ncl; ++s)
       if (T.level[s] == lev) cl.push_back(s);
     if (cl.empty()) continue;
-    std::vector<int64_t> gst(T.ncl, -1), rt(T.ncl, -1);
+    std::vector<int64_t> gst(T.ncl, -1), rt(T.ncl, -1), poff(T.ncl, -1), ptot(T.ncl, -1);
     std::vector<int> wcol(T.ncl, 0);
-    {  // weighted condensed blocks (transposed, kcap rows per block)
+    {  // row offsets of the pieces: the kappa_b rows of block b follow each other
+      Step& sc = B.step(SK_SCAN);
+      for (int s : cl) {
+        PScan c;
+        c.first = (int)sc.scansrc.size();
+        c.count = (int)star[s].size();
+        poff[s] = B.wi(std::max<int64_t>(c.count, 1)).off;
+        ptot[s] = B.wi(1).off;
+        c.offs = Iw(poff[s]);
+        c.total = Iw(ptot[s]);
+        for (int li : star[s]) sc.scansrc.push_back(Iw(un[bnode[li]].Kap));
+        sc.scan.push_back(c);
+      }
+    }
+    {  // weighted condensed blocks (transposed, kappa_b rows per block, stacked compactly)
       GW<double> g(B.step(SK_GEMM_D));
       for (int s : cl) {
         const bool lf = T.leaf(s);
@@ -1411,20 +1438,22 @@ void Planner::basis(bool rows) {
           const int owner = rows ? nd.t : nd.s;
           // 1/omega = theta^{-(level s - level owner)/2} / ||G~_b||
           const double alpha = std::pow(th, -0.5 * (T.level[s] - T.level[owner]));
-          const DRef<double> out = Dw(gst[s]) + (int64_t)j * kcap * w;
+          const DRef<double> out = Dw(gst[s]);
+          const DRef<int> kap = Iw(u.Kap), ro = Iw(poff[s]) + (int64_t)j;
           const int fl = sflag | h2k::IT_TRANS_B | h2k::IT_SCALE_INV;
           if (lf) {
             const int64_t roff = T.begin[s] - T.begin[owner];
             g.task(out, w, kcap, w);
+            g.dev(DRef<int>(), DRef<int>(), kap, ro);
             g.mm(Dw(u.Sb), kcap, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
           } else {
             // children's coefficients packed: [0, k_c0) and [k_c0, k_c0 + k_c1)
             const int c0 = T.children[s][0], c1 = T.children[s][1];
             g.task(out, w, kcap, kc);
-            g.dev(rankout + c0);
+            g.dev(rankout + c0, DRef<int>(), kap, ro);
             g.mm(Dw(u.Sb), kcap, Dw(proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
             g.task(out, w, kcap, kc);
-            g.dev(rankout + c1, rankout + c0);
+            g.dev(rankout + c1, rankout + c0, kap, ro);
             g.mm(Dw(u.Sb), kcap, Dw(proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
           }
         }
@@ -1443,7 +1472,7 @@ void Planner::basis(bool rows) {
           w1 = rankout + T.children[s][0];
           w2 = rankout + T.children[s][1];
         }
-        q.add(Dw(gst[s]), w, (int)star[s].size() * kcap, w, Dw(rt[s]), w, 1, w1, w2);
+        q.add(Dw(gst[s]), w, (int)star[s].size() * kcap, w, Dw(rt[s]), w, 1, w1, w2, Iw(ptot[s]));
       }
     }
     {  // left singular vectors of the weighted matrix
@@ -1567,6 +1596,7 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     tasks[i].m_dev = res(tk[i].m_dev, P);
     tasks[i].n_dev = res(tk[i].n_dev, P);
     tasks[i].coff_dev = res(tk[i].coff_dev, P);
+    tasks[i].roff_dev = res(tk[i].roff_dev, P);
     tasks[i].ldc = tk[i].ldc;
     tasks[i].m = tk[i].m;
     tasks[i].n = tk[i].n;
@@ -1658,7 +1688,7 @@ static void finalize(Plan& P, double eps) {
           int* stat = P.bufi.as<int>() + st.stat_off + 2 * i;
           h2k::QrTask t{res(q.a, P),  res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), res(q.m_dev, P), stat,
                         q.lda,        q.ldr,       q.m,               q.w,                q.trans_r,         q.mul_we,
-                        q.part};
+                        q.part,       q.m_off};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.qr.size();
@@ -1699,6 +1729,22 @@ static void finalize(Plan& P, double eps) {
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.ref.size();
+        break;
+      }
+      case SK_SCAN: {
+        align(64);
+        st.desc_off = blob.size();
+        for (auto& c : st.scan) {
+          h2k::ScanTask t{c.first, c.count, res(c.offs, P), res(c.total, P)};
+          blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
+        }
+        align(64);
+        st.desc2_off = blob.size();
+        for (auto& r : st.scansrc) {
+          const int* ptr = res(r, P);
+          blob.insert(blob.end(), (char*)&ptr, (char*)&ptr + sizeof(ptr));
+        }
+        st.ndesc = (int)st.scan.size();
         break;
       }
       case SK_CVT_F2D: break;
@@ -1829,6 +1875,13 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
           timed(h2k::K_CVT, si,
                 [&] { h2k::launch_convert_f32_to_f64(res(st.cvt_in, P), res(st.cvt_out, P), st.cvt_n, s); });
         break;
+      case SK_SCAN:
+        if (st.ndesc > 0)
+          timed(h2k::K_SCAN, si, [&] {
+            h2k::launch_scan((const h2k::ScanTask*)(base + st.desc_off), (const int* const*)(base + st.desc2_off),
+                             st.ndesc, s);
+          });
+        break;
       case SK_REF:
         if (st.ndesc > 0)
           timed(h2k::K_REF, si, [&] {
@@ -1857,7 +1910,7 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
       (void)hipEventDestroy(e.b);
     }
     if (trace) {
-      static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref"};
+      static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref", "scan"};
       for (size_t i = 0; i < P.steps.size(); ++i) {
         const Step& st = P.steps[i];
         std::fprintf(stderr, "[h2 step %3zu] phase %d %-6s tasks %7d tiles %8d wmax %4d  %9.3f ms  %.3g GF %.3g GB\n",
@@ -1904,7 +1957,7 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
         }
       } else {
         static const int kmap[] = {h2k::K_GEMM_F64, h2k::K_GEMM_F32, -1, -1, h2k::K_CHOL, h2k::K_FILL, h2k::K_CVT,
-                                   h2k::K_REF};
+                                   h2k::K_REF, h2k::K_SCAN};
         const int kid = kmap[kind];
         P.units_k[kid] += kind == SK_CVT_F2D ? (st.cvt_n > 0) : st.ndesc;
         P.flops_k[kid] += st.flops;

@@ -59,7 +59,7 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
   std::vector<T> c0((size_t)m * n);
   for (auto& x : c0) x = (T)g.next();
   T* dc = up(c0, keep);
-  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1};
+  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1};
   std::vector<h2k::GemmTile> tiles;
   for (int i = 0; i < m; i += 64)
     for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
@@ -99,7 +99,7 @@ double qr_test(hipStream_t s, int m, int w) {
   double* da = up(A, keep);
   std::vector<double> R0((size_t)w * w, 0.0);
   double* dr = up(R0, keep);
-  h2k::QrTask t{da, dr, nullptr, nullptr, nullptr, nullptr, w, w, m, w, 0, 0, -1};
+  h2k::QrTask t{da, dr, nullptr, nullptr, nullptr, nullptr, w, w, m, w, 0, 0, -1, 0};
   auto* dt = up(std::vector<h2k::QrTask>{t}, keep);
   h2k::launch_qr(dt, 1, w, s);
   H2_HIP(hipStreamSynchronize(s));
@@ -138,9 +138,9 @@ double qr_split_test(hipStream_t s, int m, int w, int we) {
   double* dr = up(R0, keep);
   int* dwe = up(std::vector<int>{we}, keep);
   const int h = m / 2;
-  h2k::QrTask t1{da, dst, dwe, nullptr, nullptr, nullptr, w, w, h, w, 0, 0, 0};
-  h2k::QrTask t2{da + (size_t)h * w, dst, dwe, nullptr, nullptr, nullptr, w, w, m - h, w, 0, 0, 1};
-  h2k::QrTask t3{dst, dr, dwe, nullptr, nullptr, nullptr, w, w, 2 * w, w, 0, 2, -1};
+  h2k::QrTask t1{da, dst, dwe, nullptr, nullptr, nullptr, w, w, h, w, 0, 0, 0, 0};
+  h2k::QrTask t2{da + (size_t)h * w, dst, dwe, nullptr, nullptr, nullptr, w, w, m - h, w, 0, 0, 1, 0};
+  h2k::QrTask t3{dst, dr, dwe, nullptr, nullptr, nullptr, w, w, 2 * w, w, 0, 2, -1, 0};
   auto* d1 = up(std::vector<h2k::QrTask>{t1, t2}, keep);
   auto* d3 = up(std::vector<h2k::QrTask>{t3}, keep);
   h2k::launch_qr(d1, 2, w, s);

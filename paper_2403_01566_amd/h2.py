@@ -32,7 +32,7 @@ EXPORTS = [
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
     "h2_selftest", "h2_kernel_name",
 ]
-NKERNEL = 12
+NKERNEL = 13
 
 
 class MulOptions(C.Structure):
