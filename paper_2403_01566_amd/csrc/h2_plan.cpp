@@ -231,10 +231,14 @@ struct QrSplit {
   Builder& B;
   Step* s1;
   Step* s2 = nullptr;
-  static constexpr int kRows = H2_QR_SPLIT_ROWS;
-  QrSplit(Builder& b, int wmax) : B(b) {
+  // Row blocks of at most kRows rows.  A step with few matrices would leave
+  // most of the GPU idle while single workgroups walk long matrices, so it
+  // splits at a quarter of that height (more, shorter, parallel pieces).
+  int kRows = H2_QR_SPLIT_ROWS;
+  QrSplit(Builder& b, int wmax, size_t ntasks) : B(b) {
     s1 = &B.step(SK_QR);
     s1->wmax = wmax;
+    if (ntasks < 2048) kRows = std::max(128, H2_QR_SPLIT_ROWS / 4);
   }
   // m_dev: optional device-side row count (at most m)
   void add(DRef<double> a, int lda, int m, int w, DRef<double> r, int ldr, int trans_r,
@@ -1187,7 +1191,7 @@ void Planner::coarsen() {
     auto wd1 = [&](const MNode& x) { return x.c0 >= 0 ? Iw(mn[x.c0].Kap) : DRef<int>(); };
     auto wd2 = [&](const MNode& x) { return x.c1 >= 0 ? Iw(mn[x.c1].Kap) : DRef<int>(); };
     {  // R_Z: R factor of Z (Z = I: R_Z = I, skipped)
-      QrSplit q(B, wmax);
+      QrSplit q(B, wmax, lv.size());
       for (int i : lv) {
         MNode& x = mn[i];
         if (!x.zI && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
@@ -1209,7 +1213,7 @@ void Planner::coarsen() {
     }
     {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
        // vectors of G^ = R_Z^* as its left ones and replaces R_G^*
-      QrSplit q(B, wmax);
+      QrSplit q(B, wmax, lv.size());
       for (int i : lv) {
         MNode& x = mn[i];
         if (x.direct) continue;
@@ -1463,7 +1467,7 @@ void Planner::basis(bool rows) {
       int wmax = 0;
       for (int s : cl) wmax = std::max(wmax, wcol[s]);
       if (wmax > 128) throw Error(H2_ERR_TOO_LARGE, "leaf size above 128");
-      QrSplit q(B, wmax);
+      QrSplit q(B, wmax, cl.size());
       for (int s : cl) {
         const int w = wcol[s];
         rt[s] = B.wd((int64_t)w * w).off;
@@ -1924,6 +1928,7 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
     // other kernels from the planned sizes
     H2_HIP(hipStreamSynchronize(s));
     std::vector<int> stat;
+    double svs[3][5] = {{0}};
     for (auto& st : P.steps) {
       const int kind = (int)st.kind;
       if (kind == SK_QR || kind == SK_SVD) {
@@ -1950,6 +1955,13 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
             if (P.qrcp)  // pivoted QR of the cols x rows transpose, stopped after r steps
               for (int j = 0; j < (int)r; ++j) fl += 4.0 * (rows - j) * (cols - j);
             fl += sw * r * (r - 1) / 2.0 * 12.0 * rows;  // Jacobi: 3 dots and a rotation per pair
+            if (std::getenv("H2_TRACE")) {
+              svs[kid - h2k::K_SVD32][0] += 1;
+              svs[kid - h2k::K_SVD32][1] += rows;
+              svs[kid - h2k::K_SVD32][2] += cols;
+              svs[kid - h2k::K_SVD32][3] += r;
+              svs[kid - h2k::K_SVD32][4] += sw;
+            }
             P.units_k[kid] += 1;
             P.flops_k[kid] += fl;
             P.bytes_k[kid] += 8.0 * (rows * cols + rows * st.svd[i].kcap + cols);
@@ -1964,6 +1976,12 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
         P.bytes_k[kid] += st.bytes;
       }
     }
+    if (std::getenv("H2_TRACE"))
+      for (int c = 0; c < 3; ++c)
+        if (svs[c][0] > 0)
+          std::fprintf(stderr, "[h2 svd class %d] tasks %.0f  mean rows %.1f cols %.1f revealed %.1f sweeps %.2f\n",
+                       c, svs[c][0], svs[c][1] / svs[c][0], svs[c][2] / svs[c][0], svs[c][3] / svs[c][0],
+                       svs[c][4] / svs[c][0]);
   }
   if (timing) {
     H2_HIP(hipEventSynchronize(ev[nev - 1]));
