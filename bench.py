@@ -52,6 +52,10 @@ WORKLOADS = {
     "c2": dict(desc="icosphere level 5 (n=20480 centroids), 1/(4 pi |x-y|) (diag = row nearfield mean), leaf 64, "
                     "eta 1, Chebyshev order 4 (k=64), A*A, eps 1e-6",
                eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1, sample=("ico", 4)),
+    "c3": dict(desc="icosphere level 6 (n=81920 centroids), single layer 1/(4 pi |x-y|) times double layer "
+                    "(x-y).n_y/(4 pi |x-y|^3), leaf 64, eta 1, Chebyshev order 4 (k=64), eps 1e-4",
+               eps=1e-4, geom=("ico", 6), kernel=1, leaf=64, order=4, eta=1.0, diag=1, dlp=True,
+               sample=("ico", 4)),
 }
 
 
@@ -66,27 +70,29 @@ def build(h2, ctx, cfg, geom=None):
     P, nrm = geometry(geom or cfg["geom"])
     T = h2.Tree(ctx, P, cfg["leaf"])
     A = h2.Matrix.interpolated(ctx, T, T, cfg["kernel"], cfg["order"], cfg["eta"], cfg["diag"], nrm)
-    return T, A
+    B = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_LAPLACE_DLP, cfg["order"], cfg["eta"], 0, nrm) \
+        if cfg.get("dlp") else A
+    return T, A, B
 
 
 def say(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def run_mode(h2, ctx, A, eps, prec, steps, warmup):
+def run_mode(h2, ctx, A, B, eps, prec, steps, warmup):
     nk = h2.NKERNEL
     for _ in range(warmup):
-        C, _ = h2.mul(ctx, A, A, eps, h2.default_options(precision=prec))
+        C, _ = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))
         del C
     # untimed: algorithmic work of every kernel from the sizes the kernels report
-    C, cnt = h2.mul(ctx, A, A, eps, h2.default_options(precision=prec, timing=3))
+    C, cnt = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec, timing=3))
     del C
     opt = h2.default_options(precision=prec, timing=2)
     t_k, l_k, lat, phase = [0.0] * nk, [0] * nk, [], [0.0] * 8
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
-        C, st = h2.mul(ctx, A, A, eps, opt)   # returns after the device work has completed
+        C, st = h2.mul(ctx, A, B, eps, opt)   # returns after the device work has completed
         lat.append(time.perf_counter() - t1)
         del C
         for i in range(nk):
@@ -133,13 +139,14 @@ def cpu_baseline(h2, ctx, cfg, gpu_flops_alg):
     P, nrm = geometry(geom)
     T = O.ClusterTree(P, cfg["leaf"])
     A = O.build_interpolated(T, cfg["kernel"], cfg["order"], cfg["eta"], diag=cfg["diag"], normals=nrm)
+    B = O.build_interpolated(T, O.KERNEL_DLP, cfg["order"], cfg["eta"], normals=nrm) if cfg.get("dlp") else A
     t0 = time.perf_counter()
-    O.mul(A, A, cfg["eps"])
+    O.mul(A, B, cfg["eps"])
     dt = time.perf_counter() - t0
     scale = 1.0
     if cfg["sample"]:
-        _, As = build(h2, ctx, cfg, cfg["sample"])
-        _, ss = h2.mul(ctx, As, As, cfg["eps"])
+        _, As, Bs = build(h2, ctx, cfg, cfg["sample"])
+        _, ss = h2.mul(ctx, As, Bs, cfg["eps"])
         scale = ss["flops_alg"] / gpu_flops_alg
         sample = (f"full oracle product of the same construction at icosphere level {geom[1]} (n={len(P)}), "
                   f"{dt:.1f} s, scaled by the ratio {scale:.4f} of the library's algorithmic flops "
@@ -180,12 +187,12 @@ def main():
     eps = cfg["eps"]
     ctx = h2.Context(0)
     say(f"building operands: {cfg['desc']}")
-    T, A = build(h2, ctx, cfg)
+    T, A, B = build(h2, ctx, cfg)
     modes = [("fp64", h2.PREC_FP64)] + ([] if args.fp64_only else [("fp32_bulk", h2.PREC_FP32_BULK)])
     res = {}
     for name, prec in modes:
         say(f"timing {name}: {args.warmup} warmup + {args.steps} steps")
-        res[name] = run_mode(h2, ctx, A, eps, prec, args.steps, args.warmup)
+        res[name] = run_mode(h2, ctx, A, B, eps, prec, args.steps, args.warmup)
         say(f"{name}: {1000.0 * res[name]['total'] / args.steps:.1f} ms per product")
     head = "fp32_bulk" if "fp32_bulk" in res and res["fp32_bulk"]["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"
     r = res[head]

@@ -95,7 +95,11 @@ typedef enum { H2_PREC_FP64 = 0, H2_PREC_FP32_BULK = 1 } h2_precision;
 
 typedef struct {
   int precision;       /* h2_precision; FP32 bulk is used only for eps >= 1e-5, tighter
-                          eps runs the bulk in FP64 (stats.prec_used tells which ran)   */
+                          eps runs the bulk in FP64.  A product whose FP32 bulk exceeds
+                          a rank cap (rounding noise kept as rank where the product
+                          cancels) is recomputed in FP64, and later products of the
+                          same pair at that eps or tighter use FP64 directly.
+                          stats.prec_used tells which ran.                              */
   double theta;        /* weight base, 0 => 1/(2*sigma), sigma = max children (= 2)   */
   double budget_coarse;/* fractions of eps for coarsening, rows, columns; 0 => 1/4 */
   double budget_row;

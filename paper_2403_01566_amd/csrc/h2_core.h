@@ -131,6 +131,9 @@ struct Context {
   hipStream_t stream = nullptr;
   int* overflow = nullptr;  // device flag set by rank-cap overflows
   std::map<std::pair<uint64_t, uint64_t>, std::shared_ptr<Plan>> plans;
+  // operand pairs whose FP32 bulk exceeded a rank cap: largest such eps (those
+  // products, and tighter ones, run the bulk in FP64)
+  std::map<std::pair<uint64_t, uint64_t>, double> fp32_fail_eps;
   uint64_t next_id = 1;
   std::weak_ptr<Context> self;
   ~Context();

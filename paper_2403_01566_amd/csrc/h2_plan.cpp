@@ -41,6 +41,9 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <queue>
+#include <set>
+#include <climits>
 #include <tuple>
 #include <deque>
 #include <cstdio>
@@ -162,6 +165,8 @@ struct Step {
 struct Plan {
   std::deque<Step> steps;  // deque: references to earlier steps stay valid
   int64_t wsd = 0, wsf = 0, wsi = 0;
+  std::vector<int64_t> base_d, base_f;  // allocation starts in the planned (unshared) layout
+  int64_t wsd_planned = 0, wsf_planned = 0;
   DevBuf bufd, buff, bufi, desc;
   std::vector<char> hdesc;
   int kc = 0, kappa_cap = 0;
@@ -195,6 +200,7 @@ struct Builder {
     DRef<double> r;
     r.ws = WS_D;
     r.off = P.wsd;
+    P.base_d.push_back(P.wsd);
     P.wsd += (std::max<int64_t>(n, 1) + 31) & ~int64_t(31);
     return r;
   }
@@ -202,6 +208,7 @@ struct Builder {
     DRef<float> r;
     r.ws = WS_F;
     r.off = P.wsf;
+    P.base_f.push_back(P.wsf);
     P.wsf += (std::max<int64_t>(n, 1) + 63) & ~int64_t(63);
     return r;
   }
@@ -833,14 +840,14 @@ void Planner::phaseA() {
   // ---------------- union tree: accumulators, top-down per depth ----------------
   B.phase = PH_EXACT;
   const int kU = kY + kX;
+  // final forms; their buffers form one allocation (one conversion in FP32 bulk)
   int64_t fin_first = -1, fin_last = -1;
-  auto fin_alloc = [&](int64_t n) {
-    DRef<T> d = W(n);
-    if (fin_first < 0) fin_first = d.off;
-    fin_last = d.off + ((std::max<int64_t>(n, 1) + (isf ? 63 : 31)) & ~int64_t(isf ? 63 : 31));
-    return d.off;
+  int64_t fin_used = 0;
+  auto fin_alloc = [&](int64_t n) {  // offset inside the region (pass 1: sizes only)
+    const int64_t o = fin_used;
+    fin_used += (std::max<int64_t>(n, 1) + (isf ? 63 : 31)) & ~int64_t(isf ? 63 : 31);
+    return o;
   };
-  // final forms; their buffers form one contiguous region
   for (auto& u : un) {
     if (!u.fin) continue;
     const int64_t m = TI.size(u.t), n = TK.size(u.r);
@@ -853,6 +860,15 @@ void Planner::phaseA() {
       u.form = 1;
       u.offG = fin_alloc(m * kU);
       u.offZa = fin_alloc(n * kU);
+    }
+  }
+  if (fin_used > 0) {
+    fin_first = W(fin_used).off;
+    fin_last = fin_first + fin_used;
+    for (auto& u : un) {
+      if (!u.fin || u.form == 4) continue;
+      u.offG += fin_first;
+      if (u.form == 1) u.offZa += fin_first;
     }
   }
   int maxdep = 0;
@@ -1665,6 +1681,165 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
   st.ndesc = (int)v.size();
 }
 
+// ------------------------------------------------------------------ workspace sharing
+// A workspace buffer lives from the first to the last step that refers to it
+// (steps run in order on one stream); buffers with disjoint lifetimes share
+// memory.  Buffers are placed in order of their first use, best fit into the
+// gaps left by buffers that died before it, else at the top.  The result
+// arrays stay live to the end (they are copied out after the product).
+template <typename F>
+static void visit_refs(Step& st, F&& f) {
+  for (auto& x : st.itd) {
+    f(x.a);
+    f(x.b);
+    f(x.scale);
+  }
+  for (auto& x : st.tkd) f(x.c);
+  for (auto& x : st.itf) {
+    f(x.a);
+    f(x.b);
+    f(x.scale);
+  }
+  for (auto& x : st.tkf) f(x.c);
+  for (auto& x : st.qr) {
+    f(x.a);
+    f(x.r);
+  }
+  for (auto& x : st.svd) {
+    f(x.a);
+    f(x.u);
+    f(x.sigma);
+    f(x.u2);
+    f(x.tolref);
+  }
+  for (auto& x : st.chol) {
+    f(x.g);
+    f(x.t);
+    f(x.r);
+  }
+  for (auto& x : st.fill) f(x.p);
+  for (auto& x : st.ref) f(x.out);
+  for (auto& x : st.refmat) f(x.a);
+  f(st.cvt_in);
+  f(st.cvt_out);
+}
+
+struct ArenaPlan {
+  const std::vector<int64_t>& base;
+  int64_t total;
+  std::vector<int> first, last;
+  std::vector<int64_t> placed;
+  static constexpr int kPage = 12;  // lookup pages of 4096 elements
+  std::vector<int> page;            // first allocation overlapping each page
+  ArenaPlan(const std::vector<int64_t>& b, int64_t t)
+      : base(b), total(t), first(b.size(), INT32_MAX), last(b.size(), -1), placed(b.size(), 0) {
+    page.assign((size_t)(t >> kPage) + 2, 0);
+    size_t i = 0;
+    for (size_t p = 0; p < page.size(); ++p) {
+      const int64_t o = (int64_t)p << kPage;
+      while (i + 1 < base.size() && base[i + 1] <= o) ++i;
+      page[p] = (int)i;
+    }
+  }
+  size_t find(int64_t off) const {  // allocation containing element `off`
+    const size_t p = std::min((size_t)(off >> kPage), page.size() - 2);
+    const auto lo = base.begin() + page[p], hi = base.begin() + std::min<size_t>(page[p + 1] + 1, base.size());
+    auto it = std::upper_bound(lo, hi, off);
+    return (size_t)(it - base.begin()) - 1;
+  }
+  int64_t size(size_t i) const { return (i + 1 < base.size() ? base[i + 1] : total) - base[i]; }
+  void use(int64_t off, int step) {
+    if (base.empty()) return;
+    const size_t i = find(off);
+    first[i] = std::min(first[i], step);
+    last[i] = std::max(last[i], step);
+  }
+  int64_t place() {
+    std::vector<size_t> order;
+    for (size_t i = 0; i < base.size(); ++i)
+      if (last[i] >= 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return first[a] < first[b]; });
+    std::map<int64_t, int64_t> byoff;                  // free gaps: offset -> size
+    std::set<std::pair<int64_t, int64_t>> bysize;      // (size, offset)
+    auto erase_gap = [&](std::map<int64_t, int64_t>::iterator g) {
+      bysize.erase({g->second, g->first});
+      byoff.erase(g);
+    };
+    auto add_gap = [&](int64_t off, int64_t sz) {
+      auto nx = byoff.lower_bound(off);
+      if (nx != byoff.end() && nx->first == off + sz) {
+        sz += nx->second;
+        erase_gap(nx);
+      }
+      auto pv = byoff.lower_bound(off);
+      if (pv != byoff.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+          off = pv->first;
+          sz += pv->second;
+          erase_gap(pv);
+        }
+      }
+      byoff[off] = sz;
+      bysize.emplace(sz, off);
+    };
+    typedef std::pair<int, size_t> Live;  // (last step, allocation)
+    std::priority_queue<Live, std::vector<Live>, std::greater<Live>> live;
+    int64_t top = 0;
+    for (size_t i : order) {
+      while (!live.empty() && live.top().first < first[i]) {
+        const size_t j = live.top().second;
+        live.pop();
+        add_gap(placed[j], size(j));
+      }
+      const int64_t need = size(i);
+      auto g = bysize.lower_bound({need, INT64_MIN});
+      if (g != bysize.end()) {
+        const int64_t off = g->second, sz = g->first;
+        erase_gap(byoff.find(off));
+        placed[i] = off;
+        if (sz > need) add_gap(off + need, sz - need);
+      } else {
+        placed[i] = top;
+        top += need;
+      }
+      live.emplace(last[i], i);
+    }
+    return top;
+  }
+  int64_t remap(int64_t off) const {
+    if (base.empty()) return off;
+    const size_t i = find(off);
+    return placed[i] + (off - base[i]);
+  }
+};
+
+static void share_workspace(Plan& P) {
+  ArenaPlan ad(P.base_d, P.wsd), af(P.base_f, P.wsf);
+  const int nst = (int)P.steps.size();
+  int si = 0;
+  auto use = [&](auto& r) {
+    if (r.ws == WS_D) ad.use(r.off, si);
+    else if (r.ws == WS_F) af.use(r.off, si);
+  };
+  for (auto& st : P.steps) {
+    visit_refs(st, use);
+    ++si;
+  }
+  si = nst;  // result arrays: live to the end
+  for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) use(*r);
+  P.wsd_planned = P.wsd;
+  P.wsf_planned = P.wsf;
+  P.wsd = ad.place();
+  P.wsf = af.place();
+  auto remap = [&](auto& r) {
+    if (r.ws == WS_D) r.off = ad.remap(r.off);
+    else if (r.ws == WS_F) r.off = af.remap(r.off);
+  };
+  for (auto& st : P.steps) visit_refs(st, remap);
+  for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) remap(*r);
+}
+
 static void finalize(Plan& P, double eps) {
   for (auto& st : P.steps) {
     const int per = st.kind == SK_QR ? 2 : (st.kind == SK_SVD ? 4 : 0);
@@ -1673,6 +1848,9 @@ static void finalize(Plan& P, double eps) {
     st.stat_off = P.wsi;
     P.wsi += ((int64_t)(per * n) + 63) & ~int64_t(63);
   }
+  if (std::getenv("H2_TRACE"))
+    std::fprintf(stderr, "[h2 plan] workspace %.3f GB fp64, %.3f GB fp32, %.3f GB int, %zu steps\n",
+                 P.wsd * 8e-9, P.wsf * 4e-9, P.wsi * 4e-9, P.steps.size());
   P.bufd.alloc(std::max<int64_t>(P.wsd, 1) * sizeof(double));
   P.buff.alloc(std::max<int64_t>(P.wsf, 1) * sizeof(float));
   P.bufi.alloc(std::max<int64_t>(P.wsi, 1) * sizeof(int));
@@ -2027,11 +2205,23 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   P->res_S = B.wd((int64_t)P->cbt.adm.size() * kc * kc);
   P->res_rank_row = B.wi(X->rows->ncl);
   P->res_rank_col = B.wi(Y->cols->ncl);
+  const bool tr = std::getenv("H2_TRACE") != nullptr;
+  const auto tp0 = std::chrono::steady_clock::now();
+  auto ws = [&](const char* what) {
+    if (tr)
+      std::fprintf(stderr, "[h2 plan] after %-8s fp64 workspace %.3f GB, host %.0f ms\n", what, P->wsd * 8e-9,
+                   std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
+  };
+  ws("union");
   if (f32) pl.phaseA<float>();
   else pl.phaseA<double>();
+  ws("exact");
   pl.coarsen();
+  ws("coarsen");
   pl.basis(true);
+  ws("rows");
   pl.basis(false);
+  ws("cols");
   pl.couplings();
   P->n_adm = P->cbt.adm.size();
   P->n_inadm = P->cbt.inadm.size();
@@ -2068,7 +2258,14 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
     opbytes += (double)M->bt.adm.size() * M->kc * M->kc * (f32 ? 4 : 8) + (double)M->nsize * (f32 ? 4 : 8);
   }
   P->bytes_alg = opbytes + 2.0 * ((double)P->wsd * w8 + (double)P->wsf * 4.0);
+  ws("counts");
+  share_workspace(*P);
+  ws("sharing");
+  if (std::getenv("H2_TRACE"))
+    std::fprintf(stderr, "[h2 plan] shared workspace: fp64 %.3f GB of %.3f GB, fp32 %.3f GB of %.3f GB\n",
+                 P->wsd * 8e-9, P->wsd_planned * 8e-9, P->wsf * 4e-9, P->wsf_planned * 4e-9);
   finalize(*P, eps);
+  ws("final");
   return P;
 }
 
@@ -2080,6 +2277,10 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
   // FP32 bulk only where its rounding (about 1e-7 of a block's norm) stays well
   // below the truncation tolerances; tighter eps runs the bulk in FP64.
   bool f32 = opt.precision == H2_PREC_FP32_BULK && eps >= 1e-5;
+  if (f32) {
+    auto f = ctx->fp32_fail_eps.find({X->id, Y->id});
+    if (f != ctx->fp32_fail_eps.end() && eps <= f->second) f32 = false;
+  }
   const int kmax = std::max(X->kc, Y->kc);
   int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
   int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
@@ -2110,6 +2311,18 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
   H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   H2_HIP(hipStreamSynchronize(ctx->stream));
   if (ovf) {
+    if (f32) {
+      // FP32 rounding of the exact blocks reached the truncation tolerance
+      // (cancellation in the product): rounding noise would be kept as rank.
+      // Run this product, and tighter ones on the same pair, in FP64.
+      double& fe = ctx->fp32_fail_eps[{X->id, Y->id}];
+      fe = std::max(fe, eps);
+      ctx->plans.erase(key);
+      P.reset();
+      h2_mul_options o2 = opt;
+      o2.precision = H2_PREC_FP64;
+      return multiply(ctx, X, Y, eps, o2, stats);
+    }
     if ((ovf & 2) && opt.max_rank == 0 && kc < 64) {
       // the default cap was too small for this product: retry once with the largest cap
       h2_mul_options o2 = opt;

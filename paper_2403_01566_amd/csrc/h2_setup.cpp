@@ -179,6 +179,10 @@ void Context::evict(uint64_t matrix_id) {
     if (it->first.first == matrix_id || (it->first.second >> 2) == matrix_id) it = plans.erase(it);
     else ++it;
   }
+  for (auto it = fp32_fail_eps.begin(); it != fp32_fail_eps.end();) {
+    if (it->first.first == matrix_id || it->first.second == matrix_id) it = fp32_fail_eps.erase(it);
+    else ++it;
+  }
 }
 
 double* Matrix::alloc64(size_t count) {
