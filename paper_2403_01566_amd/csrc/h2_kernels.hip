@@ -227,6 +227,29 @@ void launch_gemm_f32(const GemmItem<float>* items, const GemmTask<float>* tasks,
   if (ntiles > 0) hipLaunchKernelGGL(gemm_kernel<float>, dim3(ntiles), dim3(256), 0, s, items, tasks, tiles);
 }
 
+// Lane exchange within a row of 16 lanes through DPP (a VALU operand
+// modifier, no LDS round trip): CTRL is a quad permutation or a row mirror.
+template <int CTRL>
+__device__ inline double dpp_mov(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of g consecutive lanes (g in 1, 2, 4, 8, 16), the
+// result in every lane of the group: lane pairs, quads, half rows, rows.
+__device__ inline double dpp_group_sum(double v, int g) {
+  if (g >= 2) v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (g >= 4) v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (g >= 8) v += dpp_mov<0x141>(v);  // row_half_mirror
+  if (g >= 16) v += dpp_mov<0x140>(v); // row_mirror
+  return v;
+}
+template <int CTRL>
+__device__ inline int dpp_mov_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+
 // ---------------------------------------------------------------------------
 // Streaming Householder QR (R only), one workgroup per matrix.
 // ---------------------------------------------------------------------------
@@ -272,7 +295,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
     double x2 = 0.0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) x2 += c[q] * c[q];
-    for (int off = 1; off < TPC; off <<= 1) x2 += __shfl_xor(x2, off, 64);
+    x2 = dpp_group_sum(x2, TPC);
     const int pd = pk(col, col, we);
     const double alpha = R[pd];
     double tau = 0.0, scal = 0.0;
@@ -310,7 +333,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
           double dot = 0.0;
 #pragma unroll
           for (int q = 0; q < RPT; ++q) dot += vb[b][sub + TPC * q] * c[q];
-          for (int off = 1; off < TPC; off <<= 1) dot += __shfl_xor(dot, off, 64);
+          dot = dpp_group_sum(dot, TPC);
           const int p = pk(j, l, we);
           const double full = R[p] + scal * dot;
           const double f = tau * scal * full;
@@ -364,23 +387,26 @@ void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Sum over the workgroup (result in every thread): wave shuffles, then one
 // exchange of the per-wave sums through LDS.
+// (red holds NT / 16 entries)
 template <int NT>
 __device__ inline double block_sum(double v, double* red) {
-  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  v = dpp_group_sum(v, 16);
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if ((threadIdx.x & 15) == 0) red[threadIdx.x >> 4] = v;
   __syncthreads();
   double t = 0.0;
-  for (int w = 0; w < NT / 64; ++w) t += red[w];
+  for (int w = 0; w < NT / 16; ++w) t += red[w];
   return t;
 }
 
 // Sum over the G consecutive lanes of a group (G a power of two <= 64).
 template <int G>
 __device__ inline double group_sum(double v) {
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  static_assert(G <= 16, "groups within a DPP row");
+  return dpp_group_sum(v, G);
 }
+
+
 
 // Truncated SVD (left singular vectors) of a small matrix A (rows x cols).
 //
@@ -403,14 +429,14 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   constexpr int LD = WMAX + 1;
   constexpr int TPC = NT / WMAX;  // lanes per column of A^T in the rank reveal
   constexpr int RPL = WMAX / TPC; // rows per lane
-  constexpr int NW = NT / 64;
+  constexpr int NR = NT / 16;  // DPP rows of the workgroup
   static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && NT % 64 == 0, "launch shape");
   __shared__ double M[WMAX * LD];
   __shared__ double nrm[WMAX];
   __shared__ int order[WMAX];
   __shared__ double vb[WMAX];
-  __shared__ double red[NW], wmx[NW];
-  __shared__ int widx[NW];
+  __shared__ double red[NR], wmx[NR];
+  __shared__ int widx[NR];
   __shared__ int sh_rot;
   __shared__ double sh_tau, sh_scal;
   const SvdTask tk = tasks[blockIdx.x];
@@ -468,24 +494,30 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
         const bool act = l < nl && done < 0;
         double v = act ? cn : -1.0, sv = (act && sub == 0) ? cn : 0.0;
         int id = act ? l : WMAX;
-        for (int off = 1; off < 64; off <<= 1) {
-          sv += __shfl_xor(sv, off, 64);
-          const double ov = __shfl_xor(v, off, 64);
-          const int oi = __shfl_xor(id, off, 64);
-          if (ov > v || (ov == v && oi < id)) {
-            v = ov;
-            id = oi;
-          }
+        sv = dpp_group_sum(sv, 16);
+        {  // argmax within the row of 16 lanes
+          double ov = dpp_mov<0xB1>(v);
+          int oi = dpp_mov_int<0xB1>(id);
+          if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+          ov = dpp_mov<0x4E>(v);
+          oi = dpp_mov_int<0x4E>(id);
+          if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+          ov = dpp_mov<0x141>(v);
+          oi = dpp_mov_int<0x141>(id);
+          if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+          ov = dpp_mov<0x140>(v);
+          oi = dpp_mov_int<0x140>(id);
+          if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
         }
-        if (lane == 0) {
-          red[wv] = sv;
-          wmx[wv] = v;
-          widx[wv] = id;
+        if ((lane & 15) == 0) {
+          red[tid >> 4] = sv;
+          wmx[tid >> 4] = v;
+          widx[tid >> 4] = id;
         }
         __syncthreads();
         double tot = 0.0, bv = -1.0;
         int p = WMAX;
-        for (int w = 0; w < NW; ++w) {
+        for (int w = 0; w < NR; ++w) {
           tot += red[w];
           if (wmx[w] > bv || (wmx[w] == bv && widx[w] < p)) {
             bv = wmx[w];
@@ -571,8 +603,9 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   if (!empty) {
     const int np = (cols + 1) & ~1;  // players incl. a dummy when cols is odd
     const int npairs = np / 2;
-    // G threads (consecutive lanes of one wave) share a pair
-    int G = 64;
+    // G threads (consecutive lanes of one wave, at most a DPP row of 16)
+    // share a pair
+    int G = 16;
     while (G > 1 && npairs * G > NT) G >>= 1;
     const int grp = tid / G, gl = tid % G;
     for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
@@ -592,12 +625,10 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
               double x = cp[r], y = cq[r];
               a += x * x; b += y * y; c += x * y;
             }
-          for (int off = 1; off < G; off <<= 1) {
-            a += __shfl_xor(a, off, 64);
-            b += __shfl_xor(b, off, 64);
-            c += __shfl_xor(c, off, 64);
-          }
-          if (valid && c != 0.0 && fabs(c) > 1e-15 * sqrt(a * b)) {
+          a = dpp_group_sum(a, G);
+          b = dpp_group_sum(b, G);
+          c = dpp_group_sum(c, G);
+          if (valid && c != 0.0 && c * c > 1e-30 * (a * b)) {
             double zeta = (b - a) / (2.0 * c);
             double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
             double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;

@@ -1109,7 +1109,47 @@ void Planner::coarsen() {
     mn[root].unode = ui;
     return of_un[ui] = root;
   };
-  for (size_t li = 0; li < C.adm.size(); ++li) make(bnode[li]);
+  // Result blocks of at most 128 x 128 whose induced sub-blocks are finer are
+  // assembled densely from their exact pieces and truncated once (a direct
+  // SVD of the block instead of a merge tree of small truncations).
+  std::vector<std::pair<int, int>> dense_asm;  // (MNode, union node of the result leaf)
+  for (size_t li = 0; li < C.adm.size(); ++li) {
+    UNode& u = un[bnode[li]];
+    const int m = (int)TI.size(u.t), n = (int)TK.size(u.r);
+    if (u.fin || m > 128 || n > 128) {
+      make(bnode[li]);
+      continue;
+    }
+    MNode x;
+    x.t = u.t;
+    x.r = u.r;
+    x.m = m;
+    x.n = n;
+    x.K = n;
+    x.U = B.wd((int64_t)m * n).off;
+    x.Z = -2;  // identity
+    x.below = u.below;
+    x.unode = bnode[li];
+    mn.push_back(x);
+    of_un[bnode[li]] = (int)mn.size() - 1;
+    dense_asm.push_back({(int)mn.size() - 1, bnode[li]});
+  }
+  if (!dense_asm.empty()) {
+    GW<double> g(B.step(SK_GEMM_D));
+    std::function<void(const MNode&, int)> add = [&](const MNode& x, int ui) {
+      const UNode& f = un[ui];
+      if (!f.fin) {
+        for (int c = 0; c < f.nchild; ++c) add(x, f.child0 + c);
+        return;
+      }
+      const int64_t ro = TI.begin[f.t] - TI.begin[x.t], co = TK.begin[f.r] - TK.begin[x.r];
+      g.task(Dw(x.U) + ro * x.n + co, x.n, f.m, f.n);
+      if (f.form == 1) g.mm(Dw(f.U), f.K, Dw(f.Z), f.K, f.K, h2k::IT_TRANS_B);
+      else if (f.form == 2) g.copy(Dw(f.U), f.K);
+      else g.copy(Dw(f.Z), f.K, h2k::IT_TRANS_A);
+    };
+    for (auto& d : dense_asm) add(mn[d.first], d.second);
+  }
   int maxh = 0;
   for (auto& x : mn) maxh = std::max(maxh, x.height);
   if (std::getenv("H2_TRACE")) {  // shape summary of the merge tree
