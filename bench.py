@@ -104,7 +104,26 @@ def run_mode(h2, ctx, A, B, eps, prec, steps, warmup):
     return dict(total=total, lat=lat, st=st, cnt=cnt, t_k=t_k, l_k=l_k, phase=[p / steps for p in phase])
 
 
-def roofline(names, r, steps):
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration),
+    or None when there is none or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    src = os.path.join(ROOT, "paper_2403_01566_amd", "csrc", "h2_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    if data.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    k = data.get("kernels", {}).get(kernel)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
+COUNTER_FILES = {"c2": "c2_icosphere5"}
+
+
+def roofline(names, r, steps, workload):
     t_k, l_k, cnt = r["t_k"], r["l_k"], r["cnt"]
     dom = max(range(len(names)), key=lambda i: t_k[i])
     name = names[dom]
@@ -120,6 +139,9 @@ def roofline(names, r, steps):
         achieved = per_launch / avg_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    tr = measured_traffic(COUNTER_FILES[workload], name) if workload in COUNTER_FILES else None
+    roof["traffic"] = tr
+    roof["traffic_unit"] = "HBM bytes per launch"
     roof.update({"kernel": name, "launches_per_step": launches, "ms_per_launch": avg_launch_s * 1e3,
                  "units_per_launch": cnt["units_kernel"][dom] / max(1, launches),
                  "algorithmic_per_launch": per_launch,
@@ -217,7 +239,7 @@ def main():
         "config": {"workload": cfg["desc"], "n": int(T.n), "eps": eps, "n_adm": st["n_adm"],
                    "n_inadm": st["n_inadm"], "rank_max": [st["rank_max_row"], st["rank_max_col"]]},
         "latency_ms": {"p50": p50, "p99": p99},
-        "roofline": roofline(names, r, args.steps),
+        "roofline": roofline(names, r, args.steps, args.workload),
         "phase_ms": dict(zip(["prep", "exact", "leaf", "coarsen", "row", "col", "couple", "total"], r["phase"])),
         "kernels": {names[i]: {"ms_per_step": r["t_k"][i] / args.steps,
                                "launches_per_step": r["cnt"]["launches_kernel"][i],
