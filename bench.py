@@ -107,14 +107,16 @@ def run_mode(h2, ctx, A, B, eps, prec, steps, warmup):
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a copy-kernel calibration),
-    or None when there is none or the kernel source changed since."""
+    or None when there is none or the kernels or the planner changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
-    src = os.path.join(ROOT, "paper_2403_01566_amd", "csrc", "h2_kernels.hip")
     if not os.path.exists(path):
         return None
     data = json.load(open(path))
-    if data.get("kernel_source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    h = hashlib.sha256()
+    for f in ("h2_kernels.hip", "h2_plan.cpp"):  # the kernels and the launches they receive
+        h.update(open(os.path.join(ROOT, "paper_2403_01566_amd", "csrc", f), "rb").read())
+    if data.get("source_sha256") != h.hexdigest():
         return None
     k = data.get("kernels", {}).get(kernel)
     return None if k is None else k["hbm_bytes_per_launch"]
@@ -240,7 +242,8 @@ def main():
                    "n_inadm": st["n_inadm"], "rank_max": [st["rank_max_row"], st["rank_max_col"]]},
         "latency_ms": {"p50": p50, "p99": p99},
         "roofline": roofline(names, r, args.steps, args.workload),
-        "phase_ms": dict(zip(["prep", "exact", "leaf", "coarsen", "row", "col", "couple", "total"], r["phase"])),
+        "phase_ms": {k: v for k, v in zip(["prep", "exact", "leaf", "coarsen", "bases", "-", "couple", "total"],
+                                           r["phase"]) if k != "-"},
         "kernels": {names[i]: {"ms_per_step": r["t_k"][i] / args.steps,
                                "launches_per_step": r["cnt"]["launches_kernel"][i],
                                "units_per_step": r["cnt"]["units_kernel"][i],

@@ -117,7 +117,8 @@ typedef struct {
 
 typedef struct {
   double t_phase[8];   /* device ms: 0 operand prep, 1 exact product, 2 leaf assembly,
-                          3 coarsening, 4 row basis, 5 column basis, 6 couplings, 7 total */
+                          3 coarsening, 4 row and column bases (built together, level by
+                          level), 5 reserved (0), 6 couplings, 7 total                   */
   double t_plan_ms;    /* host planning time of this call (0 when the plan was cached)   */
   double bytes_alg;    /* algorithmic bytes of the product from the planned sizes          */
   double flops_alg;    /* algorithmic flops of the product from the planned sizes          */

@@ -437,7 +437,7 @@ class Planner {
   template <typename T>
   void phaseA();
   void coarsen();
-  void basis(bool rows);
+  void bases();
   void couplings();
 };
 
@@ -1440,157 +1440,198 @@ void Planner::coarsen() {
 }
 
 // ------------------------------------------------------------------ adaptive bases
-void Planner::basis(bool rows) {
-  B.phase = rows ? PH_ROW : PH_COL;
-  const Tree& T = rows ? TI : TK;
-  std::vector<std::vector<int>> own(T.ncl);
-  for (size_t li = 0; li < C.adm.size(); ++li) {
-    const auto& nd = C.nodes[C.adm[li]];
-    own[rows ? nd.t : nd.s].push_back((int)li);
-  }
-  DRef<double> leafout = rows ? P.res_vleaf : P.res_wleaf;
-  DRef<double> trout = rows ? P.res_vtr : P.res_wtr;
-  DRef<int> rankout = rows ? P.res_rank_row : P.res_rank_col;
+void Planner::bases() {
+  // Row and column bases are independent: both are built bottom-up in the
+  // same launches, level by level (more tasks per launch on the small levels).
+  B.phase = PH_ROW;
+  struct Side {
+    bool rows;
+    const Tree* T;
+    std::vector<std::vector<int>> own, star;  // star: row*(s) / col*(s)
+    std::vector<std::map<int, int64_t>> proj;
+    DRef<double> leafout, trout;
+    DRef<int> rankout;
+    int sflag;
+    std::vector<int> cl, wcol;
+    std::vector<int64_t> gst, rt, poff, ptot;
+  };
+  Side side[2];
   const int kk = kc * kc;
-  std::vector<std::map<int, int64_t>> proj(T.ncl);
-  std::vector<std::vector<int>> star(T.ncl);  // row*(s) / col*(s)
-  for (int s = 0; s < T.ncl; ++s) {
-    for (int a = s; a >= 0; a = T.parent[a])
-      for (int li : own[a]) star[s].push_back(li);
-    for (int li : star[s]) proj[s][li] = B.wd((int64_t)kc * kcap).off;
-  }
-  std::vector<int64_t> vhat(T.ncl, -1);
   const double th = P.theta;
-  const int sflag = rows ? h2k::IT_TRANS_A : 0;
-  for (int lev = T.depth - 1; lev >= 0; --lev) {
-    std::vector<int> cl;
-    for (int s = 0; s < T.ncl; ++s)
-      if (T.level[s] == lev) cl.push_back(s);
-    if (cl.empty()) continue;
-    std::vector<int64_t> gst(T.ncl, -1), rt(T.ncl, -1), poff(T.ncl, -1), ptot(T.ncl, -1);
-    std::vector<int> wcol(T.ncl, 0);
+  int maxdepth = 0;
+  for (int sd = 0; sd < 2; ++sd) {
+    Side& X = side[sd];
+    X.rows = sd == 0;
+    X.T = X.rows ? &TI : &TK;
+    const Tree& T = *X.T;
+    X.own.assign(T.ncl, {});
+    for (size_t li = 0; li < C.adm.size(); ++li) {
+      const auto& nd = C.nodes[C.adm[li]];
+      X.own[X.rows ? nd.t : nd.s].push_back((int)li);
+    }
+    X.leafout = X.rows ? P.res_vleaf : P.res_wleaf;
+    X.trout = X.rows ? P.res_vtr : P.res_wtr;
+    X.rankout = X.rows ? P.res_rank_row : P.res_rank_col;
+    X.sflag = X.rows ? h2k::IT_TRANS_A : 0;
+    X.proj.assign(T.ncl, {});
+    X.star.assign(T.ncl, {});
+    for (int s = 0; s < T.ncl; ++s) {
+      for (int a = s; a >= 0; a = T.parent[a])
+        for (int li : X.own[a]) X.star[s].push_back(li);
+      for (int li : X.star[s]) X.proj[s][li] = B.wd((int64_t)kc * kcap).off;
+    }
+    X.gst.assign(T.ncl, -1);
+    X.rt.assign(T.ncl, -1);
+    X.poff.assign(T.ncl, -1);
+    X.ptot.assign(T.ncl, -1);
+    X.wcol.assign(T.ncl, 0);
+    maxdepth = std::max(maxdepth, T.depth);
+  }
+  for (int lev = maxdepth - 1; lev >= 0; --lev) {
+    size_t ncl = 0;
+    for (Side& X : side) {
+      X.cl.clear();
+      for (int s = 0; s < X.T->ncl; ++s)
+        if (X.T->level[s] == lev) X.cl.push_back(s);
+      ncl += X.cl.size();
+    }
+    if (ncl == 0) continue;
     {  // row offsets of the pieces: the kappa_b rows of block b follow each other
       Step& sc = B.step(SK_SCAN);
-      for (int s : cl) {
-        PScan c;
-        c.first = (int)sc.scansrc.size();
-        c.count = (int)star[s].size();
-        poff[s] = B.wi(std::max<int64_t>(c.count, 1)).off;
-        ptot[s] = B.wi(1).off;
-        c.offs = Iw(poff[s]);
-        c.total = Iw(ptot[s]);
-        for (int li : star[s]) sc.scansrc.push_back(Iw(un[bnode[li]].Kap));
-        sc.scan.push_back(c);
-      }
+      for (Side& X : side)
+        for (int s : X.cl) {
+          PScan c;
+          c.first = (int)sc.scansrc.size();
+          c.count = (int)X.star[s].size();
+          X.poff[s] = B.wi(std::max<int64_t>(c.count, 1)).off;
+          X.ptot[s] = B.wi(1).off;
+          c.offs = Iw(X.poff[s]);
+          c.total = Iw(X.ptot[s]);
+          for (int li : X.star[s]) sc.scansrc.push_back(Iw(un[bnode[li]].Kap));
+          sc.scan.push_back(c);
+        }
     }
     {  // weighted condensed blocks (transposed, kappa_b rows per block, stacked compactly)
       GW<double> g(B.step(SK_GEMM_D));
-      for (int s : cl) {
-        const bool lf = T.leaf(s);
-        const int w = lf ? (int)T.size(s) : 2 * kc;
-        wcol[s] = w;
-        const int nrow = (int)star[s].size() * kcap;
-        gst[s] = B.wd((int64_t)std::max(nrow, 1) * w).off;
-        for (size_t j = 0; j < star[s].size(); ++j) {
-          const int li = star[s][j];
-          const UNode& u = un[bnode[li]];
-          const auto& nd = C.nodes[C.adm[li]];
-          const int owner = rows ? nd.t : nd.s;
-          // 1/omega = theta^{-(level s - level owner)/2} / ||G~_b||
-          const double alpha = std::pow(th, -0.5 * (T.level[s] - T.level[owner]));
-          const DRef<double> out = Dw(gst[s]);
-          const DRef<int> kap = Iw(u.Kap), ro = Iw(poff[s]) + (int64_t)j;
-          const int fl = sflag | h2k::IT_TRANS_B | h2k::IT_SCALE_INV;
-          if (lf) {
-            const int64_t roff = T.begin[s] - T.begin[owner];
-            g.task(out, w, kcap, w);
-            g.dev(DRef<int>(), DRef<int>(), kap, ro);
-            g.mm(Dw(u.Sb), kcap, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
-          } else {
-            // children's coefficients packed: [0, k_c0) and [k_c0, k_c0 + k_c1)
-            const int c0 = T.children[s][0], c1 = T.children[s][1];
-            g.task(out, w, kcap, kc);
-            g.dev(rankout + c0, DRef<int>(), kap, ro);
-            g.mm(Dw(u.Sb), kcap, Dw(proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
-            g.task(out, w, kcap, kc);
-            g.dev(rankout + c1, rankout + c0, kap, ro);
-            g.mm(Dw(u.Sb), kcap, Dw(proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+      for (Side& X : side) {
+        const Tree& T = *X.T;
+        for (int s : X.cl) {
+          const bool lf = T.leaf(s);
+          const int w = lf ? (int)T.size(s) : 2 * kc;
+          X.wcol[s] = w;
+          const int nrow = (int)X.star[s].size() * kcap;
+          X.gst[s] = B.wd((int64_t)std::max(nrow, 1) * w).off;
+          for (size_t j = 0; j < X.star[s].size(); ++j) {
+            const int li = X.star[s][j];
+            const UNode& u = un[bnode[li]];
+            const auto& nd = C.nodes[C.adm[li]];
+            const int owner = X.rows ? nd.t : nd.s;
+            // 1/omega = theta^{-(level s - level owner)/2} / ||G~_b||
+            const double alpha = std::pow(th, -0.5 * (T.level[s] - T.level[owner]));
+            const DRef<double> out = Dw(X.gst[s]);
+            const DRef<int> kap = Iw(u.Kap), ro = Iw(X.poff[s]) + (int64_t)j;
+            const int fl = X.sflag | h2k::IT_TRANS_B | h2k::IT_SCALE_INV;
+            if (lf) {
+              const int64_t roff = T.begin[s] - T.begin[owner];
+              g.task(out, w, kcap, w);
+              g.dev(DRef<int>(), DRef<int>(), kap, ro);
+              g.mm(Dw(u.Sb), kcap, Dw(X.rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
+            } else {
+              // children's coefficients packed: [0, k_c0) and [k_c0, k_c0 + k_c1)
+              const int c0 = T.children[s][0], c1 = T.children[s][1];
+              g.task(out, w, kcap, kc);
+              g.dev(X.rankout + c0, DRef<int>(), kap, ro);
+              g.mm(Dw(u.Sb), kcap, Dw(X.proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+              g.task(out, w, kcap, kc);
+              g.dev(X.rankout + c1, X.rankout + c0, kap, ro);
+              g.mm(Dw(u.Sb), kcap, Dw(X.proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+            }
           }
         }
       }
     }
     {  // R^* of the weighted matrix (the launcher picks the width class per task)
       int wmax = 0;
-      for (int s : cl) wmax = std::max(wmax, wcol[s]);
+      for (Side& X : side)
+        for (int s : X.cl) wmax = std::max(wmax, X.wcol[s]);
       if (wmax > 128) throw Error(H2_ERR_TOO_LARGE, "leaf size above 128");
-      QrSplit q(B, wmax, cl.size());
-      for (int s : cl) {
-        const int w = wcol[s];
-        rt[s] = B.wd((int64_t)w * w).off;
-        DRef<int> w1, w2;
-        if (!T.leaf(s)) {
-          w1 = rankout + T.children[s][0];
-          w2 = rankout + T.children[s][1];
+      QrSplit q(B, wmax, ncl);
+      for (Side& X : side) {
+        const Tree& T = *X.T;
+        for (int s : X.cl) {
+          const int w = X.wcol[s];
+          X.rt[s] = B.wd((int64_t)w * w).off;
+          DRef<int> w1, w2;
+          if (!T.leaf(s)) {
+            w1 = X.rankout + T.children[s][0];
+            w2 = X.rankout + T.children[s][1];
+          }
+          q.add(Dw(X.gst[s]), w, (int)X.star[s].size() * kcap, w, Dw(X.rt[s]), w, 1, w1, w2, Iw(X.ptot[s]));
         }
-        q.add(Dw(gst[s]), w, (int)star[s].size() * kcap, w, Dw(rt[s]), w, 1, w1, w2, Iw(ptot[s]));
       }
     }
     {  // left singular vectors of the weighted matrix
       Step& st = B.step(SK_SVD);
-      for (int s : cl) {
-        const int w = wcol[s];
-        st.wmax = std::max(st.wmax, w);
-        PSvd v;
-        v.a = Dw(rt[s]);
-        if (T.leaf(s)) v.u = leafout + T.begin[s] * kc;
-        else {
-          // stacked transfers: rows [0, k_c0) give E_c0, the rest E_c1
-          const int c0 = T.children[s][0], c1 = T.children[s][1];
-          v.u = trout + (int64_t)c0 * kk;
-          v.u2 = trout + (int64_t)c1 * kk;
-          v.split_dev = rankout + c0;
-          v.w_dev = rankout + c0;
-          v.w_dev2 = rankout + c1;
-          v.urows = kc;
+      for (Side& X : side) {
+        const Tree& T = *X.T;
+        for (int s : X.cl) {
+          const int w = X.wcol[s];
+          st.wmax = std::max(st.wmax, w);
+          PSvd v;
+          v.a = Dw(X.rt[s]);
+          if (T.leaf(s)) v.u = X.leafout + T.begin[s] * kc;
+          else {
+            // stacked transfers: rows [0, k_c0) give E_c0, the rest E_c1
+            const int c0 = T.children[s][0], c1 = T.children[s][1];
+            v.u = X.trout + (int64_t)c0 * kk;
+            v.u2 = X.trout + (int64_t)c1 * kk;
+            v.split_dev = X.rankout + c0;
+            v.w_dev = X.rankout + c0;
+            v.w_dev2 = X.rankout + c1;
+            v.urows = kc;
+          }
+          v.sigma = Dw(B.wd(w).off);
+          v.rank = X.rankout + s;
+          v.tolkind = X.rows ? 1 : 2;
+          v.tolfactor = 1.0;
+          v.lda = w;
+          v.ldu = kc;
+          v.rows = w;
+          v.cols = w;
+          v.kcap = kc;
+          st.svd.push_back(v);
         }
-        v.sigma = Dw(B.wd(w).off);
-        v.rank = rankout + s;
-        v.tolkind = rows ? 1 : 2;
-        v.tolfactor = 1.0;
-        v.lda = w;
-        v.ldu = kc;
-        v.rows = w;
-        v.cols = w;
-        v.kcap = kc;
-        st.svd.push_back(v);
       }
     }
     {  // transfers and projections G^_{s,b} = V_s^* G^c_b|_s (coefficient part)
       GW<double> g(B.step(SK_GEMM_D));
-      for (int s : cl) {
-        if (T.leaf(s)) {
-          for (int li : star[s]) {
-            const UNode& u = un[bnode[li]];
-            const auto& nd = C.nodes[C.adm[li]];
-            const int owner = rows ? nd.t : nd.s;
-            const int64_t roff = T.begin[s] - T.begin[owner];
-            g.task(Dw(proj[s][li]), kcap, kc, kcap);
-            g.mm(leafout + T.begin[s] * kc, kc, Dw(rows ? u.Uh : u.Vh) + roff * kcap, kcap, (int)T.size(s),
-                 h2k::IT_TRANS_A);
-          }
-        } else {
-          const int c0 = T.children[s][0], c1 = T.children[s][1];
-          for (int li : star[s]) {
-            g.task(Dw(proj[s][li]), kcap, kc, kcap);
-            g.mm(trout + (int64_t)c0 * kk, kc, Dw(proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
-            g.mm(trout + (int64_t)c1 * kk, kc, Dw(proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
+      for (Side& X : side) {
+        const Tree& T = *X.T;
+        for (int s : X.cl) {
+          if (T.leaf(s)) {
+            for (int li : X.star[s]) {
+              const UNode& u = un[bnode[li]];
+              const auto& nd = C.nodes[C.adm[li]];
+              const int owner = X.rows ? nd.t : nd.s;
+              const int64_t roff = T.begin[s] - T.begin[owner];
+              g.task(Dw(X.proj[s][li]), kcap, kc, kcap);
+              g.mm(X.leafout + T.begin[s] * kc, kc, Dw(X.rows ? u.Uh : u.Vh) + roff * kcap, kcap, (int)T.size(s),
+                   h2k::IT_TRANS_A);
+            }
+          } else {
+            const int c0 = T.children[s][0], c1 = T.children[s][1];
+            for (int li : X.star[s]) {
+              g.task(Dw(X.proj[s][li]), kcap, kc, kcap);
+              g.mm(X.trout + (int64_t)c0 * kk, kc, Dw(X.proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
+              g.mm(X.trout + (int64_t)c1 * kk, kc, Dw(X.proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
+            }
           }
         }
       }
     }
   }
-  if (rows) row_proj = std::move(proj);
-  else col_proj = std::move(proj);
+  row_proj = std::move(side[0].proj);
+  col_proj = std::move(side[1].proj);
 }
 
 // ------------------------------------------------------------------ couplings
@@ -2258,10 +2299,8 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   ws("exact");
   pl.coarsen();
   ws("coarsen");
-  pl.basis(true);
-  ws("rows");
-  pl.basis(false);
-  ws("cols");
+  pl.bases();
+  ws("bases");
   pl.couplings();
   P->n_adm = P->cbt.adm.size();
   P->n_inadm = P->cbt.inadm.size();
