@@ -2386,6 +2386,36 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
   H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
   double tph[8] = {0};
   execute(ctx, *P, opt.timing, tph);
+  // while the device works: the result's block tree and one allocation for
+  // its arrays (filled by device copies once the product is done)
+  auto Cm = std::make_unique<Matrix>();
+  Cm->ctx = ctx;
+  Cm->hold = ctx->self.lock();
+  Cm->id = ctx->next_id++;
+  Cm->rows = X->rows;
+  Cm->cols = Y->cols;
+  build_block_tree(Cm->bt, *X->rows, *Y->cols, X->bt.eta);
+  Cm->kc = kc;
+  Cm->w_is_v = false;
+  const int64_t n_vleaf = X->rows->n * kc, n_vtr = (int64_t)X->rows->ncl * kc * kc, n_wleaf = Y->cols->n * kc,
+                n_wtr = (int64_t)Y->cols->ncl * kc * kc, n_s = (int64_t)P->cbt.adm.size() * kc * kc,
+                n_n = P->cnsize;
+  auto pad = [](int64_t c) { return (std::max<int64_t>(c, 1) + 31) & ~int64_t(31); };
+  Cm->bufs.emplace_back(new DevBuf);
+  Cm->bufs.back()->alloc((size_t)(pad(n_vleaf) + pad(n_vtr) + pad(n_wleaf) + pad(n_wtr) + pad(n_s) + pad(n_n)) *
+                         sizeof(double));
+  double* carve = Cm->bufs.back()->as<double>();
+  auto take = [&](int64_t c) {
+    double* d = carve;
+    carve += pad(c);
+    return d;
+  };
+  Cm->V.leaf = take(n_vleaf);
+  Cm->V.transfer = take(n_vtr);
+  Cm->W.leaf = take(n_wleaf);
+  Cm->W.transfer = take(n_wtr);
+  Cm->S = take(n_s);
+  Cm->N = take(n_n);
   int ovf = 0;
   H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   H2_HIP(hipStreamSynchronize(ctx->stream));
@@ -2411,27 +2441,16 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
     throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "coarsened rank above coarse_rank cap"
                                              : "basis rank above max_rank cap");
   }
-  // result matrix owning copies of the result arrays
-  auto Cm = std::make_unique<Matrix>();
-  Cm->ctx = ctx;
-  Cm->hold = ctx->self.lock();
-  Cm->id = ctx->next_id++;
-  Cm->rows = X->rows;
-  Cm->cols = Y->cols;
-  build_block_tree(Cm->bt, *X->rows, *Y->cols, X->bt.eta);
-  Cm->kc = kc;
-  Cm->w_is_v = false;
-  auto cp = [&](const DRef<double>& src, int64_t count) {
-    double* d = Cm->alloc64(std::max<int64_t>(count, 1));
+  // the result matrix owns copies of the result arrays
+  auto cp = [&](double* d, const DRef<double>& src, int64_t count) {
     if (count) H2_HIP(hipMemcpyAsync(d, res(src, *P), count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-    return d;
   };
-  Cm->V.leaf = cp(P->res_vleaf, X->rows->n * kc);
-  Cm->V.transfer = cp(P->res_vtr, (int64_t)X->rows->ncl * kc * kc);
-  Cm->W.leaf = cp(P->res_wleaf, Y->cols->n * kc);
-  Cm->W.transfer = cp(P->res_wtr, (int64_t)Y->cols->ncl * kc * kc);
-  Cm->S = cp(P->res_S, (int64_t)P->cbt.adm.size() * kc * kc);
-  Cm->N = cp(P->res_N, P->cnsize);
+  cp(Cm->V.leaf, P->res_vleaf, n_vleaf);
+  cp(Cm->V.transfer, P->res_vtr, n_vtr);
+  cp(Cm->W.leaf, P->res_wleaf, n_wleaf);
+  cp(Cm->W.transfer, P->res_wtr, n_wtr);
+  cp(Cm->S, P->res_S, n_s);
+  cp(Cm->N, P->res_N, n_n);
   Cm->noff = P->cnoff;
   Cm->nsize = P->cnsize;
   Cm->rank_row.resize(X->rows->ncl);
