@@ -399,14 +399,86 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
-// Sum over the G consecutive lanes of a group (G a power of two <= 64).
+// Sum over the G consecutive lanes of a group (G a power of two <= 16).
 template <int G>
 __device__ inline double group_sum(double v) {
   static_assert(G <= 16, "groups within a DPP row");
   return dpp_group_sum(v, G);
 }
 
-
+// Sweeps of one-sided Jacobi on the columns of M (M[c * LD + r], rows x
+// cols) with round-robin pair ordering.  The G consecutive lanes of a group
+// share a pair: each lane keeps its K rows of both columns in registers
+// between the three dot products and the rotation.  One barrier per round.
+// Returns the number of sweeps (at most 40; the last one without rotations
+// unless the cap was reached).
+template <int WMAX, int NT, int G>
+__device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot) {
+  constexpr int LD = WMAX + 1;
+  constexpr int K = (WMAX + G - 1) / G;
+  const int tid = threadIdx.x;
+  const int np = (cols + 1) & ~1;  // players incl. a dummy when cols is odd
+  const int npairs = np / 2, m1 = np - 1;
+  const int grp = tid / G, gl = tid % G;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
+    if (tid == 0) *sh_rot = 0;
+    __syncthreads();
+    for (int rnd = 0; rnd < m1; ++rnd) {
+      for (int g = grp; g < npairs; g += NT / G) {
+        int p, q;
+        if (g == 0) {
+          p = m1;
+          q = rnd;
+        } else {
+          p = rnd + g;
+          if (p >= m1) p -= m1;
+          q = rnd - g;
+          if (q < 0) q += m1;
+        }
+        if (p >= cols || q >= cols) continue;  // the dummy player (whole group)
+        double* cp = M + p * LD;
+        double* cq = M + q * LD;
+        double x[K], y[K];
+        double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int r = gl + k * G;
+          x[k] = r < rows ? cp[r] : 0.0;
+          y[k] = r < rows ? cq[r] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          a += x[k] * x[k];
+          b += y[k] * y[k];
+          c += x[k] * y[k];
+        }
+        a = dpp_group_sum(a, G);
+        b = dpp_group_sum(b, G);
+        c = dpp_group_sum(c, G);
+        if (c != 0.0 && c * c > 1e-30 * (a * b)) {
+          const double zeta = (b - a) / (2.0 * c);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int r = gl + k * G;
+            if (r < rows) {
+              cp[r] = cs * x[k] - sn * y[k];
+              cq[r] = sn * x[k] + cs * y[k];
+            }
+          }
+          if (gl == 0) *sh_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    if (!*sh_rot) break;
+    __syncthreads();
+  }
+  return sweeps;
+}
 
 // Truncated SVD (left singular vectors) of a small matrix A (rows x cols).
 //
@@ -422,22 +494,22 @@ __device__ inline double group_sum(double v) {
 // Without such a threshold A itself goes to the Jacobi.
 //
 // Jacobi: M[c * LD + r] holds column c (contiguous rows); the odd stride keeps
-// lanes that read different columns on different LDS banks.  Round-robin
-// pairs, G lanes per pair, one barrier per round.
+// lanes that read different columns on different LDS banks.
 template <int WMAX, int NT>
 __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo) {
   constexpr int LD = WMAX + 1;
   constexpr int TPC = NT / WMAX;  // lanes per column of A^T in the rank reveal
   constexpr int RPL = WMAX / TPC; // rows per lane
-  constexpr int NR = NT / 16;  // DPP rows of the workgroup
+  constexpr int NR = NT / 16;     // DPP rows of the workgroup
+  constexpr int NW = NT / 64;     // waves of the workgroup
   static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && NT % 64 == 0, "launch shape");
   __shared__ double M[WMAX * LD];
-  __shared__ double nrm[WMAX];
+  __shared__ double nrm[WMAX], snrm[WMAX], inv[WMAX];
   __shared__ int order[WMAX];
-  __shared__ double vb[WMAX];
+  __shared__ double vb[WMAX];  // reflector, lane-major: vb[sub * RPL + q] is row sub + TPC q
   __shared__ double red[NR], wmx[NR];
   __shared__ int widx[NR];
-  __shared__ int sh_rot;
+  __shared__ int sh_rot, sh_keep;
   __shared__ double sh_tau, sh_scal;
   const SvdTask tk = tasks[blockIdx.x];
   const bool sq = tk.w_dev || tk.w_dev2;
@@ -490,12 +562,14 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       int r = 0;
       const int jmax = nl < ni ? nl : ni;
       for (int j = 0; j < jmax; ++j) {
-        // remaining Frobenius norm and pivot (largest column, lowest index on ties)
+        // remaining Frobenius norm and pivot (largest column, lowest index on
+        // ties): DPP within rows of 16 lanes, lane shuffles across the four
+        // rows of a wave, then the NW wave results through LDS
         const bool act = l < nl && done < 0;
         double v = act ? cn : -1.0, sv = (act && sub == 0) ? cn : 0.0;
         int id = act ? l : WMAX;
         sv = dpp_group_sum(sv, 16);
-        {  // argmax within the row of 16 lanes
+        {
           double ov = dpp_mov<0xB1>(v);
           int oi = dpp_mov_int<0xB1>(id);
           if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
@@ -508,16 +582,24 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
           ov = dpp_mov<0x140>(v);
           oi = dpp_mov_int<0x140>(id);
           if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+#pragma unroll
+          for (int off = 16; off < 64; off <<= 1) {
+            sv += __shfl_xor(sv, off);
+            ov = __shfl_xor(v, off);
+            oi = __shfl_xor(id, off);
+            if (ov > v || (ov == v && oi < id)) { v = ov; id = oi; }
+          }
         }
-        if ((lane & 15) == 0) {
-          red[tid >> 4] = sv;
-          wmx[tid >> 4] = v;
-          widx[tid >> 4] = id;
+        if (lane == 0) {
+          red[wv] = sv;
+          wmx[wv] = v;
+          widx[wv] = id;
         }
         __syncthreads();
         double tot = 0.0, bv = -1.0;
         int p = WMAX;
-        for (int w = 0; w < NR; ++w) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
           tot += red[w];
           if (wmx[w] > bv || (wmx[w] == bv && widx[w] < p)) {
             bv = wmx[w];
@@ -549,7 +631,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
 #pragma unroll
           for (int q = 0; q < RPL; ++q) {
             const int i = sub + TPC * q;
-            vb[i] = i > j ? x[q] : 0.0;
+            vb[sub * RPL + q] = i > j ? x[q] : 0.0;
           }
           if (sub == 0) {
             sh_tau = tau;
@@ -562,11 +644,13 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
           const double tau = sh_tau, scal = sh_scal;
           if (tau != 0.0) {
             double xj = 0.0, dot = 0.0;
+            double w[RPL];
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
               const int i = sub + TPC * q;
+              w[q] = vb[sub * RPL + q];
               if (i == j) xj = x[q];
-              dot += vb[i] * x[q];
+              dot += w[q] * x[q];
             }
             xj = group_sum<TPC>(xj);
             dot = group_sum<TPC>(dot);
@@ -575,7 +659,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
               const int i = sub + TPC * q;
-              x[q] -= f * vb[i];
+              x[q] -= f * w[q];
               if (i == j) x[q] -= tau * full;
             }
           }
@@ -601,51 +685,12 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
     __syncthreads();
   }
   if (!empty) {
-    const int np = (cols + 1) & ~1;  // players incl. a dummy when cols is odd
-    const int npairs = np / 2;
-    // G threads (consecutive lanes of one wave, at most a DPP row of 16)
-    // share a pair
-    int G = 16;
-    while (G > 1 && npairs * G > NT) G >>= 1;
-    const int grp = tid / G, gl = tid % G;
-    for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
-      if (tid == 0) sh_rot = 0;
-      __syncthreads();
-      for (int rnd = 0; rnd < np - 1; ++rnd) {
-        for (int g = grp; g < npairs; g += NT / G) {
-          int p, q;
-          if (g == 0) { p = np - 1; q = rnd; }
-          else { p = (rnd + g) % (np - 1); q = (rnd - g + (np - 1)) % (np - 1); }
-          const bool valid = p < cols && q < cols;
-          double a = 0.0, b = 0.0, c = 0.0;
-          double* cp = M + (valid ? p : 0) * LD;
-          double* cq = M + (valid ? q : 0) * LD;
-          if (valid)
-            for (int r = gl; r < rows; r += G) {
-              double x = cp[r], y = cq[r];
-              a += x * x; b += y * y; c += x * y;
-            }
-          a = dpp_group_sum(a, G);
-          b = dpp_group_sum(b, G);
-          c = dpp_group_sum(c, G);
-          if (valid && c != 0.0 && c * c > 1e-30 * (a * b)) {
-            double zeta = (b - a) / (2.0 * c);
-            double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-            for (int r = gl; r < rows; r += G) {
-              double x = cp[r], y = cq[r];
-              cp[r] = cs * x - sn * y;
-              cq[r] = sn * x + cs * y;
-            }
-            if (gl == 0) sh_rot = 1;
-          }
-        }
-        __syncthreads();
-      }
-      ++sweeps;
-      if (!sh_rot) break;
-      __syncthreads();
-    }
+    // G lanes per pair, at most a DPP row of 16, all pairs of a round at once
+    // (2 TPC lanes per pair always fit: at most WMAX / 2 pairs)
+    const int npairs = ((cols + 1) & ~1) / 2;
+    if (npairs * 16 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
+    else if (npairs * 8 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 8>(M, rows, cols, &sh_rot);
+    else sweeps = jacobi_sweeps<WMAX, NT, (2 * TPC < 8 ? 2 * TPC : 8)>(M, rows, cols, &sh_rot);
   }
   if (tk.stat && tid == 0) {
     tk.stat[0] = rows;
@@ -654,61 +699,76 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
     tk.stat[3] = sweeps;
   }
   const int c_all = sq ? we : tk.cols;  // number of singular values reported
-  for (int c = tid; c < c_all; c += NT) {
+  // column norms, 16 lanes per column
+  for (int c = tid / 16; c < c_all; c += NT / 16) {
     double v = 0.0;
     if (!empty && c < cols)
-      for (int r = 0; r < rows; ++r) v += M[c * LD + r] * M[c * LD + r];
-    nrm[c] = sqrt(v);
+      for (int r = tid % 16; r < rows; r += 16) v += M[c * LD + r] * M[c * LD + r];
+    v = dpp_group_sum(v, 16);
+    if (tid % 16 == 0) nrm[c] = sqrt(v);
   }
+  if (tid == 0) sh_keep = c_all;
   __syncthreads();
+  // descending order (ties by index); snrm holds the sorted values
   for (int c = tid; c < c_all; c += NT) {
     int rk = 0;
-    double v = nrm[c];
-    for (int d = 0; d < c_all; ++d) rk += (nrm[d] > v) || (nrm[d] == v && d < c);
+    const double v = nrm[c];
+#pragma unroll 8
+    for (int d = 0; d < c_all; ++d) {
+      const double w = nrm[d];
+      rk += (w > v) || (w == v && d < c);
+    }
     order[rk] = c;
+    snrm[rk] = v;
   }
   __syncthreads();
-  const double smax = c_all > 0 ? nrm[order[0]] : 0.0;
+  const double smax = c_all > 0 ? snrm[0] : 0.0;
   const double thr = jthr_scale * (tk.tol_abs + tk.tol_rel * smax + ref);
   int keep = 0;
   if (!tk.frob) {
-    for (int i = 0; i < c_all; ++i) keep += nrm[i] > thr;
+#pragma unroll 8
+    for (int i = 0; i < c_all; ++i) keep += snrm[i] > thr;
   } else {
-    // fewest kept values whose dropped tail has Frobenius norm <= thr
-    double tail = 0.0;
-    keep = c_all;
+    // fewest kept values whose dropped tail has Frobenius norm <= thr: the
+    // tail sums s_i (accumulated from the smallest value up) grow as i
+    // falls, and keep is the smallest i with s_i <= thr^2
     const double thr2 = thr * thr;
-    for (int i = c_all - 1; i >= 0; --i) {
-      double v = nrm[order[i]];
-      if (tail + v * v > thr2) break;
-      tail += v * v;
-      keep = i;
+    for (int i = tid; i < c_all; i += NT) {
+      double tail = 0.0;
+#pragma unroll 8
+      for (int d = c_all - 1; d >= i; --d) tail += snrm[d] * snrm[d];
+      if (tail <= thr2) atomicMin(&sh_keep, i);
     }
+    __syncthreads();
+    keep = sh_keep;
   }
   if (keep > tk.kcap) {
     if (tid == 0 && overflow) atomicOr(overflow, tk.ovf_bit);
     keep = tk.kcap;
   }
   const int sc = sq ? tk.cols : c_all;
-  for (int i = tid; i < sc; i += NT) tk.sigma[i] = i < c_all ? nrm[order[i]] : 0.0;
+  for (int i = tid; i < sc; i += NT) tk.sigma[i] = i < c_all ? snrm[i] : 0.0;
   if (tid == 0) *tk.rank = keep;
-  auto uval = [&](int r, int i) -> double {
-    if (i >= keep || r >= rows) return 0.0;
-    const int c = order[i];
-    return M[c * LD + r] / nrm[c];
-  };
-  if (!tk.u2) {
-    const int ur = sq ? tk.rows : rows;
-    for (int e = tid; e < ur * tk.kcap; e += NT) {
-      int r = e / tk.kcap, i = e - r * tk.kcap;
-      tk.u[(int64_t)r * tk.ldu + i] = uval(r, i);
-    }
-  } else {
-    const int split = tk.split_dev ? *tk.split_dev : 0;
-    for (int e = tid; e < tk.urows * tk.kcap; e += NT) {
-      int r = e / tk.kcap, i = e - r * tk.kcap;
-      tk.u[(int64_t)r * tk.ldu + i] = r < split ? uval(r, i) : 0.0;
-      tk.u2[(int64_t)r * tk.ldu + i] = (split + r < rows) ? uval(split + r, i) : 0.0;
+  for (int i = tid; i < keep; i += NT) inv[i] = 1.0 / snrm[i];
+  __syncthreads();
+  // kept normalised columns; lanes run along the columns of U (coalesced rows)
+  const int kc = tk.kcap;
+  for (int i0 = 0; i0 < kc; i0 += 64) {
+    const int i = i0 + lane;
+    const bool kept = i < keep;
+    const int off = kept ? order[i] * LD : 0;
+    const double s = kept ? inv[i] : 0.0;
+    if (i < kc) {
+      if (!tk.u2) {
+        const int ur = sq ? tk.rows : rows;
+        for (int r = wv; r < ur; r += NW) tk.u[(int64_t)r * tk.ldu + i] = (kept && r < rows) ? M[off + r] * s : 0.0;
+      } else {
+        const int split = tk.split_dev ? *tk.split_dev : 0;
+        for (int r = wv; r < tk.urows; r += NW) {
+          tk.u[(int64_t)r * tk.ldu + i] = (kept && r < split && r < rows) ? M[off + r] * s : 0.0;
+          tk.u2[(int64_t)r * tk.ldu + i] = (kept && split + r < rows) ? M[off + split + r] * s : 0.0;
+        }
+      }
     }
   }
 }
