@@ -56,6 +56,18 @@ constexpr int GBM = 64, GBN = 64, GBK = 16;
 // global loads of slice s + 1 are in flight into registers and then land in
 // the other buffer, so each slice costs one barrier.  A wave whose quarter
 // lies outside the task's (device-side) size skips its MFMAs.
+// Loads and stores through global-address-space pointers: the operands are
+// plain device memory, and global (not flat) instructions are counted only by
+// the vector-memory counter, so waiting on LDS never waits on them.
+template <typename T>
+__device__ inline T gload(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline void gstore(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 template <typename T>
 struct GemmSlice {
   T a[4], b[4];
@@ -76,7 +88,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
   if (tk.roff_dev) tk.c += (int64_t)*tk.roff_dev * tk.ldc;
   if (tl.m0 >= tk.m || tl.n0 >= tk.n) return;  // whole tile outside the device-side size
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
+  const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wm = wv >> 1, wn = wv & 1;
   const int m0 = tl.m0, n0 = tl.n0;
   const bool active = m0 + wm * 32 < tk.m && n0 + wn * 32 < tk.n;
@@ -86,11 +98,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
       for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
 
   // copies (IT_COPY items) go straight into the accumulators
-  int nmm = 0;  // product items
+  int nmm = 0, nsl = 0;  // product items, their 16-wide slices
   for (int it = 0; it < tk.nitem; ++it) {
     const GemmItem<T> item = items[tk.item0 + it];
     if (!(item.flags & IT_COPY)) {
       ++nmm;
+      nsl += (item.k + GBK - 1) / GBK;
       continue;
     }
     double alpha = item.alpha;
@@ -107,7 +120,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
           int row = m0 + wm * 32 + a * 16 + Mfma<T>::row(lane, v);
           int col = n0 + wn * 32 + b * 16 + (lane & 15);
           if (row < tk.m && col < tk.n) {
-            T x = ta ? item.a[(int64_t)col * item.lda + row] : item.a[(int64_t)row * item.lda + col];
+            T x = ta ? gload(item.a + (int64_t)col * item.lda + row) : gload(item.a + (int64_t)row * item.lda + col);
             acc[a][b][v] += al * x;
           }
         }
@@ -137,46 +150,49 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
       }
       return true;
     };
+    // Loads are unconditional (an out-of-range element reads element 0 of the
+    // same operand, replaced by zero when stored), so the eight loads of a
+    // slice issue back to back and stay in flight during the MFMAs.
     auto load = [&](GemmSlice<T>& g) {
       const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
+      const int64_t sa = ta ? 1 : item.lda, ska = ta ? item.lda : 1;
+      const int64_t sb = tb ? item.ldb : 1, skb = tb ? 1 : item.ldb;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
         int i, kk;
         if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
-        int gi = m0 + i, gk = k0 + kk;
-        T x = T(0);
-        if (gi < tk.m && gk < kend)
-          x = ta ? item.a[(int64_t)gk * item.lda + gi] : item.a[(int64_t)gi * item.lda + gk];
-        g.a[q] = al * x;
+        const int gi = m0 + i, gk = k0 + kk;
+        const bool in = gi < tk.m && gk < kend;
+        g.a[q] = gload(item.a + (in ? gi * sa + gk * ska : 0));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
         int j, kk;
         if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
-        int gj = n0 + j, gk = k0 + kk;
-        T x = T(0);
-        if (gj < tk.n && gk < kend)
-          x = tb ? item.b[(int64_t)gj * item.ldb + gk] : item.b[(int64_t)gk * item.ldb + gj];
-        g.b[q] = x;
+        const int gj = n0 + j, gk = k0 + kk;
+        const bool in = gj < tk.n && gk < kend;
+        g.b[q] = gload(item.b + (in ? gj * sb + gk * skb : 0));
       }
     };
-    auto store = [&](const GemmSlice<T>& g, int buf) {
+    auto store = [&](const GemmSlice<T>& g, int buf) {  // same item and k0 as the load
       const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
         int i, kk;
         if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
-        As[buf][kk][i] = g.a[q];
+        const bool in = m0 + i < tk.m && k0 + kk < kend;
+        As[buf][kk][i] = in ? al * g.a[q] : T(0);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         int e = tid + 256 * q;
         int j, kk;
         if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
-        Bs[buf][kk][j] = g.b[q];
+        const bool in = n0 + j < tk.n && k0 + kk < kend;
+        Bs[buf][kk][j] = in ? g.b[q] : T(0);
       }
     };
     k0 = -GBK;
@@ -187,9 +203,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
     store(g, 0);
     __syncthreads();
     int buf = 0;
-    for (;;) {
-      const bool more = advance();
-      if (more) load(g);  // next slice in flight during the MFMAs below
+    // the loop exits at its bottom only, so every path back to its head
+    // passes the store of the loaded slice
+    for (int sl = 1; sl <= nsl; ++sl) {
+      const bool more = sl < nsl;
+      if (more) {
+        advance();
+        load(g);  // next slice in flight during the MFMAs below
+      }
       if (active) {
 #pragma unroll
         for (int kk = 0; kk < GBK; kk += 4) {
@@ -200,10 +221,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
             for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
         }
       }
-      if (!more) break;
-      store(g, buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+      if (more) {
+        store(g, buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
     }
   }
   for (int a = 0; a < 2; ++a)
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
         int col = n0 + wn * 32 + b * 16 + (lane & 15);
         if (row < tk.m && col < tk.n) {
           T* p = tk.c + (int64_t)row * tk.ldc + col;
-          *p = tk.beta ? (*p + acc[a][b][v]) : acc[a][b][v];
+          gstore(p, tk.beta ? T(gload(p) + acc[a][b][v]) : T(acc[a][b][v]));
         }
       }
 }

@@ -159,6 +159,7 @@ struct Step {
   size_t desc_off = 0, desc2_off = 0, tiles_off = 0;
   int ndesc = 0, ntiles = 0;
   double flops = 0, bytes = 0;
+  double flops_tile = 0;  // GEMM: MFMA work incl. padding to 32 x 32 quarters and 16-wide slices
   int64_t stat_off = -1;  // QR / SVD: per-task size reports (int workspace)
 };
 
@@ -337,6 +338,7 @@ struct GW {
     auto& tk = WS<T>::tasks(*s).back();
     tk.nitem++;
     s->flops += 2.0 * tk.m * tk.n * k;
+    s->flops_tile += 2.0 * ((tk.m + 31) & ~31) * ((tk.n + 31) & ~31) * ((k + 15) & ~15);
     s->bytes += (double)sizeof(T) * ((double)tk.m * k + (double)k * tk.n);
   }
   void copy(DRef<T> a, int lda, int flags = 0, double alpha = 1.0) {
@@ -619,12 +621,44 @@ void Planner::phaseA() {
   for (int i = 0; i < 4; ++i)
     if (uniq[alias[i]] != all[i]) all[i]->lvl = uniq[alias[i]]->lvl;
   // ---------------- basis products P_s = W_{X,s}^* V_{Y,s} (Section 4.1) ----------------
+  // Only clusters that carry an admissible block of X (column) or Y (row)
+  // need P_s.  A sum over |s| > KS rows is split into row chunks of KS whose
+  // partial products are added by a second step, so no single tile walks a
+  // long K range.
   DRef<T> Pm = W((int64_t)TJ.ncl * kk);
   {
+    constexpr int KS = 256;
+    std::vector<char> need(TJ.ncl, 0);
+    for (int node : bx.adm) need[bx.nodes[node].s] = 1;
+    for (int node : by.adm) need[by.nodes[node].t] = 1;
+    int64_t nparts = 0;
+    for (int s = 0; s < TJ.ncl; ++s)
+      if (need[s] && TJ.size(s) > KS) nparts += (TJ.size(s) + KS - 1) / KS;
+    DRef<T> Pp = nparts ? W(nparts * kk) : DRef<T>();
     GW<T> g = newstep();
+    int64_t part = 0;
     for (int s = 0; s < TJ.ncl; ++s) {
-      g.task(Pm + (int64_t)s * kk, kY, kX, kY);
-      g.mm(WX.full(s), kX, VY.full(s), kY, (int)TJ.size(s), h2k::IT_TRANS_A);
+      if (!need[s]) continue;
+      const int ns = (int)TJ.size(s);
+      if (ns <= KS) {
+        g.task(Pm + (int64_t)s * kk, kY, kX, kY);
+        g.mm(WX.full(s), kX, VY.full(s), kY, ns, h2k::IT_TRANS_A);
+        continue;
+      }
+      for (int r0 = 0; r0 < ns; r0 += KS, ++part) {
+        g.task(Pp + part * kk, kY, kX, kY);
+        g.mm(WX.full(s) + (int64_t)r0 * kX, kX, VY.full(s) + (int64_t)r0 * kY, kY, std::min(KS, ns - r0),
+             h2k::IT_TRANS_A);
+      }
+    }
+    if (nparts) {
+      GW<T> g2 = newstep();
+      part = 0;
+      for (int s = 0; s < TJ.ncl; ++s) {
+        if (!need[s] || TJ.size(s) <= KS) continue;
+        g2.task(Pm + (int64_t)s * kk, kY, kX, kY);
+        for (int64_t r0 = 0; r0 < TJ.size(s); r0 += KS, ++part) g2.copy(Pp + part * kk, kY);
+      }
     }
   }
   auto Pref = [&](int s) { return Pm + (int64_t)s * kk; };
@@ -2176,9 +2210,10 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
       static const char* kname[] = {"gemm64", "gemm32", "qr", "svd", "chol", "fill", "cvt", "ref", "scan"};
       for (size_t i = 0; i < P.steps.size(); ++i) {
         const Step& st = P.steps[i];
-        std::fprintf(stderr, "[h2 step %3zu] phase %d %-6s tasks %7d tiles %8d wmax %4d  %9.3f ms  %.3g GF %.3g GB\n",
+        std::fprintf(stderr,
+                     "[h2 step %3zu] phase %d %-6s tasks %7d tiles %8d wmax %4d  %9.3f ms  %.3g GF %.3g GB  tile GF %.3g\n",
                      i, st.phase, kname[(int)st.kind], st.ndesc, st.ntiles, st.wmax, step_ms[i], st.flops * 1e-9,
-                     st.bytes * 1e-9);
+                     st.bytes * 1e-9, st.flops_tile * 1e-9);
       }
     }
   }
@@ -2188,7 +2223,9 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
     H2_HIP(hipStreamSynchronize(s));
     std::vector<int> stat;
     double svs[3][5] = {{0}};
+    size_t stepno = 0;
     for (auto& st : P.steps) {
+      ++stepno;
       const int kind = (int)st.kind;
       if (kind == SK_QR || kind == SK_SVD) {
         const int per = kind == SK_QR ? 2 : 4;
@@ -2197,6 +2234,20 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
         if (n)
           H2_HIP(hipMemcpy(stat.data(), P.bufi.as<int>() + st.stat_off, per * n * sizeof(int),
                            hipMemcpyDeviceToHost));
+        if (kind == SK_SVD && n && std::getenv("H2_TRACE")) {  // per-step shape summary
+          double sm[4] = {0, 0, 0, 0};
+          int mx[4] = {0, 0, 0, 0};
+          for (size_t i = 0; i < n; ++i) {
+            for (int c = 0; c < 4; ++c) {
+              sm[c] += stat[4 * i + c];
+              mx[c] = std::max(mx[c], stat[4 * i + c]);
+            }
+          }
+          std::fprintf(stderr,
+                       "[h2 svd step %3zu] tasks %zu  mean/max rows %.1f/%d cols %.1f/%d jacobi cols %.1f/%d "
+                       "sweeps %.2f/%d\n",
+                       stepno - 1, n, sm[0] / n, mx[0], sm[1] / n, mx[1], sm[2] / n, mx[2], sm[3] / n, mx[3]);
+        }
         for (size_t i = 0; i < n; ++i) {
           if (kind == SK_QR) {
             const double m = stat[2 * i], w = stat[2 * i + 1];
