@@ -312,14 +312,17 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
   const int tid = threadIdx.x, sub = tid % TPC, l = tid / TPC;
   for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
 
-  // reflector of column c from (alpha = R[c][c], the group's chunk registers)
+  // reflector of column c from (alpha = R[c][c], the group's chunk registers);
+  // the vector goes to LDS lane-major (vb[slot][sub * RPT + q] is chunk row
+  // sub + TPC q), so each lane moves contiguous runs
   auto reflect = [&](const double* c, int col, int slot) {
-    double x2 = 0.0;
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) x2 += c[q] * c[q];
-    x2 = dpp_group_sum(x2, TPC);
     const int pd = pk(col, col, we);
     const double alpha = R[pd];
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: a shorter dependent chain
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) s4[q & 3] += c[q] * c[q];
+    double x2 = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    x2 = dpp_group_sum(x2, TPC);
     double tau = 0.0, scal = 0.0;
     if (x2 != 0.0) {
       const double nrm = sqrt(alpha * alpha + x2);
@@ -329,7 +332,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
       if (sub == 0) R[pd] = beta;
     }
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) vb[slot][sub + TPC * q] = c[q];
+    for (int q = 0; q < RPT; ++q) vb[slot][sub * RPT + q] = c[q];
     if (sub == 0) {
       tb[slot][0] = tau;
       tb[slot][1] = scal;
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       const int i = sub + TPC * q;
-      c[q] = (i < cr && l < we) ? tk.a[(int64_t)(r0 + i) * tk.lda + l] : 0.0;
+      c[q] = (i < cr && l < we) ? gload(tk.a + (int64_t)(r0 + i) * tk.lda + l) : 0.0;
     }
     __syncthreads();  // R of the previous chunk complete, both slots free
     if (l == 0) reflect(c, 0, 0);
@@ -350,18 +353,24 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
     for (int j = 0; j < we; ++j) {
       const int b = j & 1;
       if (l > j && l < we) {
+        const int p = pk(j, l, we);
+        const double rjl = R[p];
         const double tau = tb[b][0], scal = tb[b][1];
         if (tau != 0.0) {
-          double dot = 0.0;
+          double w[RPT];
+          double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) dot += vb[b][sub + TPC * q] * c[q];
+          for (int q = 0; q < RPT; ++q) {
+            w[q] = vb[b][sub * RPT + q];
+            d4[q & 3] += w[q] * c[q];
+          }
+          double dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
           dot = dpp_group_sum(dot, TPC);
-          const int p = pk(j, l, we);
-          const double full = R[p] + scal * dot;
+          const double full = rjl + scal * dot;
           const double f = tau * scal * full;
 #pragma unroll
-          for (int q = 0; q < RPT; ++q) c[q] -= f * vb[b][sub + TPC * q];
-          if (sub == 0) R[p] -= tau * full;
+          for (int q = 0; q < RPT; ++q) c[q] -= f * w[q];
+          if (sub == 0) R[p] = rjl - tau * full;
         }
         if (l == j + 1) reflect(c, j + 1, b ^ 1);
       }
@@ -583,7 +592,19 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       int done = -1;     // step at which this column was the pivot
       int r = 0;
       const int jmax = nl < ni ? nl : ni;
+      // The registers hold a window of rows: lane sub keeps rows
+      // j0 + sub + TPC q (j0 = j rounded down to a multiple of TPC), so row j
+      // sits in x[0] of lane j % TPC.  A finished row leaves the registers
+      // (its R entry goes straight to M, the register is zeroed), and every
+      // TPC steps the window moves on; sums and updates then run over all
+      // registers without per-row predicates.
       for (int j = 0; j < jmax; ++j) {
+        const int sj = j % TPC;
+        if (j > 0 && sj == 0) {
+#pragma unroll
+          for (int q = 0; q + 1 < RPL; ++q) x[q] = x[q + 1];
+          x[RPL - 1] = 0.0;
+        }
         // remaining Frobenius norm and pivot (largest column, lowest index on
         // ties): DPP within rows of 16 lanes, lane shuffles across the four
         // rows of a wave, then the NW wave results through LDS
@@ -631,76 +652,60 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
         if (tot <= tq * tq) break;
         r = j + 1;
         if (l == p) {  // reflector of the pivot column on rows >= j
-          double xj = 0.0, x2 = 0.0;
+          const double xj = group_sum<TPC>(sub == sj ? x[0] : 0.0);
+          if (sub == sj) x[0] = 0.0;
+          double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int q = 0; q < RPL; ++q) {
-            const int i = sub + TPC * q;
-            if (i == j) xj = x[q];
-            if (i > j) x2 += x[q] * x[q];
-          }
-          xj = group_sum<TPC>(xj);
-          x2 = group_sum<TPC>(x2);
-          double tau = 0.0, scal = 0.0;
+          for (int q = 0; q < RPL; ++q) s4[q & 3] += x[q] * x[q];
+          const double x2 = group_sum<TPC>((s4[0] + s4[1]) + (s4[2] + s4[3]));
+          double tau = 0.0, scal = 0.0, beta = xj;
           if (x2 != 0.0) {
             const double nn = sqrt(xj * xj + x2);
-            const double beta = xj >= 0.0 ? -nn : nn;
+            beta = xj >= 0.0 ? -nn : nn;
             tau = (beta - xj) / beta;
             scal = 1.0 / (xj - beta);
-#pragma unroll
-            for (int q = 0; q < RPL; ++q)
-              if (sub + TPC * q == j) x[q] = beta;
           }
 #pragma unroll
-          for (int q = 0; q < RPL; ++q) {
-            const int i = sub + TPC * q;
-            vb[sub * RPL + q] = i > j ? x[q] : 0.0;
-          }
+          for (int q = 0; q < RPL; ++q) vb[sub * RPL + q] = x[q];
           if (sub == 0) {
             sh_tau = tau;
             sh_scal = scal;
+            M[j * LD + l] = beta;
           }
           done = j;
         }
         __syncthreads();
         if (l < nl && done < 0) {  // apply to the remaining columns
           const double tau = sh_tau, scal = sh_scal;
+          const double xj = group_sum<TPC>(sub == sj ? x[0] : 0.0);
+          double rjl = xj;  // R entry of row j
           if (tau != 0.0) {
-            double xj = 0.0, dot = 0.0;
             double w[RPL];
+            double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
-              const int i = sub + TPC * q;
               w[q] = vb[sub * RPL + q];
-              if (i == j) xj = x[q];
-              dot += w[q] * x[q];
+              d4[q & 3] += w[q] * x[q];
             }
-            xj = group_sum<TPC>(xj);
-            dot = group_sum<TPC>(dot);
+            const double dot = group_sum<TPC>((d4[0] + d4[1]) + (d4[2] + d4[3]));
             const double full = xj + scal * dot;
             const double f = tau * scal * full;
 #pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-              const int i = sub + TPC * q;
-              x[q] -= f * w[q];
-              if (i == j) x[q] -= tau * full;
-            }
+            for (int q = 0; q < RPL; ++q) x[q] -= f * w[q];
+            rjl = xj - tau * full;
           }
-          double c2 = 0.0;
+          if (sub == 0) M[j * LD + l] = rjl;
+          if (sub == sj) x[0] = 0.0;
+          double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int q = 0; q < RPL; ++q)
-            if (sub + TPC * q > j) c2 += x[q] * x[q];
-          cn = group_sum<TPC>(c2);
+          for (int q = 0; q < RPL; ++q) s4[q & 3] += x[q] * x[q];
+          cn = group_sum<TPC>((s4[0] + s4[1]) + (s4[2] + s4[3]));
         }
       }
-      // Jacobi matrix (nl x r): column i, row l = R[i][l]; a pivoted column
-      // keeps its reflector below its step, which is not part of R
-      if (l < nl) {
-#pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-          const int i = sub + TPC * q;
-          if (i < r) M[i * LD + l] = (done < 0 || i <= done) ? x[q] : 0.0;
-        }
-      }
+      // Jacobi matrix (nl x r): column i, row l = R[i][l], written step by
+      // step above; a pivoted column has no entries below its step
+      if (l < nl && done >= 0)
+        for (int i = done + 1 + sub; i < r; i += TPC) M[i * LD + l] = 0.0;
       cols = r;
       jthr_scale = 0.75;
     }
