@@ -300,7 +300,8 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
   constexpr int CH = RPT * TPC;   // chunk rows
   static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 64, "lanes per column");
   __shared__ double R[WMAX * (WMAX + 1) / 2];
-  __shared__ double vb[2][CH];
+  constexpr int VS = RPT + 2;  // padded run per lane: the TPC runs start on different LDS banks
+  __shared__ double vb[2][TPC * VS];
   __shared__ double tb[2][2];
   const QrTask tk = tasks[blockIdx.x];
   const int we = eff_width(tk.w, tk.w_dev, tk.w_dev2);
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
   for (int e = tid; e < we * (we + 1) / 2; e += NT) R[e] = 0.0;
 
   // reflector of column c from (alpha = R[c][c], the group's chunk registers);
-  // the vector goes to LDS lane-major (vb[slot][sub * RPT + q] is chunk row
+  // the vector goes to LDS lane-major (vb[slot][sub * VS + q] is chunk row
   // sub + TPC q), so each lane moves contiguous runs
   auto reflect = [&](const double* c, int col, int slot) {
     const int pd = pk(col, col, we);
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
       if (sub == 0) R[pd] = beta;
     }
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) vb[slot][sub * RPT + q] = c[q];
+    for (int q = 0; q < RPT; ++q) vb[slot][sub * VS + q] = c[q];
     if (sub == 0) {
       tb[slot][0] = tau;
       tb[slot][1] = scal;
@@ -361,7 +362,7 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
           double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int q = 0; q < RPT; ++q) {
-            w[q] = vb[b][sub * RPT + q];
+            w[q] = vb[b][sub * VS + q];
             d4[q & 3] += w[q] * c[q];
           }
           double dot = (d4[0] + d4[1]) + (d4[2] + d4[3]);
@@ -537,7 +538,8 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   __shared__ double M[WMAX * LD];
   __shared__ double nrm[WMAX], snrm[WMAX], inv[WMAX];
   __shared__ int order[WMAX];
-  __shared__ double vb[WMAX];  // reflector, lane-major: vb[sub * RPL + q] is row sub + TPC q
+  constexpr int VS = RPL + 2;  // padded run per lane: the TPC runs start on different LDS banks
+  __shared__ double vb[TPC * VS];  // reflector, lane-major: vb[sub * VS + q] is row sub + TPC q
   __shared__ double red[NR], wmx[NR];
   __shared__ int widx[NR];
   __shared__ int sh_rot, sh_keep;
@@ -666,7 +668,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
             scal = 1.0 / (xj - beta);
           }
 #pragma unroll
-          for (int q = 0; q < RPL; ++q) vb[sub * RPL + q] = x[q];
+          for (int q = 0; q < RPL; ++q) vb[sub * VS + q] = x[q];
           if (sub == 0) {
             sh_tau = tau;
             sh_scal = scal;
@@ -684,7 +686,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
             double d4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < RPL; ++q) {
-              w[q] = vb[sub * RPL + q];
+              w[q] = vb[sub * VS + q];
               d4[q & 3] += w[q] * x[q];
             }
             const double dot = group_sum<TPC>((d4[0] + d4[1]) + (d4[2] + d4[3]));
