@@ -77,8 +77,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
                                                    const GemmTask<T>* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles) {
-  __shared__ T As[2][GBK][GBM + 4];
-  __shared__ T Bs[2][GBK][GBN + 4];
+  __shared__ T As[2][GBK][GBM + 1];  // odd row stride: the 16 lanes that store one column of a slice hit distinct banks
+  __shared__ T Bs[2][GBK][GBN + 1];
   typedef typename Mfma<T>::acc acc_t;
   const GemmTile tl = tiles[blockIdx.x];
   GemmTask<T> tk = tasks[tl.task];
@@ -267,6 +267,13 @@ __device__ inline double dpp_group_sum(double v, int g) {
   if (g >= 16) v += dpp_mov<0x140>(v); // row_mirror
   return v;
 }
+// Ordering of LDS accesses between the lanes of one wave (no workgroup barrier).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CTRL>
 __device__ inline int dpp_mov_int(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
@@ -816,64 +823,72 @@ void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipSt
 // ---------------------------------------------------------------------------
 // Scaled Cholesky orthonormalisation step.
 // ---------------------------------------------------------------------------
+// One wave per task; lane l owns column l.  H holds the scaled Gram matrix,
+// then the upper Cholesky factor U in its upper triangle; the inverse
+// X = U^-1 is built in the strict lower triangle (X[i][l] at H[l][i]) with
+// its diagonal in xd.  Every loop runs over a row or column index shared by
+// all lanes (a lane outside the range is idle), so the LDS reads of U are
+// broadcasts and consecutive iterations are independent.
 template <int WMAX>
 __global__ __launch_bounds__(64) void chol_kernel(const CholTask* __restrict__ tasks) {
   __shared__ double H[WMAX][WMAX + 1];
-  __shared__ double Ri[WMAX][WMAX + 1];
-  __shared__ double d[WMAX];
+  __shared__ double d[WMAX], xd[WMAX];
   const CholTask tk = tasks[blockIdx.x];
-  const int w = tk.w, tid = threadIdx.x;
+  const int w = tk.w, l = threadIdx.x;
   const int we = tk.weff ? min(*tk.weff, w) : w;
-  for (int i = tid; i < w; i += 64) {
-    double g = (i < we) ? tk.g[(int64_t)i * tk.ldg + i] : 0.0;
-    d[i] = g > 0.0 ? sqrt(g) : 0.0;
+  if (l < w) {
+    const double g = (l < we) ? gload(tk.g + (int64_t)l * tk.ldg + l) : 0.0;
+    d[l] = g > 0.0 ? sqrt(g) : 0.0;
   }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += 64) {
-    int i = e / w, l = e - i * w;
-    double v = 0.0;
-    if (i < we && l < we) {
-      if (d[i] > 0.0 && d[l] > 0.0) v = tk.g[(int64_t)i * tk.ldg + l] / (d[i] * d[l]);
-      else v = (i == l) ? 1.0 : 0.0;
-    } else if (i == l) {
-      v = 1.0;
+  wave_sync();
+  if (l < w) {
+    const double dl = d[l];
+    for (int i = 0; i < w; ++i) {
+      double v = 0.0;
+      if (i < we && l < we) {
+        if (d[i] > 0.0 && dl > 0.0) v = gload(tk.g + (int64_t)i * tk.ldg + l) / (d[i] * dl);
+        else v = (i == l) ? 1.0 : 0.0;
+      } else if (i == l) {
+        v = 1.0;
+      }
+      H[i][l] = v;
     }
-    H[i][l] = v;
-    Ri[i][l] = 0.0;
   }
-  __syncthreads();
-  // right-looking Cholesky of the leading we x we block (identity beyond),
-  // upper factor stored in the upper triangle of H
+  wave_sync();
+  // right-looking Cholesky of the leading we x we block (identity beyond)
   for (int j = 0; j < we; ++j) {
-    if (tid == 0) H[j][j] = sqrt(fmax(H[j][j], 1e-300));
-    __syncthreads();
-    for (int l = j + 1 + tid; l < we; l += 64) H[j][l] /= H[j][j];
-    __syncthreads();
-    for (int e = tid; e < (we - j - 1) * (we - j - 1); e += 64) {
-      int i = j + 1 + e / (we - j - 1), l = j + 1 + e % (we - j - 1);
-      if (l >= i) H[i][l] -= H[j][i] * H[j][l];
+    const double piv = sqrt(fmax(H[j][j], 1e-300));
+    if (l >= j && l < we) H[j][l] = (l == j) ? piv : H[j][l] / piv;
+    wave_sync();
+    if (l > j && l < we) {
+      const double ujl = H[j][l];
+      for (int i = j + 1; i <= l; ++i) H[i][l] -= H[j][i] * ujl;
     }
-    __syncthreads();
+    wave_sync();
   }
-  // inverse of the upper factor, one column per thread (back substitution)
-  for (int l = tid; l < we; l += 64) {
-    for (int i = l; i >= 0; --i) {
+  // X = U^-1, row by row from the bottom: X[i][l] = (delta_il - sum_{k=i+1..l} U[i][k] X[k][l]) / U[i][i]
+  for (int i = we - 1; i >= 0; --i) {
+    if (l >= i && l < we) {
       double s = (i == l) ? 1.0 : 0.0;
-      for (int k2 = i + 1; k2 <= l; ++k2) s -= H[i][k2] * Ri[k2][l];
-      Ri[i][l] = s / H[i][i];
+      for (int k = i + 1; k <= l; ++k) s -= H[i][k] * (k == l ? xd[l] : H[l][k]);
+      const double x = s / H[i][i];
+      if (i == l) xd[l] = x;
+      else H[l][i] = x;
     }
   }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += 64) {
-    int i = e / w, l = e - i * w;
-    bool in = i < we && l < we;
-    double tv = 0.0, rv = 0.0;
-    if (in && l >= i) {
-      tv = d[i] > 0.0 ? Ri[i][l] / d[i] : 0.0;
-      rv = H[i][l] * d[l];
+  wave_sync();
+  if (l < w) {
+    const double dl = d[l];
+    for (int i = 0; i < w; ++i) {
+      const bool in = i < we && l < we && l >= i;
+      double tv = 0.0, rv = 0.0;
+      if (in) {
+        tv = d[i] > 0.0 ? (i == l ? xd[l] : H[l][i]) / d[i] : 0.0;
+        rv = H[i][l] * dl;
+      }
+      tk.t[(int64_t)i * tk.ldt + l] = tv;
+      tk.r[(int64_t)i * tk.ldr + l] = rv;
     }
-    tk.t[(int64_t)i * tk.ldt + l] = tv;
-    tk.r[(int64_t)i * tk.ldr + l] = rv;
   }
 }
 

@@ -324,6 +324,7 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(svd_test(s, 128, overflow, 1));
   e.push_back(chol_test(s, 12, 200));
   e.push_back(chol_test(s, 32, 300));
+  e.push_back(chol_test(s, 50, 400));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
   return (int)e.size();
 }
