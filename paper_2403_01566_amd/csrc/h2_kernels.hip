@@ -901,36 +901,65 @@ void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Block-norm lower bounds for the coarsening tolerance.
 // ---------------------------------------------------------------------------
+// Largest row or column norm over the task's matrices.  A matrix of at most
+// 128 columns is read once, row by row: the lanes of a wave cover a row (two
+// coalesced loads), a wave reduction gives its norm, and each lane keeps the
+// sums of its two columns (combined over the four waves in LDS).  Wider
+// matrices take the plain per-thread loops.
 __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ tasks, const RefMat* __restrict__ mats) {
   __shared__ double red[256];
+  __shared__ double cols4[4][128];
   const RefTask tk = tasks[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double best = 0.0;
   for (int q = 0; q < tk.count; ++q) {
     const RefMat m = mats[tk.first + q];
-    for (int r = threadIdx.x; r < m.rows; r += blockDim.x) {
-      double s = 0.0;
-      for (int c = 0; c < m.cols; ++c) {
-        double x = m.a[(int64_t)r * m.lda + c];
-        s += x * x;
+    if (m.cols <= 128) {
+      const bool in0 = lane < m.cols, in1 = lane + 64 < m.cols;
+      double c0 = 0.0, c1 = 0.0;
+      for (int r = wv; r < m.rows; r += 4) {
+        const double* row = m.a + (int64_t)r * m.lda;
+        const double x0 = in0 ? gload(row + lane) : 0.0;
+        const double x1 = in1 ? gload(row + lane + 64) : 0.0;
+        c0 += x0 * x0;
+        c1 += x1 * x1;
+        double s = x0 * x0 + x1 * x1;
+        s = dpp_group_sum(s, 16);
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        best = fmax(best, s);
       }
-      best = fmax(best, s);
-    }
-    for (int c = threadIdx.x; c < m.cols; c += blockDim.x) {
-      double s = 0.0;
-      for (int r = 0; r < m.rows; ++r) {
-        double x = m.a[(int64_t)r * m.lda + c];
-        s += x * x;
+      cols4[wv][lane] = c0;
+      cols4[wv][lane + 64] = c1;
+      __syncthreads();
+      if (tid < 128) best = fmax(best, (cols4[0][tid] + cols4[1][tid]) + (cols4[2][tid] + cols4[3][tid]));
+      __syncthreads();
+    } else {
+      for (int r = tid; r < m.rows; r += blockDim.x) {
+        double s = 0.0;
+        for (int c = 0; c < m.cols; ++c) {
+          const double x = m.a[(int64_t)r * m.lda + c];
+          s += x * x;
+        }
+        best = fmax(best, s);
       }
-      best = fmax(best, s);
+      for (int c = tid; c < m.cols; c += blockDim.x) {
+        double s = 0.0;
+        for (int r = 0; r < m.rows; ++r) {
+          const double x = m.a[(int64_t)r * m.lda + c];
+          s += x * x;
+        }
+        best = fmax(best, s);
+      }
     }
   }
-  red[threadIdx.x] = best;
+  red[tid] = best;
   __syncthreads();
   for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    if (tid < off) red[tid] = fmax(red[tid], red[tid + off]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *tk.out = tk.factor * sqrt(red[0]);
+  if (tid == 0) *tk.out = tk.factor * sqrt(red[0]);
 }
 
 void launch_ref(const RefTask* tasks, const RefMat* mats, int ntasks, hipStream_t s) {
