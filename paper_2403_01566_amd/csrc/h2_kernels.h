@@ -38,6 +38,8 @@ struct GemmTask {
   const int* coff_dev;
   const int* roff_dev;
   int ldc, m, n, item0, nitem, beta;
+  int nslice;  // 16-wide K slices of the product items: sum of ceil(k / 16)
+  int ncopy;   // copy items
 };
 
 struct GemmTile {

@@ -97,15 +97,13 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
     for (int b = 0; b < 2; ++b)
       for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
 
-  // copies (IT_COPY items) go straight into the accumulators
-  int nmm = 0, nsl = 0;  // product items, their 16-wide slices
-  for (int it = 0; it < tk.nitem; ++it) {
+  // copies (IT_COPY items) go straight into the accumulators; the task
+  // carries the number of product slices, so a task without copies never
+  // walks its item list here
+  const int nsl = tk.nslice;
+  for (int it = 0; it < (tk.ncopy > 0 ? tk.nitem : 0); ++it) {
     const GemmItem<T> item = items[tk.item0 + it];
-    if (!(item.flags & IT_COPY)) {
-      ++nmm;
-      nsl += (item.k + GBK - 1) / GBK;
-      continue;
-    }
+    if (!(item.flags & IT_COPY)) continue;
     double alpha = item.alpha;
     if (item.scale) {
       double s = *item.scale;
@@ -126,7 +124,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
         }
   }
 
-  if (nmm > 0) {
+  if (nsl > 0) {
     // slice cursor over the product items
     int it = -1, k0 = 0, kend = 0;
     GemmItem<T> item{};

@@ -1738,6 +1738,12 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     tasks[i].item0 = tk[i].item0;
     tasks[i].nitem = tk[i].nitem;
     tasks[i].beta = tk[i].beta;
+    tasks[i].nslice = tasks[i].ncopy = 0;
+    for (int q = 0; q < tk[i].nitem; ++q) {
+      const auto& x = it[tk[i].item0 + q];
+      if (x.flags & h2k::IT_COPY) ++tasks[i].ncopy;
+      else tasks[i].nslice += (x.k + 15) / 16;
+    }
     for (int m0 = 0; m0 < tk[i].m; m0 += 64)
       for (int n0 = 0; n0 < tk[i].n; n0 += 64) tiles.push_back({(int)i, m0, n0, 0});
   }

@@ -59,7 +59,7 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
   std::vector<T> c0((size_t)m * n);
   for (auto& x : c0) x = (T)g.next();
   T* dc = up(c0, keep);
-  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1};
+  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1, nitem * ((k + 15) / 16), 0};
   std::vector<h2k::GemmTile> tiles;
   for (int i = 0; i < m; i += 64)
     for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
@@ -165,13 +165,13 @@ double qr_split_test(hipStream_t s, int m, int w, int we) {
   return err / ref;
 }
 
-double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0) {
+double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0, double decades = 10.0) {
   std::vector<void*> keep;
   Lcg g(7 + w);
   // A = U diag(sig) V^T with decaying singular values, formed densely
   std::vector<double> A((size_t)w * w, 0.0);
   std::vector<double> sig(w);
-  for (int i = 0; i < w; ++i) sig[i] = std::pow(10.0, -10.0 * i / std::max(1, w - 1));
+  for (int i = 0; i < w; ++i) sig[i] = std::pow(10.0, -decades * i / std::max(1, w - 1));
   std::vector<double> X((size_t)w * w), Y((size_t)w * w);
   for (auto& x : X) x = g.next();
   for (auto& x : Y) x = g.next();
@@ -322,6 +322,7 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(svd_test(s, 128, overflow));
   e.push_back(svd_test(s, 40, overflow, 1));
   e.push_back(svd_test(s, 128, overflow, 1));
+  e.push_back(svd_test(s, 100, overflow, 1, 30.0));  // short rank (about 20) of a wide matrix
   e.push_back(chol_test(s, 12, 200));
   e.push_back(chol_test(s, 32, 300));
   e.push_back(chol_test(s, 50, 400));
