@@ -25,6 +25,8 @@ Readings where the paper leaves the construction open ("a suitable algorithm"):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -92,12 +94,28 @@ class ClusterTree:
     def is_leaf(self, t):
         return len(self.children[t]) == 0
 
+    # Squared diameter and distance as plain sums of products in axis order
+    # (Python floats: no fused multiply-add), the arithmetic the library's
+    # host planner uses too, so exact ties of the admissibility condition on
+    # regular point sets are decided alike.
+    def diam2(self, t):
+        acc = 0.0
+        for d in self.hi[t] - self.lo[t]:
+            acc += float(d) * float(d)
+        return acc
+
+    def dist2(self, t, s):
+        gap = np.maximum(0.0, np.maximum(self.lo[t] - self.hi[s], self.lo[s] - self.hi[t]))
+        acc = 0.0
+        for g in gap:
+            acc += float(g) * float(g)
+        return acc
+
     def diam(self, t):
-        return float(np.linalg.norm(self.hi[t] - self.lo[t]))
+        return math.sqrt(self.diam2(t))
 
     def dist(self, t, s):
-        gap = np.maximum(0.0, np.maximum(self.lo[t] - self.hi[s], self.lo[s] - self.hi[t]))
-        return float(np.linalg.norm(gap))
+        return math.sqrt(self.dist2(t, s))
 
     def leaves(self):
         return [t for t in range(self.ncl) if self.is_leaf(t)]
@@ -116,10 +134,12 @@ class ClusterTree:
 
 
 def admissible(tree_r: ClusterTree, tree_c: ClusterTree, t: int, s: int, eta: float) -> bool:
-    """eq. (admissibility): max(diam) <= 2*eta*dist."""
+    """eq. (admissibility): max(diam) <= 2*eta*dist, decided on the squares:
+    max(diam^2) <= (2 eta)^2 dist^2."""
     if tree_r is not tree_c:
         raise NotImplementedError
-    return max(tree_r.diam(t), tree_c.diam(s)) <= 2.0 * eta * tree_r.dist(t, s)
+    e2 = (2.0 * eta) * (2.0 * eta)
+    return max(tree_r.diam2(t), tree_c.diam2(s)) <= e2 * tree_r.dist2(t, s)
 
 
 class BlockTree:

@@ -45,6 +45,7 @@ struct Tree {
   bool leaf(int t) const { return children[t].empty(); }
   double diam(int t) const;
   double dist(int t, int s) const;
+  double diam2(int t) const;  // squared, without fused multiply-add (see the admissibility test)
 };
 
 std::shared_ptr<Tree> build_tree(const double* pts, int64_t n, int dim, int leaf_size);

@@ -17,23 +17,31 @@
 namespace h2 {
 
 // ------------------------------------------------------------------ trees
-double Tree::diam(int t) const {
+// Squared diameter and distance: plain products and sums in axis order (no
+// fused multiply-add), the arithmetic of the oracle, so that exact ties of
+// the admissibility condition are decided alike on both sides.
+double Tree::diam2(int t) const {
+#pragma clang fp contract(off)
   double s = 0;
   for (int a = 0; a < dim; ++a) {
-    double d = hi[t * dim + a] - lo[t * dim + a];
+    const double d = hi[t * dim + a] - lo[t * dim + a];
     s += d * d;
   }
-  return std::sqrt(s);
+  return s;
 }
+double Tree::diam(int t) const { return std::sqrt(diam2(t)); }
 
-double Tree::dist(int t, int s) const {
+static double dist2_between(const Tree& R, int t, const Tree& C, int s) {
+#pragma clang fp contract(off)
   double acc = 0;
-  for (int a = 0; a < dim; ++a) {
-    double g = std::max(0.0, std::max(lo[t * dim + a] - hi[s * dim + a], lo[s * dim + a] - hi[t * dim + a]));
+  for (int a = 0; a < R.dim; ++a) {
+    const double g =
+        std::max(0.0, std::max(R.lo[t * R.dim + a] - C.hi[s * C.dim + a], C.lo[s * C.dim + a] - R.hi[t * R.dim + a]));
     acc += g * g;
   }
-  return std::sqrt(acc);
+  return acc;
 }
+double Tree::dist(int t, int s) const { return std::sqrt(dist2_between(*this, t, *this, s)); }
 
 std::shared_ptr<Tree> build_tree(const double* pts, int64_t n, int dim, int leaf_size) {
   auto T = std::make_shared<Tree>();
@@ -108,15 +116,9 @@ void build_block_tree(BlockTree& bt, const Tree& R, const Tree& C, double eta) {
   for (size_t q = 0; q < bt.nodes.size(); ++q) {
     int t = bt.nodes[q].t, s = bt.nodes[q].s;
     bt.index[{t, s}] = (int)q;
-    bool adm = std::max(R.diam(t), C.diam(s)) <= 2.0 * eta * R.dist(t, s);
-    if (&R != &C) adm = std::max(R.diam(t), C.diam(s)) <= 2.0 * eta * [&] {
-      double acc = 0;
-      for (int a = 0; a < R.dim; ++a) {
-        double g = std::max(0.0, std::max(R.lo[t * R.dim + a] - C.hi[s * C.dim + a], C.lo[s * C.dim + a] - R.hi[t * R.dim + a]));
-        acc += g * g;
-      }
-      return std::sqrt(acc);
-    }();
+    // max(diam) <= 2 eta dist, squared: max(diam^2) <= (2 eta)^2 dist^2
+    const double e2 = (2.0 * eta) * (2.0 * eta);
+    const bool adm = std::max(R.diam2(t), C.diam2(s)) <= e2 * dist2_between(R, t, C, s);
     if (adm) {
       bt.nodes[q].kind = BK_ADM;
       bt.nodes[q].leaf_index = (int)bt.adm.size();
