@@ -169,6 +169,27 @@ h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld);
  * h2_matrix_blocks).  out: |t| x |s| row-major in tree order. */
 h2_status h2_block_dense(h2_matrix M, int64_t b, double* out);
 
+/* Matrix-vector product with an H2-matrix (Section 2: O(nk) operations with
+ * the nested bases): y = M x (trans = 0) or y = M^T x (trans = 1) for nrhs
+ * vectors at once.  x holds cols(M) x nrhs (rows(M) x nrhs when trans) and y
+ * the other side, host memory, row-major (vector j is column j), original
+ * point order.  Runs on the device with a cached plan per (M, trans, nrhs);
+ * synchronous.  nrhs >= 1, else INVALID_ARG. */
+h2_status h2_matvec(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y);
+
+/* Global error of a product as the experiments of Section 6 report it: the
+ * relative spectral error ||XY - C||_2 / ||XY||_2, both norms estimated by
+ * `iters` steps of the power iteration (the paper uses ten).  Each step on
+ * E^T E (E = XY - C, resp. XY) takes z of unit norm, sets sigma = ||E z|| and
+ * z = E^T E z / ||E^T E z||; the estimate is the last sigma (a lower bound of
+ * ||E||_2).  z0: cols(Y) entries, host, original order, not all zero (the
+ * caller supplies it, e.g. seeded random).  C may be NULL (then *err_norm =
+ * 0).  X's column tree must be Y's row tree and C must have X's row tree and
+ * Y's column tree, else INCOMPATIBLE.  Device matrix-vector products only;
+ * synchronous. */
+h2_status h2_product_error(h2_matrix X, h2_matrix Y, h2_matrix C, int iters, const double* z0, double* err_norm,
+                           double* xy_norm);
+
 /* Sizes of M: numbers of admissible / inadmissible leaves, rank cap, maximal
  * row and column ranks. */
 h2_status h2_matrix_info(h2_matrix M, int64_t* n_adm, int64_t* n_inadm, int* kcap, int* rank_max_row,

@@ -236,6 +236,14 @@ class H2Matrix:
         y[self.rows.perm] = yp
         return y.reshape(np.shape(x)[:1] + np.shape(x)[1:])
 
+    def rmatvec(self, x):
+        """y = X^* x in the original index order (the adjoint recursion)."""
+        xp = np.asarray(x)[self.rows.perm]
+        yp = self.apply_block_adjoint(0, 0, xp.reshape(len(xp), -1))
+        y = np.empty_like(yp)
+        y[self.cols.perm] = yp
+        return y.reshape((self.cols.n,) + np.shape(x)[1:])
+
     def storage_words(self):
         w = sum(v.size for v in self.V.leaf.values()) + sum(e.size for e in self.V.transfer.values())
         w += sum(v.size for v in self.W.leaf.values()) + sum(e.size for e in self.W.transfer.values())

@@ -198,6 +198,29 @@ h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld) {
   });
 }
 
+h2_status h2_matvec(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y) {
+  return guard([&] {
+    require(M && x && y, "null argument");
+    require(nrhs >= 1, "nrhs below 1");
+    require(trans == 0 || trans == 1, "trans must be 0 or 1");
+    auto& m = *M->m;
+    H2_HIP(hipSetDevice(m.ctx->device));
+    h2::matvec(&m, trans, nrhs, x, y);
+  });
+}
+
+h2_status h2_product_error(h2_matrix X, h2_matrix Y, h2_matrix C, int iters, const double* z0, double* err_norm,
+                           double* xy_norm) {
+  return guard([&] {
+    require(X && Y && z0 && err_norm && xy_norm, "null argument");
+    require(iters >= 1, "iters below 1");
+    require(X->m->ctx == Y->m->ctx && (!C || C->m->ctx == X->m->ctx), "matrices belong to different contexts");
+    for (int64_t i = 0; i < Y->m->cols->n; ++i) require(std::isfinite(z0[i]), "non-finite start vector");
+    H2_HIP(hipSetDevice(X->m->ctx->device));
+    h2::product_error(X->m.get(), Y->m.get(), C ? C->m.get() : nullptr, iters, z0, err_norm, xy_norm);
+  });
+}
+
 h2_status h2_block_dense(h2_matrix M, int64_t b, double* out) {
   return guard([&] {
     require(M && out, "null argument");

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <stdexcept>
 #include <string>
@@ -124,6 +125,7 @@ struct Matrix {
 };
 
 struct Plan;
+struct MvPlan;
 
 // Device, stream and plan cache.  Shared by the context handle and every
 // matrix created in it, so handles may be released in any order.
@@ -135,6 +137,8 @@ struct Context {
   // operand pairs whose FP32 bulk exceeded a rank cap: largest such eps (those
   // products, and tighter ones, run the bulk in FP64)
   std::map<std::pair<uint64_t, uint64_t>, double> fp32_fail_eps;
+  // matrix-vector plans: (matrix id, transposed, number of vectors)
+  std::map<std::tuple<uint64_t, int, int64_t>, std::shared_ptr<MvPlan>> mvplans;
   uint64_t next_id = 1;
   std::weak_ptr<Context> self;
   ~Context();
@@ -146,6 +150,13 @@ std::unique_ptr<Matrix> build_interpolated(Context* ctx, std::shared_ptr<Tree> r
 
 std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
                                  h2_mul_stats* stats);
+
+// y = M x (trans = 0) or M^T x (trans = 1) for nrhs vectors, host arrays in
+// the original point order, row-major (one vector per column).
+void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y);
+// Power-iteration estimates of ||XY - C||_2 (C may be null: 0) and ||XY||_2,
+// started from z0 (cols(Y) entries, original order).
+void product_error(Matrix* X, Matrix* Y, Matrix* C, int iters, const double* z0, double* err, double* nxy);
 
 void to_dense(const Matrix& M, double* out, int64_t ld);
 void block_dense(const Matrix& M, int64_t b, double* out);

@@ -164,6 +164,12 @@ void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s);
 void launch_ref(const RefTask* tasks, const RefMat* mats, int ntasks, hipStream_t s);
 void launch_fill(const FillTask* tasks, int ntasks, hipStream_t s);
 void launch_scan(const ScanTask* tasks, const int* const* src, int ntasks, hipStream_t s);
+// Vector kernels of the power iteration: y = a x + b y (x may alias y), and
+// partial sums of x . y, one per workgroup of kDotBlocks (the host adds them
+// in index order).
+constexpr int kDotBlocks = 256;
+void launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s);
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, hipStream_t s);
 void launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStream_t s);
 void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s);
 

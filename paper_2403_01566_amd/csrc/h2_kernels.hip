@@ -14,6 +14,7 @@
 //    triangular transform that orthonormalises a tall near-orthogonal matrix.
 #include "h2_kernels.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace h2k {
@@ -1000,6 +1001,33 @@ void launch_convert_f64_to_f32(const double* in, float* out, int64_t n, hipStrea
 }
 void launch_convert_f32_to_f64(const float* in, double* out, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(cvt_f2d, dim3(1024), dim3(256), 0, s, in, out, n);
+}
+
+__global__ void axpby_kernel(const double* x, double* y, int64_t n, double a, double b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+void launch_axpby(const double* x, double* y, int64_t n, double a, double b, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(axpby_kernel, dim3(blocks), dim3(256), 0, s, x, y, n, a, b);
+}
+
+// Grid-stride partial sums; each workgroup reduces its lanes (DPP rows, lane
+// shuffles, then LDS over the four waves) into partial[blockIdx.x].
+__global__ __launch_bounds__(256) void dot_kernel(const double* x, const double* y, int64_t n, double* partial) {
+  __shared__ double red[4];
+  double v = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) v += x[i] * y[i];
+  v = dpp_group_sum(v, 16);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+void launch_dot(const double* x, const double* y, int64_t n, double* partial, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel, dim3(kDotBlocks), dim3(256), 0, s, x, y, n, partial);
 }
 
 __global__ void scan_kernel(const ScanTask* __restrict__ tasks, const int* const* __restrict__ src, int ntasks) {

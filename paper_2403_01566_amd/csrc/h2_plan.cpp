@@ -2542,4 +2542,231 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
   return Cm;
 }
 
+// ------------------------------------------------------------------ matrix-vector products
+// y = M x for an H2-matrix (Section 2: O(nk) with the nested bases), as
+// level-batched GEMM steps on nrhs vectors at once:
+//   forward   x^_s = W_s^* x|_s      (leaves), x^_s = sum_c E_c^* x^_c (upwards)
+//   couplings y^_t = sum_{(t,s) admissible} S_ts x^_s
+//   backward  y^_c += E_c y^_parent (downwards), y|_t = V_t y^_t (leaves)
+//   nearfield y|_t += N_ts x|_s      (inadmissible leaves)
+// The adjoint swaps the roles of the two bases and transposes S and N.
+// Vectors are held in tree order inside the plan's workspace.
+struct MvPlan {
+  std::shared_ptr<Plan> P;
+  int64_t in_off = 0, out_off = 0;  // input / output vectors in the plan's FP64 workspace
+  const Tree* tin = nullptr;
+  const Tree* tout = nullptr;
+  int64_t nrhs = 1;
+  double* in() const { return P->bufd.as<double>() + in_off; }
+  double* out() const { return P->bufd.as<double>() + out_off; }
+};
+
+static std::shared_ptr<MvPlan> build_mv(Matrix* M, int trans, int64_t nrhs) {
+  auto mv = std::make_shared<MvPlan>();
+  mv->P = std::make_shared<Plan>();
+  Plan& P = *mv->P;
+  Builder B(P);
+  const Tree& Ti = trans ? *M->rows : *M->cols;
+  const Tree& To = trans ? *M->cols : *M->rows;
+  const BasisDev& Bi = trans ? M->V : M->W;
+  const BasisDev& Bo = trans ? M->W : M->V;
+  const int kc = M->kc, nr = (int)nrhs;
+  mv->tin = &Ti;
+  mv->tout = &To;
+  mv->nrhs = nrhs;
+  const DRef<double> X = B.wd(Ti.n * nrhs), Y = B.wd(To.n * nrhs);
+  const DRef<double> xh = B.wd((int64_t)Ti.ncl * kc * nrhs), yh = B.wd((int64_t)To.ncl * kc * nrhs);
+  mv->in_off = X.off;
+  mv->out_off = Y.off;
+  auto ext = [](const double* p) { return DRef<double>::external(const_cast<double*>(p)); };
+  auto XH = [&](int s) { return xh + (int64_t)s * kc * nrhs; };
+  auto YH = [&](int t) { return yh + (int64_t)t * kc * nrhs; };
+  const auto& bt = M->bt;
+  // forward transform
+  {
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int s = 0; s < Ti.ncl; ++s) {
+      if (!Ti.leaf(s)) continue;
+      g.task(XH(s), nr, kc, nr);
+      g.mm(ext(Bi.leaf) + Ti.begin[s] * kc, kc, X + Ti.begin[s] * nrhs, nr, (int)Ti.size(s), h2k::IT_TRANS_A);
+    }
+  }
+  for (int l = Ti.depth - 2; l >= 0; --l) {
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int s = 0; s < Ti.ncl; ++s) {
+      if (Ti.level[s] != l || Ti.leaf(s)) continue;
+      g.task(XH(s), nr, kc, nr);
+      for (int c : Ti.children[s]) g.mm(ext(Bi.transfer) + (int64_t)c * kc * kc, kc, XH(c), nr, kc, h2k::IT_TRANS_A);
+    }
+  }
+  // couplings (every output cluster gets y^, zero without admissible blocks)
+  {
+    std::vector<std::vector<int>> of(To.ncl);
+    for (size_t i = 0; i < bt.adm.size(); ++i) {
+      const auto& nd = bt.nodes[bt.adm[i]];
+      of[trans ? nd.s : nd.t].push_back((int)i);
+    }
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int t = 0; t < To.ncl; ++t) {
+      g.task(YH(t), nr, kc, nr);
+      for (int i : of[t]) {
+        const auto& nd = bt.nodes[bt.adm[i]];
+        g.mm(ext(M->S) + (int64_t)i * kc * kc, kc, XH(trans ? nd.t : nd.s), nr, kc, trans ? h2k::IT_TRANS_A : 0);
+      }
+    }
+  }
+  // backward transform
+  for (int l = 1; l < To.depth; ++l) {
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int c = 0; c < To.ncl; ++c) {
+      if (To.level[c] != l) continue;
+      g.task(YH(c), nr, kc, nr, 1);
+      g.mm(ext(Bo.transfer) + (int64_t)c * kc * kc, kc, YH(To.parent[c]), nr, kc);
+    }
+  }
+  // leaves and nearfield; nearfield blocks of a non-leaf output cluster
+  // follow in one step per level (their rows overlap the leaves')
+  std::vector<std::vector<int>> near(To.ncl);
+  for (size_t i = 0; i < bt.inadm.size(); ++i) {
+    const auto& nd = bt.nodes[bt.inadm[i]];
+    near[trans ? nd.s : nd.t].push_back((int)i);
+  }
+  auto near_items = [&](GW<double>& g, int t) {
+    for (int i : near[t]) {
+      const auto& nd = bt.nodes[bt.inadm[i]];
+      const int64_t m = M->rows->size(nd.t), n = M->cols->size(nd.s);
+      if (!trans) g.mm(ext(M->N) + M->noff[i], (int)n, X + M->cols->begin[nd.s] * nrhs, nr, (int)n);
+      else g.mm(ext(M->N) + M->noff[i], (int)n, X + M->rows->begin[nd.t] * nrhs, nr, (int)m, h2k::IT_TRANS_A);
+    }
+  };
+  {
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int t = 0; t < To.ncl; ++t) {
+      if (!To.leaf(t)) continue;
+      g.task(Y + To.begin[t] * nrhs, nr, (int)To.size(t), nr);
+      g.mm(ext(Bo.leaf) + To.begin[t] * kc, kc, YH(t), nr, kc);
+      near_items(g, t);
+    }
+  }
+  for (int l = 0; l < To.depth; ++l) {
+    bool any = false;
+    for (int t = 0; t < To.ncl; ++t) any |= To.level[t] == l && !To.leaf(t) && !near[t].empty();
+    if (!any) continue;
+    GW<double> g(B.step(SK_GEMM_D));
+    for (int t = 0; t < To.ncl; ++t) {
+      if (To.level[t] != l || To.leaf(t) || near[t].empty()) continue;
+      g.task(Y + To.begin[t] * nrhs, nr, (int)To.size(t), nr, 1);
+      near_items(g, t);
+    }
+  }
+  finalize(P, 0.0);
+  return mv;
+}
+
+static std::shared_ptr<MvPlan> get_mv(Matrix* M, int trans, int64_t nrhs) {
+  Context* ctx = M->ctx;
+  const auto key = std::make_tuple(M->id, trans, nrhs);
+  auto it = ctx->mvplans.find(key);
+  if (it != ctx->mvplans.end()) return it->second;
+  auto mv = build_mv(M, trans, nrhs);
+  ctx->mvplans[key] = mv;
+  return mv;
+}
+
+void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y) {
+  Context* ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  auto mv = get_mv(M, trans, nrhs);
+  const Tree& Ti = *mv->tin;
+  const Tree& To = *mv->tout;
+  std::vector<double> xt((size_t)Ti.n * nrhs), yt((size_t)To.n * nrhs);
+  for (int64_t i = 0; i < Ti.n; ++i) std::memcpy(&xt[i * nrhs], x + Ti.perm[i] * nrhs, nrhs * sizeof(double));
+  H2_HIP(hipMemcpyAsync(mv->in(), xt.data(), xt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  execute(ctx, *mv->P, 0, nullptr);
+  H2_HIP(hipMemcpyAsync(yt.data(), mv->out(), yt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  H2_HIP(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < To.n; ++i) std::memcpy(y + To.perm[i] * nrhs, &yt[i * nrhs], nrhs * sizeof(double));
+}
+
+// Power iteration on E^* E (E = XY - C, or XY): z = z0 / ||z0||; each step
+// w = E z, sigma = ||w|| (the Rayleigh estimate of the largest singular value
+// for the unit vector z), z = E^* w / ||E^* w||.  The estimate after `iters`
+// steps is the sigma of the last step.
+void product_error(Matrix* X, Matrix* Y, Matrix* C, int iters, const double* z0, double* err, double* nxy) {
+  Context* ctx = X->ctx;
+  hipStream_t s = ctx->stream;
+  auto same = [](const Tree& a, const Tree& b) { return &a == &b || (a.n == b.n && a.perm == b.perm); };
+  if (!same(*X->cols, *Y->rows)) throw Error(H2_ERR_INCOMPATIBLE, "X columns and Y rows use different cluster trees");
+  if (C && (!same(*C->rows, *X->rows) || !same(*C->cols, *Y->cols)))
+    throw Error(H2_ERR_INCOMPATIBLE, "C does not have the row tree of X and the column tree of Y");
+  auto pY = get_mv(Y, 0, 1), pX = get_mv(X, 0, 1), pXt = get_mv(X, 1, 1), pYt = get_mv(Y, 1, 1);
+  std::shared_ptr<MvPlan> pC, pCt;
+  if (C) {
+    pC = get_mv(C, 0, 1);
+    pCt = get_mv(C, 1, 1);
+  }
+  const Tree& Tc = *Y->cols;
+  const int64_t nc = Tc.n, nr = X->rows->n, nm = Y->rows->n;
+  DevBuf z, zs, part;
+  z.alloc(nc * sizeof(double));
+  zs.alloc(nc * sizeof(double));
+  part.alloc(h2k::kDotBlocks * sizeof(double));
+  {
+    std::vector<double> zt(nc);
+    for (int64_t i = 0; i < nc; ++i) zt[i] = z0[Tc.perm[i]];
+    H2_HIP(hipMemcpy(zs.p, zt.data(), nc * sizeof(double), hipMemcpyHostToDevice));
+  }
+  auto dot = [&](const double* a, const double* b, int64_t n) {
+    std::vector<double> ph(h2k::kDotBlocks);
+    h2k::launch_dot(a, b, n, part.as<double>(), s);
+    H2_HIP(hipMemcpyAsync(ph.data(), part.p, ph.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    H2_HIP(hipStreamSynchronize(s));
+    double t = 0.0;
+    for (double v : ph) t += v;
+    return t;
+  };
+  auto copy = [&](double* dst, const double* src, int64_t n) {
+    H2_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  };
+  auto power = [&](bool withC) {
+    copy(z.as<double>(), zs.as<double>(), nc);
+    const double n0 = std::sqrt(dot(z.as<double>(), z.as<double>(), nc));
+    if (n0 == 0.0) throw Error(H2_ERR_INVALID_ARG, "zero start vector");
+    h2k::launch_axpby(z.as<double>(), z.as<double>(), nc, 0.0, 1.0 / n0, s);
+    double sig = 0.0;
+    for (int it = 0; it < iters; ++it) {
+      // w = E z
+      copy(pY->in(), z.as<double>(), nc);
+      execute(ctx, *pY->P, 0, nullptr);
+      copy(pX->in(), pY->out(), nm);
+      execute(ctx, *pX->P, 0, nullptr);
+      double* w = pX->out();
+      if (withC) {
+        copy(pC->in(), z.as<double>(), nc);
+        execute(ctx, *pC->P, 0, nullptr);
+        h2k::launch_axpby(pC->out(), w, nr, -1.0, 1.0, s);
+      }
+      sig = std::sqrt(dot(w, w, nr));
+      // z = E^* w / ||E^* w||
+      copy(pXt->in(), w, nr);
+      execute(ctx, *pXt->P, 0, nullptr);
+      copy(pYt->in(), pXt->out(), nm);
+      execute(ctx, *pYt->P, 0, nullptr);
+      double* zt = pYt->out();
+      if (withC) {
+        copy(pCt->in(), w, nr);
+        execute(ctx, *pCt->P, 0, nullptr);
+        h2k::launch_axpby(pCt->out(), zt, nc, -1.0, 1.0, s);
+      }
+      const double nz = std::sqrt(dot(zt, zt, nc));
+      if (nz == 0.0) break;
+      h2k::launch_axpby(zt, z.as<double>(), nc, 1.0 / nz, 0.0, s);
+    }
+    return sig;
+  };
+  *err = C ? power(true) : 0.0;
+  *nxy = power(false);
+  H2_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace h2

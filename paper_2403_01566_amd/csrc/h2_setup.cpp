@@ -172,6 +172,7 @@ Context::~Context() {
   (void)hipSetDevice(device);
   if (stream) (void)hipStreamSynchronize(stream);
   plans.clear();
+  mvplans.clear();
   if (overflow) (void)hipFree(overflow);
   if (stream) (void)hipStreamDestroy(stream);
 }
@@ -179,6 +180,10 @@ Context::~Context() {
 void Context::evict(uint64_t matrix_id) {
   for (auto it = plans.begin(); it != plans.end();) {
     if (it->first.first == matrix_id || (it->first.second >> 2) == matrix_id) it = plans.erase(it);
+    else ++it;
+  }
+  for (auto it = mvplans.begin(); it != mvplans.end();) {
+    if (std::get<0>(it->first) == matrix_id) it = mvplans.erase(it);
     else ++it;
   }
   for (auto it = fp32_fail_eps.begin(); it != fp32_fail_eps.end();) {

@@ -30,7 +30,7 @@ EXPORTS = [
     "h2_tree_permutation", "h2_tree_info", "h2_tree_clusters", "h2_tree_destroy",
     "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
-    "h2_selftest", "h2_kernel_name",
+    "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error",
 ]
 NKERNEL = 13
 
@@ -83,6 +83,8 @@ _sig = {
     "h2_matrix_destroy": (None, [_vp]),
     "h2_selftest": (C.c_int, [_vp, _dp, C.c_int, _ip]),
     "h2_kernel_name": (C.c_char_p, [C.c_int]),
+    "h2_matvec": (C.c_int, [_vp, C.c_int, C.c_int64, _dp, _dp]),
+    "h2_product_error": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp, _dp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -199,6 +201,21 @@ class Matrix:
         _check(_lib.h2_to_dense(self.h, _dptr(out), ncols))
         return out
 
+    @property
+    def shape(self):
+        return (self._keep[1].n, self._keep[2].n)
+
+    def matvec(self, x, trans=False):
+        """y = M x, or M^T x with trans: x of shape (n,) or (n, nrhs), original order (device product)."""
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        x2 = xa.reshape(xa.shape[0], -1)
+        nin, nout = (self.shape[0], self.shape[1]) if trans else (self.shape[1], self.shape[0])
+        if x2.shape[0] != nin:
+            raise ValueError(f"x has {x2.shape[0]} rows, expected {nin}")
+        y2 = np.zeros((nout, x2.shape[1]), dtype=np.float64)
+        _check(_lib.h2_matvec(self.h, int(bool(trans)), x2.shape[1], _dptr(x2), _dptr(y2)))
+        return y2[:, 0] if xa.ndim == 1 else y2
+
     def block_dense(self, b, m, n):
         out = np.zeros((m, n), dtype=np.float64)
         _check(_lib.h2_block_dense(self.h, int(b), _dptr(out)))
@@ -239,6 +256,15 @@ def mul(ctx: Context, X: Matrix, Y: Matrix, eps: float, options: MulOptions | No
     opt = options if options is not None else default_options()
     _check(_lib.h2_mul(ctx.h, X.h, Y.h, float(eps), C.byref(opt), C.byref(h), C.byref(st)))
     return Matrix(h, (ctx,) + X._keep[1:2] + Y._keep[2:3]), st.as_dict()
+
+
+def product_error(X: Matrix, Y: Matrix, Cm: Matrix | None, z0, iters: int = 10):
+    """Power-iteration estimates (||XY - C||_2, ||XY||_2) from the start vector z0."""
+    z = np.ascontiguousarray(z0, dtype=np.float64)
+    e, nxy = C.c_double(), C.c_double()
+    _check(_lib.h2_product_error(X.h, Y.h, None if Cm is None else Cm.h, int(iters), _dptr(z), C.byref(e),
+                                 C.byref(nxy)))
+    return e.value, nxy.value
 
 
 def kernel_names():

@@ -125,3 +125,9 @@ def batched_instances(count: int = 64, seed: int = 2403):
         pseed = int(rng.integers(0, 2**31 - 1))
         out.append({"n": n, "order": p, "leaf": 32 if p <= 4 else 64, "points_seed": pseed})
     return out
+
+
+def start_vector(n: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal start vector of the power iteration (n entries,
+    original point order)."""
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)

@@ -1,0 +1,163 @@
+"""GPU H2 matrix-vector products and the power-iteration estimate of the
+global error of a product (Section 2 products; the error column of Section 6),
+through the C ABI, against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_01566_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h2():
+    from paper_2403_01566_amd import h2 as mod
+    return mod
+
+
+@pytest.fixture(scope="module")
+def ctx(h2):
+    return h2.Context(0)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _case(h2, ctx, case):
+    if case == "c1":
+        P, nrm, leaf, kern, order, eta, diag = W.grid2d(32), None, 32, 0, 3, 0.5, 0
+    elif case == "sphere3":
+        (P, nrm), leaf, kern, order, eta, diag = W.icosphere(3), 64, 1, 3, 1.0, 1
+    elif case == "dlp2":
+        (P, nrm), leaf, kern, order, eta, diag = W.icosphere(2), 20, 2, 2, 1.0, 0
+    elif case == "random2d":
+        P, nrm, leaf, kern, order, eta, diag = W.uniform2d(900, 11), None, 24, 0, 4, 0.5, 0
+    elif case == "tiny":
+        P, nrm, leaf, kern, order, eta, diag = W.uniform2d(30, 4), None, 32, 0, 3, 0.5, 0
+    else:
+        raise KeyError(case)
+    T = h2.Tree(ctx, P, leaf)
+    A = h2.Matrix.interpolated(ctx, T, T, kern, order, eta, diag, nrm)
+    To = O.ClusterTree(P, leaf)
+    Ao = O.build_interpolated(To, kern, order, eta, diag=diag, normals=nrm)
+    return T, A, To, Ao
+
+
+def _check_mv(A, D, x, trans):
+    y = A.matvec(x, trans=trans)
+    ref = (D.T if trans else D) @ x
+    bound = 1e-13 * np.abs(D.T if trans else D).sum(axis=1).max() * np.abs(x).max()
+    assert y.shape == ref.shape
+    assert np.abs(y - ref).max() <= bound, (np.abs(y - ref).max(), bound)
+
+
+@pytest.mark.parametrize("case", ["c1", "sphere3", "dlp2", "random2d", "tiny"])
+def test_matvec_against_oracle(h2, ctx, case):
+    _say(f"[matvec] {case}")
+    T, A, To, Ao = _case(h2, ctx, case)
+    D = Ao.to_dense()
+    rng = np.random.default_rng(5)
+    x1 = rng.standard_normal(T.n)
+    x4 = rng.standard_normal((T.n, 4))
+    for trans in (False, True):
+        _check_mv(A, D, x1, trans)
+        _check_mv(A, D, x4, trans)
+    # the oracle's own products agree with the same dense matrix
+    assert np.abs(Ao.matvec(x1) - A.matvec(x1)).max() <= 1e-13 * np.abs(D).sum(axis=1).max()
+    assert np.abs(Ao.rmatvec(x1) - A.matvec(x1, trans=True)).max() <= 1e-13 * np.abs(D).sum(axis=0).max()
+
+
+@pytest.mark.parametrize("case,eps", [("c1", 1e-4), ("sphere3", 1e-5), ("dlp2", 1e-4)])
+def test_matvec_of_a_product(h2, ctx, case, eps):
+    """The result of h2_mul has its own (induced) block tree and bases."""
+    _say(f"[matvec product] {case} eps={eps}")
+    T, A, To, Ao = _case(h2, ctx, case)
+    Cg, st = h2.mul(ctx, A, A, eps)
+    Cd = Cg.to_dense(T.n, T.n)
+    rng = np.random.default_rng(6)
+    for trans in (False, True):
+        _check_mv(Cg, Cd, rng.standard_normal(T.n), trans)
+        _check_mv(Cg, Cd, rng.standard_normal((T.n, 3)), trans)
+
+
+@pytest.mark.parametrize("case,eps", [("c1", 1e-4), ("sphere3", 1e-6), ("random2d", 1e-5)])
+def test_product_error_against_oracle(h2, ctx, case, eps):
+    _say(f"[product error] {case} eps={eps}")
+    T, A, To, Ao = _case(h2, ctx, case)
+    Cg, st = h2.mul(ctx, A, A, eps)
+    Cd = Cg.to_dense(T.n, T.n)
+    z0 = W.start_vector(T.n, 17)
+    err, nxy = h2.product_error(A, A, Cg, z0, 10)
+    err_o, nxy_o = O.product_error(Ao, Ao, lambda z: Cd @ z, lambda w: Cd.T @ w, z0, 10)
+    D = Ao.to_dense()
+    Ex = D @ D
+    exact_err = np.linalg.norm(Ex - Cd, 2)
+    exact_n = np.linalg.norm(Ex, 2)
+    _say(f"  err {err:.6e} oracle {err_o:.6e} exact {exact_err:.6e}; |XY| {nxy:.6e} oracle {nxy_o:.6e} "
+         f"exact {exact_n:.6e}")
+    assert nxy == pytest.approx(nxy_o, rel=1e-12)
+    assert err == pytest.approx(err_o, rel=1e-6, abs=1e-13 * nxy)
+    # Rayleigh values of E^* E: lower bounds of the spectral norms
+    assert err <= exact_err * (1 + 1e-9) + 1e-13 * nxy
+    assert nxy <= exact_n * (1 + 1e-12)
+    assert nxy >= 0.9 * exact_n
+    # the block-relative bound eps gives a global relative bound of the same order
+    assert err / nxy <= 10 * eps
+    # without C: the error is zero and the norm is unchanged
+    e0, n0 = h2.product_error(A, A, None, z0, 10)
+    assert e0 == 0.0 and n0 == pytest.approx(nxy, rel=1e-14)
+
+
+def test_product_error_of_distinct_operands(h2, ctx):
+    """X != Y: the adjoint applies X^T before Y^T."""
+    _say("[product error] X = single layer, Y = double layer")
+    P, nrm = W.icosphere(2)
+    T = h2.Tree(ctx, P, 20)
+    X = h2.Matrix.interpolated(ctx, T, T, 1, 3, 1.0, 1, nrm)
+    Y = h2.Matrix.interpolated(ctx, T, T, 2, 3, 1.0, 0, nrm)
+    To = O.ClusterTree(P, 20)
+    Xo = O.build_interpolated(To, 1, 3, 1.0, diag=1, normals=nrm)
+    Yo = O.build_interpolated(To, 2, 3, 1.0, normals=nrm)
+    Cg, st = h2.mul(ctx, X, Y, 1e-4)
+    Cd = Cg.to_dense(T.n, T.n)
+    z0 = W.start_vector(T.n, 3)
+    err, nxy = h2.product_error(X, Y, Cg, z0, 10)
+    err_o, nxy_o = O.product_error(Xo, Yo, lambda z: Cd @ z, lambda w: Cd.T @ w, z0, 10)
+    assert nxy == pytest.approx(nxy_o, rel=1e-12)
+    assert err == pytest.approx(err_o, rel=1e-6, abs=1e-13 * nxy)
+
+
+def test_matvec_and_error_paths(h2, ctx):
+    _say("[matvec] error paths")
+    T, A, To, Ao = _case(h2, ctx, "c1")
+    x = np.ones(T.n)
+    y = np.zeros(T.n)
+    xp = x.ctypes.data_as(h2._dp)
+    yp = y.ctypes.data_as(h2._dp)
+    assert h2._lib.h2_matvec(A.h, 2, 1, xp, yp) == h2.H2_ERR_INVALID_ARG
+    assert h2._lib.h2_matvec(A.h, 0, 0, xp, yp) == h2.H2_ERR_INVALID_ARG
+    assert h2._lib.h2_matvec(None, 0, 1, xp, yp) == h2.H2_ERR_INVALID_ARG
+    assert h2._lib.h2_matvec(A.h, 0, 1, None, yp) == h2.H2_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        A.matvec(np.ones(T.n + 1))
+    with pytest.raises(h2.H2Error) as ei:
+        h2.product_error(A, A, None, np.zeros(T.n), 10)
+    assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    with pytest.raises(h2.H2Error) as ei:
+        h2.product_error(A, A, None, x, 0)
+    assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    bad = x.copy()
+    bad[3] = np.nan
+    with pytest.raises(h2.H2Error) as ei:
+        h2.product_error(A, A, None, bad, 10)
+    assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    T2 = h2.Tree(ctx, W.uniform2d(1024, 3), 32)
+    A2 = h2.Matrix.interpolated(ctx, T2, T2, 0, 3, 0.5)
+    with pytest.raises(h2.H2Error) as ei:
+        h2.product_error(A, A2, None, x, 10)
+    assert ei.value.code == h2.H2_ERR_INCOMPATIBLE
