@@ -26,6 +26,11 @@ construction one refinement level lower (n = 5120), scaled to the timed
 workload by the ratio of the two products' algorithmic flops as the library
 counts them; for the small grid workload the full product itself.
 
+global_error (untimed): the relative spectral error of one product, both
+norms estimated by ten device power-iteration steps, with the storage of the
+product.  --sweep LEVELS instead times G*G, G*K and K*K over icosphere levels at
+eps 1e-4 and reports time per degree of freedom, storage and error per n.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -181,6 +186,74 @@ def cpu_baseline(h2, ctx, cfg, gpu_flops_alg):
             "seconds": dt}
 
 
+def global_error(h2, ctx, A, B, n, eps, prec, iters=10):
+    """Relative spectral error ||AB - C||_2 / ||AB||_2 of one product C, both
+    norms estimated by `iters` power-iteration steps on the device from a
+    seeded start vector (the error column of the paper's experiments).
+    Untimed: it runs after the timed steps."""
+    from paper_2403_01566_amd import workloads as W
+    C, _ = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))
+    z0 = W.start_vector(n, 2403)
+    t0 = time.perf_counter()
+    err, nxy = h2.product_error(A, B, C, z0, iters)
+    dt = time.perf_counter() - t0
+    return {"rel_spectral": err / nxy, "abs": err, "norm_product": nxy, "power_steps": iters,
+            "seconds": dt, "storage_mb": C.storage_bytes() / 1e6}
+
+
+SWEEP = {
+    "slp": dict(x=(1, 1), y=(1, 1), desc="G*G, G = single layer 1/(4 pi |x-y|) (diag = row nearfield mean)"),
+    "slp_dlp": dict(x=(1, 1), y=(2, 0), desc="G*K, K = double layer (x-y).n_y/(4 pi |x-y|^3)"),
+    "dlp": dict(x=(2, 0), y=(2, 0), desc="K*K"),
+}
+
+
+def sweep(h2, ctx, levels, steps, eps):
+    """Time per degree of freedom over n (the runtime plot of the paper's
+    experiments), with the storage and the relative spectral error of each
+    product (the columns of its tables): icosphere levels, leaf 64, eta 1,
+    Chebyshev order 4, the given eps.  A product that the library rejects
+    (a rank cap) is reported with its error message."""
+    from paper_2403_01566_amd import workloads as W
+    rows = []
+    for kind, kc in SWEEP.items():
+        for lev in levels:
+            P, nrm = W.icosphere(lev)
+            T = h2.Tree(ctx, P, 64)
+            A = h2.Matrix.interpolated(ctx, T, T, kc["x"][0], 4, 1.0, kc["x"][1], nrm)
+            B = h2.Matrix.interpolated(ctx, T, T, kc["y"][0], 4, 1.0, kc["y"][1], nrm) if kc["y"] != kc["x"] else A
+            row = {"operator": kind, "level": lev, "n": int(T.n)}
+            try:
+                t0 = time.perf_counter()
+                C, st0 = h2.mul(ctx, A, B, eps)   # first call: host plan + device run
+                first = time.perf_counter() - t0
+                del C
+                ts = []
+                for _ in range(steps):
+                    t1 = time.perf_counter()
+                    C, st = h2.mul(ctx, A, B, eps)
+                    ts.append(time.perf_counter() - t1)
+                    del C
+                ts.sort()
+                med = ts[len(ts) // 2]
+                ge = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
+                row.update({"ms": med * 1e3, "us_per_dof": med * 1e6 / T.n, "first_call_ms": first * 1e3,
+                            "plan_ms": st0["t_plan_ms"], "storage_mb": ge["storage_mb"],
+                            "rel_error": ge["rel_spectral"], "precision_used": st["prec_used"],
+                            "rank_max": [st["rank_max_row"], st["rank_max_col"]], "n_adm": st["n_adm"],
+                            "n_inadm": st["n_inadm"]})
+                say(f"sweep {kind} level {lev} n={T.n}: {row['ms']:.1f} ms, {row['us_per_dof']:.3f} us/DOF, "
+                    f"{row['storage_mb']:.1f} MB, rel. error {row['rel_error']:.2e}")
+            except h2.H2Error as e:
+                row["error"] = str(e)
+                say(f"sweep {kind} level {lev} n={T.n}: {e}")
+            rows.append(row)
+            del A, B, T
+    return {"sweep": rows, "eps": eps, "steps": steps,
+            "config": {"geometry": "icosphere (triangle centroids, outward normals)", "leaf": 64, "eta": 1.0,
+                       "order": 4, "operators": {k: v["desc"] for k, v in SWEEP.items()}}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,6 +264,9 @@ def main():
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
+    ap.add_argument("--sweep", default="", metavar="LEVELS",
+                    help="comma-separated icosphere levels: time per DOF, storage and error per n, then exit")
+    ap.add_argument("--sweep-eps", type=float, default=1e-4)
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -206,6 +282,11 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     from paper_2403_01566_amd import h2
+    if args.sweep:
+        ctx = h2.Context(0)
+        levels = [int(x) for x in args.sweep.split(",")]
+        print(json.dumps(sweep(h2, ctx, levels, max(1, args.steps), args.sweep_eps)), flush=True)
+        return
     names = h2.kernel_names()
     cfg = WORKLOADS[args.workload]
     eps = cfg["eps"]
@@ -256,6 +337,8 @@ def main():
                          "precision_used": "fp32_bulk" if x["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"}
                   for name, x in res.items()},
     }
+    say("global error of one product (10 power-iteration steps, untimed)")
+    out["global_error"] = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
     if not args.no_cpu_baseline:
         say("oracle on the host cores (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(h2, ctx, cfg, st["flops_alg"])

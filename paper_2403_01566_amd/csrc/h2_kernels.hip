@@ -556,7 +556,9 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   const int rows = sq ? we : tk.rows;
   int cols = sq ? we : tk.cols;
   const int wcls = rows > cols ? rows : cols;
-  if (wcls <= wlo || wcls > WMAX) return;  // another launch handles this size class
+  // another launch handles this size class; the smallest class also takes
+  // empty tasks (both children of rank 0), which report rank 0 and zero vectors
+  if ((wlo > 0 && wcls <= wlo) || wcls > WMAX) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double ref = tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0;
   const bool qr = tk.qrcp && tk.tol_rel == 0.0;
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
     const double fro = sqrt(block_sum<NT>(ss, red));
     // every singular value is below the Frobenius norm: nothing survives an
     // absolute threshold above it
-    empty = (tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref);
+    empty = cols == 0 || ((tk.tol_rel == 0.0) && (fro <= tk.tol_abs + ref));
   } else {
     const int nl = rows, ni = cols;
     const int l = tid / TPC, sub = tid % TPC;
@@ -593,7 +595,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
     for (int q = 0; q < RPL; ++q) ss += x[q] * x[q];
     const double cn0 = group_sum<TPC>(ss);  // squared norm of this column
     const double fro = sqrt(block_sum<NT>(ss, red));
-    empty = fro <= tk.tol_abs + ref;
+    empty = cols == 0 || fro <= tk.tol_abs + ref;
     if (!empty) {
       const double tq = 0.125 * (tk.tol_abs + ref);
       double cn = cn0;   // squared norm of the rows below the current step

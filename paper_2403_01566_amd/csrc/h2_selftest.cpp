@@ -165,6 +165,32 @@ double qr_split_test(hipStream_t s, int m, int w, int we) {
   return err / ref;
 }
 
+// A split task whose two children both have rank 0 (effective width 0): rank
+// 0, zero singular values and zero vectors in both outputs, whatever the
+// output buffers held before.  Returns 0 when so, 1 otherwise.
+double svd_empty_test(hipStream_t s, int* overflow) {
+  std::vector<void*> keep;
+  const int w = 16, kc = 8;
+  std::vector<double> A((size_t)w * w, 1.0), U0((size_t)kc * kc, 7.0), S0(w, 7.0);
+  std::vector<int> ints = {0, 0, 12345};  // child ranks, then the output rank
+  double* da = up(A, keep);
+  double* du = up(U0, keep);
+  double* du2 = up(U0, keep);
+  double* ds = up(S0, keep);
+  int* di = up(ints, keep);
+  h2k::SvdTask t{da, du, du2, ds, di + 2, nullptr, di, di + 1, di, nullptr, 0.0, 1e-6, 0.0,
+                 w, kc, w, w, kc, 0, 1, 1, kc, 0};
+  auto* dt = up(std::vector<h2k::SvdTask>{t}, keep);
+  h2k::launch_svd(dt, 1, w, overflow, s);
+  H2_HIP(hipStreamSynchronize(s));
+  double err = down(di, 3)[2] == 0 ? 0.0 : 1.0;
+  for (double v : down(du, U0.size())) err = std::max(err, v == 0.0 ? 0.0 : 1.0);
+  for (double v : down(du2, U0.size())) err = std::max(err, v == 0.0 ? 0.0 : 1.0);
+  for (double v : down(ds, S0.size())) err = std::max(err, v == 0.0 ? 0.0 : 1.0);
+  for (void* p : keep) (void)hipFree(p);
+  return err;
+}
+
 double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0, double decades = 10.0) {
   std::vector<void*> keep;
   Lcg g(7 + w);
@@ -326,6 +352,7 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(chol_test(s, 12, 200));
   e.push_back(chol_test(s, 32, 300));
   e.push_back(chol_test(s, 50, 400));
+  e.push_back(svd_empty_test(s, overflow));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
   return (int)e.size();
 }
