@@ -14,8 +14,10 @@ Follows Section 2 of the paper:
 
 Readings: Chebyshev nodes of the first kind per axis on the cluster's bounding
 box, xi_j = (a+b)/2 + (b-a)/2 cos((2j+1) pi / (2p)); the tensor index runs
-with the first axis fastest; an edge shorter than 1e-12 * root diameter is
-widened symmetrically to that length.  Double layer: W_s[j, mu] =
+with the first axis fastest; an edge shorter than max(1e-12 * root diameter,
+1e-2 * the box's longest edge) is widened symmetrically to that length (a
+flat cluster, e.g. inside one face of a polyhedral surface, would otherwise
+give normal derivatives of the Lagrange polynomials of size 1/width).  Double layer: W_s[j, mu] =
 n_j . grad l_{s,mu}(y_j), nearfield (x-y).n_y / (4 pi |x-y|^3), diagonal 0.
 Single layer 1/(4 pi |x-y|): diagonal = mean of the kernel over the other
 entries of the row's nearfield blocks.  -log|x-y|: diagonal 0.
@@ -91,11 +93,11 @@ class Interp:
         d = tree.dim
         self.k = self.p ** d
         root_diam = tree.diam(0)
-        minw = 1e-12 * root_diam
         self.a = np.empty((tree.ncl, d))
         self.b = np.empty((tree.ncl, d))
         for t in range(tree.ncl):
             lo, hi = tree.lo[t].copy(), tree.hi[t].copy()
+            minw = max(1e-12 * root_diam, 1e-2 * float(np.max(hi - lo)))
             for ax in range(d):
                 if hi[ax] - lo[ax] < minw:
                     c = 0.5 * (lo[ax] + hi[ax])

@@ -300,11 +300,18 @@ std::unique_ptr<Matrix> build_interpolated(Context* ctx, std::shared_ptr<Tree> r
   build_block_tree(M->bt, R, C, eta);
   const int p = order;
   // widened boxes and nodes per cluster
+  // an edge shorter than max(1e-12 root diameter, 1e-2 longest edge of the
+  // box) is widened to that length: a flat cluster (inside one face of a
+  // polyhedral surface) would otherwise give normal derivatives of the
+  // Lagrange polynomials of size 1/width
   auto make_nodes = [&](const Tree& T, std::vector<double>& nodes_out) {
-    double minw = 1e-12 * T.diam(0);
+    const double root_w = 1e-12 * T.diam(0);
     nodes_out.assign((size_t)T.ncl * dim * p, 0.0);
     for (int t = 0; t < T.ncl; ++t)
       for (int a = 0; a < dim; ++a) {
+        double longest = 0.0;
+        for (int b = 0; b < dim; ++b) longest = std::max(longest, T.hi[t * dim + b] - T.lo[t * dim + b]);
+        const double minw = std::max(root_w, 1e-2 * longest);
         double lo = T.lo[t * dim + a], hi = T.hi[t * dim + a];
         if (hi - lo < minw) {
           double c = 0.5 * (lo + hi);

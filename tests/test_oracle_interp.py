@@ -120,3 +120,19 @@ def test_slp_diagonal_rule_and_dense_exact_nearfield():
         if i in I:
             js.extend(j for j in T.perm[T.begin[s]:T.end[s]] if j != i)
     assert abs(D[i, i] - G[i, js].mean()) < 1e-12
+
+
+def test_flat_clusters_keep_double_layer_bases_bounded():
+    """Clusters inside one face of the cube surface have zero thickness along
+    the normal; their boxes are widened to 1e-2 of the longest edge, so the
+    normal derivatives of the Lagrange polynomials stay of size p^2 / width."""
+    P, nrm = W.cube_surface(16)
+    T = O.ClusterTree(P, 64)
+    edges = T.hi - T.lo
+    assert (edges.min(axis=1) == 0.0).any()  # the case exists
+    A = O.build_interpolated(T, O.KERNEL_DLP, 4, 1.0, normals=nrm)
+    assert max(np.abs(v).max() for v in A.W.leaf.values()) < 1e4
+    # the factored and the dense form agree to rounding (no cancellation)
+    x = np.random.default_rng(0).standard_normal(T.n)
+    D = A.to_dense()
+    assert np.abs(A.matvec(x) - D @ x).max() <= 1e-13 * np.abs(D).sum(axis=1).max() * np.abs(x).max()
