@@ -28,8 +28,9 @@ counts them; for the small grid workload the full product itself.
 
 global_error (untimed): the relative spectral error of one product, both
 norms estimated by ten device power-iteration steps, with the storage of the
-product.  --sweep LEVELS instead times G*G, G*K and K*K over icosphere levels at
-eps 1e-4 and reports time per degree of freedom, storage and error per n.
+product.  --sweep LEVELS instead times G*G, G*K and K*K over icosphere levels, and
+--sweep-cube M K*K on the cube surface with m x m squares per face, at eps
+1e-4, and reports time per degree of freedom, storage and error per n.
 
 Prints one JSON line.
 """
@@ -208,50 +209,54 @@ SWEEP = {
 }
 
 
-def sweep(h2, ctx, levels, steps, eps):
+def sweep(h2, ctx, jobs, steps, eps):
     """Time per degree of freedom over n (the runtime plot of the paper's
     experiments), with the storage and the relative spectral error of each
-    product (the columns of its tables): icosphere levels, leaf 64, eta 1,
-    Chebyshev order 4, the given eps.  A product that the library rejects
-    (a rank cap) is reported with its error message."""
+    product (the columns of its tables).  jobs: (operator, geometry, size)
+    with geometry "ico" (icosphere level) or "cube" (m x m squares per face
+    of [-1,1]^3); leaf 64, eta 1, Chebyshev order 4, the given eps.  A product
+    that the library rejects (a rank cap, memory) is reported with its error."""
     from paper_2403_01566_amd import workloads as W
     rows = []
-    for kind, kc in SWEEP.items():
-        for lev in levels:
-            P, nrm = W.icosphere(lev)
-            T = h2.Tree(ctx, P, 64)
+    for kind, geo, size in jobs:
+        kc = SWEEP[kind]
+        P, nrm = W.icosphere(size) if geo == "ico" else W.cube_surface(size)
+        T = h2.Tree(ctx, P, 64)
+        row = {"operator": kind, "geometry": geo, "size": size, "n": int(T.n)}
+        try:
             A = h2.Matrix.interpolated(ctx, T, T, kc["x"][0], 4, 1.0, kc["x"][1], nrm)
             B = h2.Matrix.interpolated(ctx, T, T, kc["y"][0], 4, 1.0, kc["y"][1], nrm) if kc["y"] != kc["x"] else A
-            row = {"operator": kind, "level": lev, "n": int(T.n)}
-            try:
-                t0 = time.perf_counter()
-                C, st0 = h2.mul(ctx, A, B, eps)   # first call: host plan + device run
-                first = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            C, st0 = h2.mul(ctx, A, B, eps)   # first call: host plan + device run
+            first = time.perf_counter() - t0
+            del C
+            ts = []
+            for _ in range(steps):
+                t1 = time.perf_counter()
+                C, st = h2.mul(ctx, A, B, eps)
+                ts.append(time.perf_counter() - t1)
                 del C
-                ts = []
-                for _ in range(steps):
-                    t1 = time.perf_counter()
-                    C, st = h2.mul(ctx, A, B, eps)
-                    ts.append(time.perf_counter() - t1)
-                    del C
-                ts.sort()
-                med = ts[len(ts) // 2]
-                ge = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
-                row.update({"ms": med * 1e3, "us_per_dof": med * 1e6 / T.n, "first_call_ms": first * 1e3,
-                            "plan_ms": st0["t_plan_ms"], "storage_mb": ge["storage_mb"],
-                            "rel_error": ge["rel_spectral"], "precision_used": st["prec_used"],
-                            "rank_max": [st["rank_max_row"], st["rank_max_col"]], "n_adm": st["n_adm"],
-                            "n_inadm": st["n_inadm"]})
-                say(f"sweep {kind} level {lev} n={T.n}: {row['ms']:.1f} ms, {row['us_per_dof']:.3f} us/DOF, "
-                    f"{row['storage_mb']:.1f} MB, rel. error {row['rel_error']:.2e}")
-            except h2.H2Error as e:
-                row["error"] = str(e)
-                say(f"sweep {kind} level {lev} n={T.n}: {e}")
-            rows.append(row)
-            del A, B, T
+            ts.sort()
+            med = ts[len(ts) // 2]
+            ge = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
+            row.update({"ms": med * 1e3, "us_per_dof": med * 1e6 / T.n, "first_call_ms": first * 1e3,
+                        "plan_ms": st0["t_plan_ms"], "storage_mb": ge["storage_mb"],
+                        "rel_error": ge["rel_spectral"], "precision_used": st["prec_used"],
+                        "rank_max": [st["rank_max_row"], st["rank_max_col"]], "n_adm": st["n_adm"],
+                        "n_inadm": st["n_inadm"]})
+            say(f"sweep {kind} {geo} {size} n={T.n}: {row['ms']:.1f} ms, {row['us_per_dof']:.3f} us/DOF, "
+                f"{row['storage_mb']:.1f} MB, rel. error {row['rel_error']:.2e}")
+            del A, B
+        except h2.H2Error as e:
+            row["error"] = str(e)
+            say(f"sweep {kind} {geo} {size} n={T.n}: {e}")
+        rows.append(row)
+        del T
     return {"sweep": rows, "eps": eps, "steps": steps,
-            "config": {"geometry": "icosphere (triangle centroids, outward normals)", "leaf": 64, "eta": 1.0,
-                       "order": 4, "operators": {k: v["desc"] for k, v in SWEEP.items()}}}
+            "config": {"geometry": {"ico": "icosphere (triangle centroids, outward normals)",
+                                    "cube": "surface of [-1,1]^3, 12 m^2 triangle centroids, face normals"},
+                       "leaf": 64, "eta": 1.0, "order": 4,
+                       "operators": {k: v["desc"] for k, v in SWEEP.items()}}}
 
 
 def main():
@@ -266,6 +271,8 @@ def main():
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
     ap.add_argument("--sweep", default="", metavar="LEVELS",
                     help="comma-separated icosphere levels: time per DOF, storage and error per n, then exit")
+    ap.add_argument("--sweep-cube", default="", metavar="M",
+                    help="comma-separated squares per cube edge: K*K on the cube surface (n = 12 m^2)")
     ap.add_argument("--sweep-eps", type=float, default=1e-4)
     args = ap.parse_args()
     if args.copy_probe:
@@ -282,10 +289,11 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     from paper_2403_01566_amd import h2
-    if args.sweep:
+    if args.sweep or args.sweep_cube:
         ctx = h2.Context(0)
-        levels = [int(x) for x in args.sweep.split(",")]
-        print(json.dumps(sweep(h2, ctx, levels, max(1, args.steps), args.sweep_eps)), flush=True)
+        jobs = [(k, "ico", int(x)) for k in ("slp", "slp_dlp", "dlp") for x in args.sweep.split(",") if x]
+        jobs += [("dlp", "cube", int(x)) for x in args.sweep_cube.split(",") if x]
+        print(json.dumps(sweep(h2, ctx, jobs, max(1, args.steps), args.sweep_eps)), flush=True)
         return
     names = h2.kernel_names()
     cfg = WORKLOADS[args.workload]

@@ -107,6 +107,7 @@ struct SvdTask {
 struct RefMat {
   const double* a;
   int lda, rows, cols;
+  double scale;  // the matrix's largest row or column norm counts times scale
 };
 struct RefTask {
   int first, count;

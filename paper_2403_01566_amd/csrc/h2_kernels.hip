@@ -902,7 +902,9 @@ void launch_chol(const CholTask* tasks, int ntasks, int wmax, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Block-norm lower bounds for the coarsening tolerance.
 // ---------------------------------------------------------------------------
-// Largest row or column norm over the task's matrices.  A matrix of at most
+// Largest row or column norm over the task's matrices, each times its scale
+// (a 1 x 1 matrix gives its value: a norm bound or a largest singular value
+// computed earlier).  A matrix of at most
 // 128 columns is read once, row by row: the lanes of a wave cover a row (two
 // coalesced loads), a wave reduction gives its norm, and each lane keeps the
 // sums of its two columns (combined over the four waves in LDS).  Wider
@@ -915,6 +917,7 @@ __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ ta
   double best = 0.0;
   for (int q = 0; q < tk.count; ++q) {
     const RefMat m = mats[tk.first + q];
+    double bm = 0.0;  // largest squared row or column norm of this matrix
     if (m.cols <= 128) {
       const bool in0 = lane < m.cols, in1 = lane + 64 < m.cols;
       double c0 = 0.0, c1 = 0.0;
@@ -928,12 +931,12 @@ __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ ta
         s = dpp_group_sum(s, 16);
         s += __shfl_xor(s, 16);
         s += __shfl_xor(s, 32);
-        best = fmax(best, s);
+        bm = fmax(bm, s);
       }
       cols4[wv][lane] = c0;
       cols4[wv][lane + 64] = c1;
       __syncthreads();
-      if (tid < 128) best = fmax(best, (cols4[0][tid] + cols4[1][tid]) + (cols4[2][tid] + cols4[3][tid]));
+      if (tid < 128) bm = fmax(bm, (cols4[0][tid] + cols4[1][tid]) + (cols4[2][tid] + cols4[3][tid]));
       __syncthreads();
     } else {
       for (int r = tid; r < m.rows; r += blockDim.x) {
@@ -942,7 +945,7 @@ __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ ta
           const double x = m.a[(int64_t)r * m.lda + c];
           s += x * x;
         }
-        best = fmax(best, s);
+        bm = fmax(bm, s);
       }
       for (int c = tid; c < m.cols; c += blockDim.x) {
         double s = 0.0;
@@ -950,9 +953,10 @@ __global__ __launch_bounds__(256) void ref_kernel(const RefTask* __restrict__ ta
           const double x = m.a[(int64_t)r * m.lda + c];
           s += x * x;
         }
-        best = fmax(best, s);
+        bm = fmax(bm, s);
       }
     }
+    best = fmax(best, bm * (m.scale * m.scale));
   }
   red[tid] = best;
   __syncthreads();

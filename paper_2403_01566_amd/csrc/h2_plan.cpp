@@ -117,6 +117,9 @@ struct PRef {
 struct PRefMat {
   DRef<double> a;
   int lda, rows, cols;
+  // a largest singular value of a truncated sub-block: counted as
+  // sigma_1 / (1 + delta_c), a lower bound of the exact block's norm
+  bool approx = false;
 };
 struct PScan {
   int first, count;
@@ -1194,20 +1197,26 @@ void Planner::coarsen() {
       std::fprintf(stderr, "[h2 merge] height %d m<=%d n<=%d K %d count %d\n", std::get<0>(kv.first),
                    std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), kv.second);
   }
-  // Truncation errors of all merges of a block add up exactly; merges of equal
-  // height act on disjoint sub-blocks, so with a Frobenius tail <= tau at every
-  // merge the total error is at most tau * sum_h sqrt(n_h).  tau_b = delta_c *
-  // nu_b / sum_h sqrt(n_h), nu_b a lower bound of ||G_b|| from the leaves.
-  std::map<int, std::map<int, int>> per_height;
-  for (auto& x : mn) per_height[x.below][x.height]++;
-  std::map<int, double> hsum;
-  std::map<int, int64_t> tau;
-  for (auto& kv : per_height) {
-    double sum = 0;
-    for (auto& hv : kv.second) sum += std::sqrt((double)hv.second);
-    hsum[kv.first] = sum;
-    tau[kv.first] = B.wd(1).off;
+  // Truncation errors of all merges of a block add up exactly.  Merges of
+  // equal height act on disjoint sub-blocks, so their errors add in squares
+  // (Frobenius norm).  A merge of an m x n sub-block of the M x N block b
+  // keeps a Frobenius tail <= delta_c nu_b sqrt(m n / (M N)) / (H_b + 1)
+  // (H_b: highest merge of b); the errors of one height then total at most
+  // delta_c nu_b / (H_b + 1), and those of all heights delta_c nu_b.  nu_b is
+  // a lower bound of ||G_b|| held on the device: first the largest row or
+  // column norm of the leaves' condensed factors, raised after every height
+  // by the largest singular values of that height's merged sub-blocks.
+  std::map<int, int> hmax;
+  std::map<int, double> barea;
+  for (auto& x : mn) {
+    hmax[x.below] = std::max(hmax[x.below], x.height);
+    barea[x.below] = std::max(barea[x.below], (double)x.m * x.n);
   }
+  std::map<int, int64_t> tau;
+  for (auto& kv : hmax) tau[kv.first] = B.wd(1).off;
+  auto share = [&](const MNode& x) {
+    return std::sqrt((double)x.m * x.n / barea[x.below]) / (hmax[x.below] + 1);
+  };
   P.max_coarse_K = 0;
   for (int h = 0; h <= maxh; ++h) {
     std::vector<int> lv;
@@ -1322,7 +1331,7 @@ void Planner::coarsen() {
         PRef r;
         r.first = (int)st.refmat.size();
         r.count = (int)kv.second.size();
-        r.factor = 1.0 / hsum[kv.first];
+        r.factor = 1.0;
         r.out = Dw(tau[kv.first]);
         for (int i : kv.second) {
           const MNode& x = mn[i];
@@ -1346,7 +1355,7 @@ void Planner::coarsen() {
         s.rank = Iw(x.Kap);
         s.tolref = Dw(tau[x.below]);
         s.tolkind = 0;
-        s.tolfactor = 1.0;
+        s.tolfactor = share(x);
         s.w_dev = wd1(x);
         s.w_dev2 = wd2(x);
         s.lda = x.K;
@@ -1363,6 +1372,22 @@ void Planner::coarsen() {
           st.wmax = std::max(st.wmax, std::max(x.m, x.n));
         }
         st.svd.push_back(s);
+      }
+    }
+    std::map<int, std::vector<int>> byb;  // blocks with merges above this height
+    for (int i : lv)
+      if (hmax[mn[i].below] > h) byb[mn[i].below].push_back(i);
+    if (!byb.empty()) {  // raise nu_b: sigma_1 of this height's merged sub-blocks of b
+      Step& st = B.step(SK_REF);
+      for (auto& kv : byb) {
+        PRef r;
+        r.first = (int)st.refmat.size();
+        r.count = 1 + (int)kv.second.size();
+        r.factor = 1.0;
+        r.out = Dw(tau[kv.first]);
+        st.refmat.push_back({Dw(tau[kv.first]), 1, 1, 1});
+        for (int i : kv.second) st.refmat.push_back({Dw(mn[i].Sig), 1, 1, 1, true});
+        st.ref.push_back(r);
       }
     }
     {  // Y = G^ V_k  (= U^ Sigma)
@@ -1951,6 +1976,51 @@ static void share_workspace(Plan& P) {
   for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) use(*r);
   P.wsd_planned = P.wsd;
   P.wsf_planned = P.wsf;
+  if (std::getenv("H2_TRACE")) {  // live FP64 workspace per step; at the peak, split by the phase of first use
+    std::vector<int64_t> diff(nst + 2, 0);
+    for (size_t i = 0; i < ad.base.size(); ++i)
+      if (ad.last[i] >= 0) {
+        diff[ad.first[i]] += ad.size(i);
+        diff[ad.last[i] + 1] -= ad.size(i);
+      }
+    int64_t cur = 0, peak = 0;
+    int pk = 0;
+    for (int k = 0; k <= nst; ++k) {
+      cur += diff[k];
+      if (cur > peak) peak = cur, pk = k;
+    }
+    double by[8] = {0};
+    for (size_t i = 0; i < ad.base.size(); ++i)
+      if (ad.last[i] >= 0 && ad.first[i] <= pk && ad.last[i] >= pk)
+        by[ad.first[i] < nst ? P.steps[ad.first[i]].phase : 7] += ad.size(i) * 8e-9;
+    std::vector<std::pair<int64_t, size_t>> big;
+    for (size_t i = 0; i < ad.base.size(); ++i)
+      if (ad.last[i] >= 0 && ad.first[i] <= pk && ad.last[i] >= pk) big.push_back({ad.size(i), i});
+    std::sort(big.rbegin(), big.rend());
+    for (size_t j = 0; j < std::min<size_t>(big.size(), 6); ++j)
+      std::fprintf(stderr, "[h2 plan]   live at peak: %.3f GB, steps %d..%d\n", big[j].first * 8e-9,
+                   ad.first[big[j].second], ad.last[big[j].second]);
+    std::fprintf(stderr, "[h2 plan]   %zu buffers live at peak\n", big.size());
+    std::map<std::pair<int, int>, std::pair<int64_t, int>> grp;
+    for (auto& b : big) {
+      auto& g = grp[{ad.first[b.second], ad.last[b.second]}];
+      g.first += b.first;
+      g.second += 1;
+    }
+    std::vector<std::pair<int64_t, std::pair<int, int>>> gs;
+    for (auto& g : grp) gs.push_back({g.second.first, g.first});
+    std::sort(gs.rbegin(), gs.rend());
+    for (size_t j = 0; j < std::min<size_t>(gs.size(), 12); ++j)
+      std::fprintf(stderr, "[h2 plan]   group steps %d..%d (kinds %d..%d): %.3f GB in %d buffers\n",
+                   gs[j].second.first, gs[j].second.second, (int)P.steps[gs[j].second.first].kind,
+                   gs[j].second.second < nst ? (int)P.steps[gs[j].second.second].kind : -1, gs[j].first * 8e-9,
+                   grp[gs[j].second].second);
+    std::fprintf(stderr,
+                 "[h2 plan] peak live fp64 %.3f GB at step %d (phase %d): by phase of first use prep %.3f exact "
+                 "%.3f leaf %.3f coarse %.3f row %.3f col %.3f couple %.3f result %.3f GB\n",
+                 peak * 8e-9, pk, pk < nst ? P.steps[pk].phase : -1, by[0], by[1], by[2], by[3], by[4], by[5], by[6],
+                 by[7]);
+  }
   P.wsd = ad.place();
   P.wsf = af.place();
   auto remap = [&](auto& r) {
@@ -1959,6 +2029,13 @@ static void share_workspace(Plan& P) {
   };
   for (auto& st : P.steps) visit_refs(st, remap);
   for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) remap(*r);
+}
+
+// Scale of a matrix in a block-norm bound: an approximate sub-block's
+// sigma_1 exceeds the exact sub-block's norm by at most the truncation error
+// made so far, which is <= delta_c times the block's norm.
+static double ref_scale(const Plan& P, const PRefMat& m, double eps) {
+  return m.approx ? 1.0 / (1.0 + eps * P.budget[0]) : 1.0;
 }
 
 static void finalize(Plan& P, double eps) {
@@ -2028,7 +2105,7 @@ static void finalize(Plan& P, double eps) {
         align(64);
         st.desc2_off = blob.size();
         for (auto& m : st.refmat) {
-          h2k::RefMat t{res(m.a, P), m.lda, m.rows, m.cols};
+          h2k::RefMat t{res(m.a, P), m.lda, m.rows, m.cols, ref_scale(P, m, eps)};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.ref.size();
@@ -2073,6 +2150,17 @@ static void set_eps(Plan& P, double eps) {
       resolve_svd(P, st, P.hdesc, eps, true);
       H2_HIP(hipMemcpy((char*)P.desc.p + st.desc_off, P.hdesc.data() + st.desc_off,
                        st.ndesc * sizeof(h2k::SvdTask), hipMemcpyHostToDevice));
+    } else if (st.kind == SK_REF) {
+      auto* mats = (h2k::RefMat*)(P.hdesc.data() + st.desc2_off);
+      bool any = false;
+      for (size_t i = 0; i < st.refmat.size(); ++i)
+        if (st.refmat[i].approx) {
+          mats[i].scale = ref_scale(P, st.refmat[i], eps);
+          any = true;
+        }
+      if (any)
+        H2_HIP(hipMemcpy((char*)P.desc.p + st.desc2_off, mats, st.refmat.size() * sizeof(h2k::RefMat),
+                         hipMemcpyHostToDevice));
     }
   P.eps_set = eps;
 }

@@ -12,6 +12,10 @@ Workloads (stand-ins for the paper's Galerkin meshes, Section 6):
     midpoints projected to the unit sphere; returns the 20*4^level triangle
     centroids (not projected) and the outward unit face normals.
   * ``fibsphere(n)``: Fibonacci lattice on the unit sphere; normals = points.
+  * ``cube_surface(m)``: surface of [-1,1]^3, every face cut into m x m
+    squares and every square into two triangles; returns the 12*m^2 triangle
+    centroids and the outward face normals (the double-layer geometry of the
+    paper's experiments: n = 3072 for m = 16, 6912 for m = 24, ...).
 """
 from __future__ import annotations
 
@@ -102,6 +106,34 @@ def icosphere(level: int):
     sgn = np.sign(np.einsum("ij,ij->i", nrm, cen))
     nrm *= sgn[:, None]
     return cen, nrm
+
+
+def cube_surface(m: int):
+    """Returns (centroids [12 m^2, 3], outward unit normals [12 m^2, 3]).
+    Face order -x, +x, -y, +y, -z, +z; on a face the two in-plane axes run in
+    increasing index order, squares row-major; each square (lower-left corner
+    (u, v), side h = 2/m) gives the triangles (u,v),(u+h,v),(u+h,v+h) and
+    (u,v),(u+h,v+h),(u,v+h), with centroids at (u + 2h/3, v + h/3) and
+    (u + h/3, v + 2h/3)."""
+    h = 2.0 / m
+    g = -1.0 + h * np.arange(m, dtype=np.float64)
+    U, V = np.meshgrid(g, g, indexing="ij")
+    U, V = U.ravel(), V.ravel()
+    tri = np.stack([np.stack([U + 2 * h / 3, V + h / 3], 1), np.stack([U + h / 3, V + 2 * h / 3], 1)], 1)
+    tri = tri.reshape(-1, 2)  # 2 m^2 in-plane centroids, the two triangles of a square adjacent
+    cen, nrm = [], []
+    for axis in range(3):
+        others = [a for a in range(3) if a != axis]
+        for sign in (-1.0, 1.0):
+            c = np.empty((tri.shape[0], 3))
+            c[:, axis] = sign
+            c[:, others[0]] = tri[:, 0]
+            c[:, others[1]] = tri[:, 1]
+            nv = np.zeros((tri.shape[0], 3))
+            nv[:, axis] = sign
+            cen.append(c)
+            nrm.append(nv)
+    return np.concatenate(cen), np.concatenate(nrm)
 
 
 def fibsphere(n: int):

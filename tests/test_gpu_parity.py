@@ -47,6 +47,9 @@ def _geometry(case):
         return dict(P=P, nrm=n, leaf=20, kern=1, order=2, eta=1.0, diag=1, dlp=True)
     if case == "random2d":
         return dict(P=W.uniform2d(900, 11), nrm=None, leaf=24, kern=0, order=4, eta=0.5, diag=0)
+    if case == "cube_dlp":
+        P, n = W.cube_surface(8)
+        return dict(P=P, nrm=n, leaf=32, kern=2, order=3, eta=1.0, diag=0)
     if case == "tiny":
         return dict(P=W.uniform2d(30, 4), nrm=None, leaf=32, kern=0, order=3, eta=0.5, diag=0)
     raise KeyError(case)
@@ -104,6 +107,8 @@ CASES = [
     ("sphere2dlp", 1e-4, 0),
     ("random2d", 1e-5, 0),
     ("random2d", 1e-4, 1),
+    ("cube_dlp", 1e-4, 0),
+    ("cube_dlp", 1e-6, 0),
 ]
 
 
