@@ -63,6 +63,9 @@ h2_status h2_context_create(int device, h2_context* out) {
       ctx->c.device = device;
       H2_HIP(hipSetDevice(device));
       H2_HIP(hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking));
+      for (auto& a : ctx->c.aux) H2_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+      H2_HIP(hipEventCreateWithFlags(&ctx->c.fork, hipEventDisableTiming));
+      for (auto& e : ctx->c.join) H2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       H2_HIP(hipMalloc((void**)&ctx->c.overflow, sizeof(int)));
     } catch (...) {
       delete ctx;

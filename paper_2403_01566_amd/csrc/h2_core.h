@@ -132,6 +132,10 @@ struct MvPlan;
 struct Context {
   int device = 0;
   hipStream_t stream = nullptr;
+  // two more streams (default priority) for the size classes of one QR or SVD
+  // step, which are independent launches; fork and join events
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
   int* overflow = nullptr;  // device flag set by rank-cap overflows
   std::map<std::pair<uint64_t, uint64_t>, std::shared_ptr<Plan>> plans;
   // operand pairs whose FP32 bulk exceeded a rank cap: largest such eps (those

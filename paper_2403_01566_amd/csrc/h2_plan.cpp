@@ -2201,7 +2201,7 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
     hipEvent_t a, b;
   };
   std::vector<KEv> kev;
-  auto timed = [&](int kid, size_t step, auto&& launch) {
+  auto timed_on = [&](hipStream_t on, int kid, size_t step, auto&& launch) {
     ++P.launches;
     ++P.launches_k[kid];
     if (!per_kernel) {
@@ -2211,10 +2211,26 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
     KEv e{kid, step, nullptr, nullptr};
     H2_HIP(hipEventCreate(&e.a));
     H2_HIP(hipEventCreate(&e.b));
-    H2_HIP(hipEventRecord(e.a, s));
+    H2_HIP(hipEventRecord(e.a, on));
     launch();
-    H2_HIP(hipEventRecord(e.b, s));
+    H2_HIP(hipEventRecord(e.b, on));
     kev.push_back(e);
+  };
+  auto timed = [&](int kid, size_t step, auto&& launch) { timed_on(s, kid, step, launch); };
+  // The size classes of a QR or SVD step are independent launches over the
+  // same tasks (each workgroup exits unless its task's device-side width is
+  // in the class): class c > 0 runs on aux stream c - 1, forked from and
+  // joined back into the main stream.
+  auto classes = [&](int ncls, auto&& launch_class) {
+    if (ncls > 1) {
+      H2_HIP(hipEventRecord(ctx->fork, s));
+      for (int c = 1; c < ncls; ++c) H2_HIP(hipStreamWaitEvent(ctx->aux[c - 1], ctx->fork, 0));
+    }
+    for (int c = 0; c < ncls; ++c) launch_class(c, c == 0 ? s : ctx->aux[c - 1]);
+    for (int c = 1; c < ncls; ++c) {
+      H2_HIP(hipEventRecord(ctx->join[c - 1], ctx->aux[c - 1]));
+      H2_HIP(hipStreamWaitEvent(s, ctx->join[c - 1], 0));
+    }
   };
   size_t si = 0;
   for (auto& st : P.steps) {
@@ -2241,16 +2257,18 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
         break;
       case SK_QR:
         if (st.ndesc > 0)
-          for (int c = 0; c < h2k::size_classes(st.wmax); ++c)
-            timed(h2k::K_QR32 + c, si,
-                  [&] { h2k::launch_qr_class((const h2k::QrTask*)(base + st.desc_off), st.ndesc, c, s); });
+          classes(h2k::size_classes(st.wmax), [&](int c, hipStream_t on) {
+            timed_on(on, h2k::K_QR32 + c, si,
+                     [&] { h2k::launch_qr_class((const h2k::QrTask*)(base + st.desc_off), st.ndesc, c, on); });
+          });
         break;
       case SK_SVD:
         if (st.ndesc > 0)
-          for (int c = 0; c < h2k::size_classes(st.wmax); ++c)
-            timed(h2k::K_SVD32 + c, si, [&] {
-              h2k::launch_svd_class((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, c, ctx->overflow, s);
+          classes(h2k::size_classes(st.wmax), [&](int c, hipStream_t on) {
+            timed_on(on, h2k::K_SVD32 + c, si, [&] {
+              h2k::launch_svd_class((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, c, ctx->overflow, on);
             });
+          });
         break;
       case SK_CHOL:
         if (st.ndesc > 0)

@@ -174,6 +174,14 @@ Context::~Context() {
   plans.clear();
   mvplans.clear();
   if (overflow) (void)hipFree(overflow);
+  for (auto& a : aux)
+    if (a) {
+      (void)hipStreamSynchronize(a);
+      (void)hipStreamDestroy(a);
+    }
+  if (fork) (void)hipEventDestroy(fork);
+  for (auto& e : join)
+    if (e) (void)hipEventDestroy(e);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
