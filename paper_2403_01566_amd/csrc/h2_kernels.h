@@ -26,6 +26,10 @@ struct GemmItem {
   double alpha;
 };
 
+// Width of the K slices of the batched GEMM: a task's nslice is the sum over
+// its product items of ceil(k / kGemmSliceK).
+constexpr int kGemmSliceK = 8;
+
 // One output matrix C (m x n, row-major, ldc): C = (beta ? C : 0) + sum of items.
 // Optional device ints: m_dev / n_dev lower m / n to min(m, *m_dev) etc.,
 // coff_dev shifts the output by *coff_dev columns and roff_dev by *roff_dev

@@ -43,7 +43,9 @@ struct Mfma<float> {
   __device__ static inline int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-constexpr int GBM = 64, GBN = 64, GBK = 16;
+constexpr int GBM = 64, GBN = 64, GBK = kGemmSliceK;
+constexpr int GQA = GBM * GBK / 256, GQB = GBN * GBK / 256;  // loads per thread and slice
+static_assert(GQA >= 1 && GQB >= 1 && GBM * GBK % 256 == 0 && GBK % 4 == 0, "GEMM tile shape");
 
 // MFMA 16x16x4 register layout used below (gfx950, checked on the device):
 //   A operand: lane l supplies A[l % 16][k0 + l / 16]
@@ -71,14 +73,17 @@ __device__ inline void gstore(T* p, T v) {
 
 template <typename T>
 struct GemmSlice {
-  T a[4], b[4];
+  T a[GQA], b[GQB];
 };
 
+// The occupancy hint (at least 5 waves per SIMD) keeps the accumulators in
+// VGPRs: 69 registers and no AGPRs give 7 waves per SIMD, where the default
+// choice (accumulators in AGPRs, 100 registers) gives 4.
 template <typename T>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict__ items,
+__global__ __launch_bounds__(256, 5) void gemm_kernel(const GemmItem<T>* __restrict__ items,
                                                    const GemmTask<T>* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles) {
-  __shared__ T As[2][GBK][GBM + 1];  // odd row stride: the 16 lanes that store one column of a slice hit distinct banks
+  __shared__ T As[2][GBK][GBM + 1];  // odd row stride: the lanes that store one column of a slice hit distinct banks
   __shared__ T Bs[2][GBK][GBN + 1];
   typedef typename Mfma<T>::acc acc_t;
   const GemmTile tl = tiles[blockIdx.x];
@@ -157,19 +162,19 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
       const int64_t sa = ta ? 1 : item.lda, ska = ta ? item.lda : 1;
       const int64_t sb = tb ? item.ldb : 1, skb = tb ? 1 : item.ldb;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GQA; ++q) {
         int e = tid + 256 * q;
         int i, kk;
-        if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
+        if (!ta) { i = e / GBK; kk = e % GBK; } else { kk = e / GBM; i = e % GBM; }
         const int gi = m0 + i, gk = k0 + kk;
         const bool in = gi < tk.m && gk < kend;
         g.a[q] = gload(item.a + (in ? gi * sa + gk * ska : 0));
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GQB; ++q) {
         int e = tid + 256 * q;
         int j, kk;
-        if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
+        if (!tb) { kk = e / GBN; j = e % GBN; } else { j = e / GBK; kk = e % GBK; }
         const int gj = n0 + j, gk = k0 + kk;
         const bool in = gj < tk.n && gk < kend;
         g.b[q] = gload(item.b + (in ? gj * sb + gk * skb : 0));
@@ -178,18 +183,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmItem<T>* __restrict
     auto store = [&](const GemmSlice<T>& g, int buf) {  // same item and k0 as the load
       const bool ta = item.flags & IT_TRANS_A, tb = item.flags & IT_TRANS_B;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GQA; ++q) {
         int e = tid + 256 * q;
         int i, kk;
-        if (!ta) { i = e >> 4; kk = e & 15; } else { kk = e >> 6; i = e & 63; }
+        if (!ta) { i = e / GBK; kk = e % GBK; } else { kk = e / GBM; i = e % GBM; }
         const bool in = m0 + i < tk.m && k0 + kk < kend;
         As[buf][kk][i] = in ? al * g.a[q] : T(0);
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < GQB; ++q) {
         int e = tid + 256 * q;
         int j, kk;
-        if (!tb) { kk = e >> 6; j = e & 63; } else { j = e >> 4; kk = e & 15; }
+        if (!tb) { kk = e / GBN; j = e % GBN; } else { j = e / GBK; kk = e % GBK; }
         const bool in = n0 + j < tk.n && k0 + kk < kend;
         Bs[buf][kk][j] = in ? g.b[q] : T(0);
       }

@@ -1767,7 +1767,7 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     for (int q = 0; q < tk[i].nitem; ++q) {
       const auto& x = it[tk[i].item0 + q];
       if (x.flags & h2k::IT_COPY) ++tasks[i].ncopy;
-      else tasks[i].nslice += (x.k + 15) / 16;
+      else tasks[i].nslice += (x.k + h2k::kGemmSliceK - 1) / h2k::kGemmSliceK;
     }
     for (int m0 = 0; m0 < tk[i].m; m0 += 64)
       for (int n0 = 0; n0 < tk[i].n; n0 += 64) tiles.push_back({(int)i, m0, n0, 0});

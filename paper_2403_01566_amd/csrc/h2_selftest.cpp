@@ -59,7 +59,7 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
   std::vector<T> c0((size_t)m * n);
   for (auto& x : c0) x = (T)g.next();
   T* dc = up(c0, keep);
-  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1, nitem * ((k + 15) / 16), 0};
+  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1, nitem * ((k + h2k::kGemmSliceK - 1) / h2k::kGemmSliceK), 0};
   std::vector<h2k::GemmTile> tiles;
   for (int i = 0; i < m; i += 64)
     for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
