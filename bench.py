@@ -267,6 +267,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
+    ap.add_argument("--no-global-error", action="store_true",
+                    help="skip the untimed power-iteration error (profiled runs: only the products' kernels)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
     ap.add_argument("--sweep", default="", metavar="LEVELS",
@@ -345,8 +347,9 @@ def main():
                          "precision_used": "fp32_bulk" if x["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"}
                   for name, x in res.items()},
     }
-    say("global error of one product (10 power-iteration steps, untimed)")
-    out["global_error"] = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
+    if not args.no_global_error:
+        say("global error of one product (10 power-iteration steps, untimed)")
+        out["global_error"] = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
     if not args.no_cpu_baseline:
         say("oracle on the host cores (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(h2, ctx, cfg, st["flops_alg"])

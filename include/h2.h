@@ -169,6 +169,37 @@ h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld);
  * h2_matrix_blocks).  out: |t| x |s| row-major in tree order. */
 h2_status h2_block_dense(h2_matrix M, int64_t b, double* out);
 
+/* Leaves of the block tree of (rows, cols) with admissibility parameter eta
+ * (the condition max(diam) <= 2 eta dist of Section 2, the tree of every
+ * matrix built here): *n_adm admissible and *n_inadm inadmissible leaves.
+ * If pairs is not NULL it receives 2 (n_adm + n_inadm) ints, the cluster
+ * pairs (t, s), admissible leaves first: the order h2_recompress expects.
+ * Call with pairs = NULL to learn the sizes. */
+h2_status h2_block_tree_leaves(h2_tree rows, h2_tree cols, double eta, int64_t* n_adm, int64_t* n_inadm,
+                               int* pairs);
+
+/* H -> H2 recompression with block-relative error (the second half of the
+ * method, Section 5, on its own): an H-matrix G on the block tree of (rows,
+ * cols, eta) becomes an H2-matrix C with adaptively chosen row and column
+ * bases and ||G|_b - C|_b||_2 <= eps ||G|_b||_2 on every admissible leaf b
+ * (the same error split as h2_mul: truncation of each block, row basis,
+ * column basis); the nearfield is copied.
+ *   ranks[i], U, Z: admissible leaf i (order of h2_block_tree_leaves) is
+ *     G_i = U_i Z_i^T with U_i |t| x k_i and Z_i |s| x k_i, k_i = ranks[i] in
+ *     [1, 128] (a zero block: rank 1, zero factors); the U_i are packed one
+ *     after the other in leaf order, row-major, rows in tree order (cluster
+ *     t covers positions begin(t) .. end(t)-1 of h2_tree_permutation), and
+ *     the Z_i likewise.
+ *   near: the inadmissible leaves' dense |t| x |s| blocks, row-major, packed
+ *     in leaf order.
+ * Host arrays, read during the call. opts: max_rank, coarse_rank (truncated
+ * block rank cap), theta, budgets and timing as for h2_mul; precision is
+ * FP64. Errors: INVALID_ARG (ranks, eps, non-finite input), TOO_LARGE (a
+ * rank cap), OUT_OF_MEMORY. Synchronous. */
+h2_status h2_recompress(h2_context ctx, h2_tree rows, h2_tree cols, double eta, const int* ranks, const double* U,
+                        const double* Z, const double* near, double eps, const h2_mul_options* opts, h2_matrix* C,
+                        h2_mul_stats* stats);
+
 /* Matrix-vector product with an H2-matrix (Section 2: O(nk) operations with
  * the nested bases): y = M x (trans = 0) or y = M^T x (trans = 1) for nrhs
  * vectors at once.  x holds cols(M) x nrhs (rows(M) x nrhs when trans) and y

@@ -177,6 +177,14 @@ def mul(X: H2Matrix, Y: H2Matrix, eps: float, TC: BlockTree | None = None,
                 visit(t2, r2, A2, B2, N2, pend2, tc2)
 
     visit(0, 0, None, None, None, [0], ("node", (0, 0)))
+    return _recompress(TI, TK, TC, finals, near, eps, theta, budget, info)
+
+
+def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
+    """Steps 3-6 of the header on the exact factors `finals` (admissible result
+    leaf b -> list of (t', r', [U], [Z]) pieces of G_b below or at b) and the
+    dense nearfield `near`: coarsening, weighted row and column bases,
+    couplings (Section 5)."""
 
     # ---------------- coarsening (Section 5.1) ----------------
     dc, dr, dw = (eps * f for f in budget)
@@ -299,6 +307,25 @@ def mul(X: H2Matrix, Y: H2Matrix, eps: float, TC: BlockTree | None = None,
     info.counts["inadm_blocks"] = len(TC.inadm)
     info.theta, info.tol_r, info.tol_w, info.delta_c = th, tol_r, tol_w, dc
     return C, info
+
+
+def recompress(TI, TK, eta, factors, near, eps, theta=None, budget=(0.25, 0.25, 0.25), info=None):
+    """H -> H2 recompression with block-relative error (Section 5 on its own):
+    an H-matrix on the block tree of (TI, TK, eta), given by factors
+    factors[b] = (U_b, Z_b) with G_b = U_b Z_b^* for every admissible leaf b
+    and dense blocks near[b] for every inadmissible leaf, becomes an H2-matrix
+    with adaptive bases: the truncation of each G_b (the coarsening step with
+    a single piece), then the weighted bases and the couplings."""
+    if not (0.0 < eps < 1.0):
+        raise ValueError("eps must be in (0,1)")
+    TC = BlockTree(TI, TK, eta)
+    if set(factors) != set(TC.adm) or set(near) != set(TC.inadm):
+        raise ValueError("blocks do not match the block tree")
+    info = info if info is not None else MulInfo()
+    finals = {b: [(b[0], b[1], [np.asarray(factors[b][0], dtype=np.float64)],
+                   [np.asarray(factors[b][1], dtype=np.float64)])] for b in TC.adm}
+    nearf = {b: np.asarray(near[b], dtype=np.float64) for b in TC.inadm}
+    return _recompress(TI, TK, TC, finals, nearf, eps, theta, budget, info)
 
 
 def block_errors(X: H2Matrix, Y: H2Matrix, C: H2Matrix):

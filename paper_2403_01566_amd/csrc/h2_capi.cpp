@@ -201,6 +201,67 @@ h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld) {
   });
 }
 
+h2_status h2_block_tree_leaves(h2_tree rows, h2_tree cols, double eta, int64_t* n_adm, int64_t* n_inadm,
+                               int* pairs) {
+  return guard([&] {
+    require(rows && cols && n_adm && n_inadm, "null argument");
+    require(eta > 0.0 && std::isfinite(eta), "eta must be positive");
+    require(rows->t->dim == cols->t->dim, "trees of different dimension");
+    h2::BlockTree bt;
+    h2::build_block_tree(bt, *rows->t, *cols->t, eta);
+    *n_adm = (int64_t)bt.adm.size();
+    *n_inadm = (int64_t)bt.inadm.size();
+    if (pairs) {
+      int64_t q = 0;
+      for (int i : bt.adm) {
+        pairs[q++] = bt.nodes[i].t;
+        pairs[q++] = bt.nodes[i].s;
+      }
+      for (int i : bt.inadm) {
+        pairs[q++] = bt.nodes[i].t;
+        pairs[q++] = bt.nodes[i].s;
+      }
+    }
+  });
+}
+
+h2_status h2_recompress(h2_context ctx, h2_tree rows, h2_tree cols, double eta, const int* ranks, const double* U,
+                        const double* Z, const double* near, double eps, const h2_mul_options* opt, h2_matrix* C,
+                        h2_mul_stats* stats) {
+  if (C) *C = nullptr;
+  return guard([&] {
+    require(ctx && rows && cols && C, "null argument");
+    require(rows->ctx == ctx && cols->ctx == ctx, "trees belong to another context");
+    h2_mul_options o;
+    h2_mul_default_options(&o);
+    if (opt) o = *opt;
+    set_device(ctx);
+    h2::BlockTree bt;
+    require(eta > 0.0 && std::isfinite(eta), "eta must be positive");
+    h2::build_block_tree(bt, *rows->t, *cols->t, eta);
+    int64_t nu = 0, nz = 0, nn = 0;
+    if (!bt.adm.empty()) require(ranks && U && Z, "null factor arrays");
+    for (size_t i = 0; i < bt.adm.size(); ++i) {
+      require(ranks[i] >= 1 && ranks[i] <= 128, "block rank outside [1, 128]");
+      nu += rows->t->size(bt.nodes[bt.adm[i]].t) * ranks[i];
+      nz += cols->t->size(bt.nodes[bt.adm[i]].s) * ranks[i];
+    }
+    for (int i : bt.inadm) nn += rows->t->size(bt.nodes[i].t) * cols->t->size(bt.nodes[i].s);
+    if (nn) require(near != nullptr, "null nearfield array");
+    for (int64_t i = 0; i < nu; ++i) require(std::isfinite(U[i]), "non-finite factor entry");
+    for (int64_t i = 0; i < nz; ++i) require(std::isfinite(Z[i]), "non-finite factor entry");
+    for (int64_t i = 0; i < nn; ++i) require(std::isfinite(near[i]), "non-finite nearfield entry");
+    auto* m = new h2_matrix_s;
+    try {
+      m->m = h2::recompress(&ctx->c, rows->t, cols->t, eta, ranks, U, Z, near, eps, o, stats);
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *C = m;
+  });
+}
+
 h2_status h2_matvec(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y) {
   return guard([&] {
     require(M && x && y, "null argument");

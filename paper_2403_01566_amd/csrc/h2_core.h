@@ -155,6 +155,14 @@ std::unique_ptr<Matrix> build_interpolated(Context* ctx, std::shared_ptr<Tree> r
 std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
                                  h2_mul_stats* stats);
 
+// H -> H2 recompression of an H-matrix on the block tree of (R, C, eta):
+// factors U_b (|t| x k_b) and Z_b (|s| x k_b) of the admissible leaves packed
+// in leaf order, dense nearfield blocks packed in inadmissible-leaf order
+// (host arrays, tree order, row-major).
+std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::shared_ptr<Tree> C, double eta,
+                                   const int* ranks, const double* U, const double* Z, const double* near,
+                                   double eps, const h2_mul_options& opt, h2_mul_stats* stats);
+
 // y = M x (trans = 0) or M^T x (trans = 1) for nrhs vectors, host arrays in
 // the original point order, row-major (one vector per column).
 void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y);

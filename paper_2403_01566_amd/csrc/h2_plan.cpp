@@ -180,6 +180,9 @@ struct Plan {
   BlockTree cbt;
   std::vector<int64_t> cnoff;
   int64_t cnsize = 0;
+  // workspace regions filled from the host before the first step (inputs of a
+  // recompression): live from the first step on
+  std::vector<DRef<double>> inputs;
   double bytes_alg = 0, flops_alg = 0;
   int64_t n_adm = 0, n_inadm = 0;
   bool f32 = false;
@@ -437,6 +440,11 @@ class Planner {
   Planner(Context* c, Matrix* x, Matrix* y, Plan& p, int kc_, int kcap_)
       : ctx(c), X(x), Y(y), TI(*x->rows), TJ(*x->cols), TK(*y->cols), kX(x->kc), kY(y->kc), P(p), B(p),
         C(p.cbt), kc(kc_), kcap(kcap_) {}
+  // recompression of given blocks: no operands, only the result's trees (the
+  // coarsening, basis and coupling stages read nothing else)
+  Planner(Context* c, const Tree& rows, const Tree& cols, Plan& p, int kc_, int kcap_)
+      : ctx(c), X(nullptr), Y(nullptr), TI(rows), TJ(rows), TK(cols), kX(0), kY(0), P(p), B(p), C(p.cbt), kc(kc_),
+        kcap(kcap_) {}
 
   void build_union();
   template <typename T>
@@ -1968,6 +1976,7 @@ static void share_workspace(Plan& P) {
     if (r.ws == WS_D) ad.use(r.off, si);
     else if (r.ws == WS_F) af.use(r.off, si);
   };
+  for (auto& r : P.inputs) use(r);  // filled before the first step
   for (auto& st : P.steps) {
     visit_refs(st, use);
     ++si;
@@ -2029,6 +2038,7 @@ static void share_workspace(Plan& P) {
   };
   for (auto& st : P.steps) visit_refs(st, remap);
   for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) remap(*r);
+  for (auto& r : P.inputs) remap(r);
 }
 
 // Scale of a matrix in a block-norm bound: an approximate sub-block's
@@ -2422,6 +2432,34 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
 }
 
 // ------------------------------------------------------------------ multiply
+// Algorithmic flops and bytes of the QR, SVD, Cholesky, fill and conversion
+// steps from their planned sizes (GEMM steps count theirs when emitted).
+static void count_work(Plan& P) {
+  double fl = 0;
+  for (auto& st : P.steps) {
+    if (st.kind == SK_QR)
+      for (auto& q : st.qr) {
+        st.flops += 2.0 * q.m * q.w * q.w;
+        st.bytes += 8.0 * ((double)q.m * q.w + (double)q.w * q.w);
+      }
+    if (st.kind == SK_SVD)
+      for (auto& v : st.svd) {
+        st.flops += 8.0 * 4.0 * v.rows * (double)v.cols * v.cols;  // about 8 sweeps of w^2/2 rotations
+        st.bytes += 8.0 * ((double)v.rows * v.cols + (double)v.rows * v.kcap + v.cols);
+      }
+    if (st.kind == SK_CHOL)
+      for (auto& c : st.chol) {
+        st.flops += 2.0 * c.w * c.w * c.w;
+        st.bytes += 8.0 * 3.0 * c.w * c.w;
+      }
+    if (st.kind == SK_FILL)
+      for (auto& f : st.fill) st.bytes += 8.0 * f.m * f.n;
+    if (st.kind == SK_CVT_F2D) st.bytes += 12.0 * st.cvt_n;
+    fl += st.flops;
+  }
+  P.flops_alg = fl;
+}
+
 static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
                                        const h2_mul_options& opt, double eps) {
   auto P = std::make_shared<Plan>();
@@ -2467,29 +2505,7 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   pl.couplings();
   P->n_adm = P->cbt.adm.size();
   P->n_inadm = P->cbt.inadm.size();
-  double fl = 0;
-  for (auto& st : P->steps) {
-    if (st.kind == SK_QR)
-      for (auto& q : st.qr) {
-        st.flops += 2.0 * q.m * q.w * q.w;
-        st.bytes += 8.0 * ((double)q.m * q.w + (double)q.w * q.w);
-      }
-    if (st.kind == SK_SVD)
-      for (auto& v : st.svd) {
-        st.flops += 8.0 * 4.0 * v.rows * (double)v.cols * v.cols;  // about 8 sweeps of w^2/2 rotations
-        st.bytes += 8.0 * ((double)v.rows * v.cols + (double)v.rows * v.kcap + v.cols);
-      }
-    if (st.kind == SK_CHOL)
-      for (auto& c : st.chol) {
-        st.flops += 2.0 * c.w * c.w * c.w;
-        st.bytes += 8.0 * 3.0 * c.w * c.w;
-      }
-    if (st.kind == SK_FILL)
-      for (auto& f : st.fill) st.bytes += 8.0 * f.m * f.n;
-    if (st.kind == SK_CVT_F2D) st.bytes += 12.0 * st.cvt_n;
-    fl += st.flops;
-  }
-  P->flops_alg = fl;
+  count_work(*P);
   // algorithmic bytes: operand storage read once, result written once, and every
   // intermediate array written once and read once
   const double w8 = 8.0;
@@ -2875,4 +2891,171 @@ void product_error(Matrix* X, Matrix* Y, Matrix* C, int iters, const double* z0,
   H2_HIP(hipStreamSynchronize(s));
 }
 
+}  // namespace h2
+
+// ------------------------------------------------------------------ H -> H2 recompression
+// An H-matrix given on the block tree of (R, Cc, eta) by factors G_b = U_b Z_b^*
+// of its admissible leaves and dense nearfield blocks is turned into an
+// H2-matrix with adaptive row and column bases (Section 5: the truncation of
+// each block to its Frobenius tail, then the weighted bases and the couplings
+// of Sections 5.2 and 5.3). The plan is built per call: the factors are
+// uploaded into workspace regions that stay live from the first step on.
+namespace h2 {
+std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::shared_ptr<Tree> Cc, double eta,
+                                   const int* ranks, const double* U, const double* Z, const double* near,
+                                   double eps, const h2_mul_options& opt, h2_mul_stats* stats) {
+  if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
+  if (!(eta > 0.0) || !std::isfinite(eta)) throw Error(H2_ERR_INVALID_ARG, "eta must be positive");
+  if (R->dim != Cc->dim) throw Error(H2_ERR_INCOMPATIBLE, "row and column trees of different dimension");
+  const int kc = opt.max_rank > 0 ? opt.max_rank : 64;
+  const int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
+  if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
+  auto t0 = std::chrono::steady_clock::now();
+  auto P = std::make_shared<Plan>();
+  P->kc = kc;
+  P->kappa_cap = kcap;
+  int sigma_br = 2;
+  for (auto& ch : R->children) sigma_br = std::max<int>(sigma_br, (int)ch.size());
+  for (auto& ch : Cc->children) sigma_br = std::max<int>(sigma_br, (int)ch.size());
+  P->sigma_br = sigma_br;
+  P->theta = opt.theta > 0 ? opt.theta : 1.0 / (2.0 * sigma_br);
+  if (!(P->theta * sigma_br < 1.0)) throw Error(H2_ERR_INVALID_ARG, "theta must be below 1/sigma");
+  P->budget[0] = opt.budget_coarse > 0 ? opt.budget_coarse : 0.25;
+  P->budget[1] = opt.budget_row > 0 ? opt.budget_row : 0.25;
+  P->budget[2] = opt.budget_col > 0 ? opt.budget_col : 0.25;
+  build_block_tree(P->cbt, *R, *Cc, eta);
+  const BlockTree& bt = P->cbt;
+  Planner pl(ctx, *R, *Cc, *P, kc, kcap);
+  Builder& B = pl.B;
+  P->res_vleaf = B.wd(R->n * kc);
+  P->res_vtr = B.wd((int64_t)R->ncl * kc * kc);
+  P->res_wleaf = B.wd(Cc->n * kc);
+  P->res_wtr = B.wd((int64_t)Cc->ncl * kc * kc);
+  P->res_S = B.wd((int64_t)bt.adm.size() * kc * kc);
+  P->res_rank_row = B.wi(R->ncl);
+  P->res_rank_col = B.wi(Cc->ncl);
+  // factors of the admissible leaves, packed in leaf order
+  int64_t nu = 0, nz = 0;
+  for (size_t li = 0; li < bt.adm.size(); ++li) {
+    const int k = ranks[li];
+    if (k < 1 || k > 128) throw Error(H2_ERR_INVALID_ARG, "block rank outside [1, 128]");
+    nu += R->size(bt.nodes[bt.adm[li]].t) * k;
+    nz += Cc->size(bt.nodes[bt.adm[li]].s) * k;
+  }
+  const DRef<double> inU = B.wd(nu), inZ = B.wd(nz);
+  pl.un.assign(bt.adm.size(), UNode());
+  pl.bnode.resize(bt.adm.size());
+  int64_t uo = 0, zo = 0;
+  for (size_t li = 0; li < bt.adm.size(); ++li) {
+    const auto& nd = bt.nodes[bt.adm[li]];
+    UNode& u = pl.un[li];
+    u.t = nd.t;
+    u.r = nd.s;
+    u.fin = true;
+    u.form = 1;
+    u.below = bt.adm[li];
+    u.K = ranks[li];
+    u.m = (int)R->size(nd.t);
+    u.n = (int)Cc->size(nd.s);
+    u.U = inU.off + uo;
+    u.Z = inZ.off + zo;
+    uo += (int64_t)u.m * u.K;
+    zo += (int64_t)u.n * u.K;
+    pl.bnode[li] = (int)li;
+  }
+  // nearfield: copied into the result as given
+  P->cnoff.assign(bt.inadm.size() + 1, 0);
+  int64_t noff = 0;
+  for (size_t i = 0; i < bt.inadm.size(); ++i) {
+    P->cnoff[i] = noff;
+    noff += R->size(bt.nodes[bt.inadm[i]].t) * Cc->size(bt.nodes[bt.inadm[i]].s);
+  }
+  P->cnoff[bt.inadm.size()] = noff;
+  P->cnsize = noff;
+  P->res_N = B.wd(noff);
+  P->inputs = {inU, inZ, P->res_N};
+  pl.coarsen();
+  pl.bases();
+  pl.couplings();
+  P->n_adm = bt.adm.size();
+  P->n_inadm = bt.inadm.size();
+  count_work(*P);
+  P->bytes_alg = 8.0 * (double)(nu + nz + noff) + 2.0 * (double)P->wsd * 8.0;
+  share_workspace(*P);
+  finalize(*P, eps);
+  set_eps(*P, eps);
+  const double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  const std::pair<const double*, int64_t> host_in[3] = {{U, nu}, {Z, nz}, {near, noff}};
+  for (int i = 0; i < 3; ++i)
+    if (host_in[i].second)
+      H2_HIP(hipMemcpyAsync(res(P->inputs[i], *P), host_in[i].first, host_in[i].second * sizeof(double),
+                            hipMemcpyHostToDevice, ctx->stream));
+  H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
+  double tph[8] = {0};
+  execute(ctx, *P, opt.timing, tph);
+  int ovf = 0;
+  H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  H2_HIP(hipStreamSynchronize(ctx->stream));
+  if (ovf)
+    throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "truncated block rank above coarse_rank cap"
+                                             : "basis rank above max_rank cap");
+  auto Cm = std::make_unique<Matrix>();
+  Cm->ctx = ctx;
+  Cm->hold = ctx->self.lock();
+  Cm->id = ctx->next_id++;
+  Cm->rows = R;
+  Cm->cols = Cc;
+  build_block_tree(Cm->bt, *R, *Cc, eta);
+  Cm->kc = kc;
+  Cm->w_is_v = false;
+  const int64_t n_vleaf = R->n * kc, n_vtr = (int64_t)R->ncl * kc * kc, n_wleaf = Cc->n * kc,
+                n_wtr = (int64_t)Cc->ncl * kc * kc, n_s = (int64_t)bt.adm.size() * kc * kc;
+  auto take = [&](int64_t c) { return Cm->alloc64((size_t)std::max<int64_t>(c, 1)); };
+  Cm->V.leaf = take(n_vleaf);
+  Cm->V.transfer = take(n_vtr);
+  Cm->W.leaf = take(n_wleaf);
+  Cm->W.transfer = take(n_wtr);
+  Cm->S = take(n_s);
+  Cm->N = take(noff);
+  auto cp = [&](double* d, const DRef<double>& src, int64_t count) {
+    if (count) H2_HIP(hipMemcpyAsync(d, res(src, *P), count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  };
+  cp(Cm->V.leaf, P->res_vleaf, n_vleaf);
+  cp(Cm->V.transfer, P->res_vtr, n_vtr);
+  cp(Cm->W.leaf, P->res_wleaf, n_wleaf);
+  cp(Cm->W.transfer, P->res_wtr, n_wtr);
+  cp(Cm->S, P->res_S, n_s);
+  cp(Cm->N, P->res_N, noff);
+  Cm->noff = P->cnoff;
+  Cm->nsize = noff;
+  Cm->rank_row.resize(R->ncl);
+  Cm->rank_col.resize(Cc->ncl);
+  H2_HIP(hipMemcpyAsync(Cm->rank_row.data(), res(P->res_rank_row, *P), R->ncl * sizeof(int), hipMemcpyDeviceToHost,
+                        ctx->stream));
+  H2_HIP(hipMemcpyAsync(Cm->rank_col.data(), res(P->res_rank_col, *P), Cc->ncl * sizeof(int),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  H2_HIP(hipStreamSynchronize(ctx->stream));
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int i = 0; i < 8; ++i) stats->t_phase[i] = tph[i];
+    stats->t_plan_ms = tplan;
+    stats->bytes_alg = P->bytes_alg;
+    stats->flops_alg = P->flops_alg;
+    stats->prec_used = H2_PREC_FP64;
+    stats->rank_max_row = Cm->rank_row.empty() ? 0 : *std::max_element(Cm->rank_row.begin(), Cm->rank_row.end());
+    stats->rank_max_col = Cm->rank_col.empty() ? 0 : *std::max_element(Cm->rank_col.begin(), Cm->rank_col.end());
+    stats->coarse_rank_max = P->max_coarse_K;
+    stats->n_adm = P->n_adm;
+    stats->n_inadm = P->n_inadm;
+    stats->launches = P->launches;
+    for (int i = 0; i < h2k::K_COUNT; ++i) {
+      stats->t_kernel[i] = P->t_k[i];
+      stats->launches_kernel[i] = P->launches_k[i];
+      stats->units_kernel[i] = P->units_k[i];
+      stats->flops_kernel[i] = P->flops_k[i];
+      stats->bytes_kernel[i] = P->bytes_k[i];
+    }
+  }
+  return Cm;
+}
 }  // namespace h2

@@ -30,7 +30,7 @@ EXPORTS = [
     "h2_tree_permutation", "h2_tree_info", "h2_tree_clusters", "h2_tree_destroy",
     "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
-    "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error",
+    "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error", "h2_block_tree_leaves", "h2_recompress",
 ]
 NKERNEL = 13
 
@@ -85,6 +85,9 @@ _sig = {
     "h2_kernel_name": (C.c_char_p, [C.c_int]),
     "h2_matvec": (C.c_int, [_vp, C.c_int, C.c_int64, _dp, _dp]),
     "h2_product_error": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp, _dp]),
+    "h2_block_tree_leaves": (C.c_int, [_vp, _vp, C.c_double, _lp, _lp, _ip]),
+    "h2_recompress": (C.c_int, [_vp, _vp, _vp, C.c_double, _ip, _dp, _dp, _dp, C.c_double, C.POINTER(MulOptions),
+                                C.POINTER(_vp), C.POINTER(MulStats)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -265,6 +268,36 @@ def product_error(X: Matrix, Y: Matrix, Cm: Matrix | None, z0, iters: int = 10):
     _check(_lib.h2_product_error(X.h, Y.h, None if Cm is None else Cm.h, int(iters), _dptr(z), C.byref(e),
                                  C.byref(nxy)))
     return e.value, nxy.value
+
+
+def block_tree_leaves(rows: Tree, cols: Tree, eta: float):
+    """Leaves of the block tree of (rows, cols, eta): (pairs [n, 2] of cluster
+    indices, admissible leaves first; number of admissible leaves)."""
+    na, ni = C.c_int64(), C.c_int64()
+    _check(_lib.h2_block_tree_leaves(rows.h, cols.h, float(eta), C.byref(na), C.byref(ni), None))
+    p = np.empty(2 * (na.value + ni.value), dtype=np.int32)
+    _check(_lib.h2_block_tree_leaves(rows.h, cols.h, float(eta), C.byref(na), C.byref(ni), p.ctypes.data_as(_ip)))
+    return p.reshape(-1, 2), na.value
+
+
+def recompress(ctx: Context, rows: Tree, cols: Tree, eta: float, factors, near, eps: float,
+               options: MulOptions | None = None):
+    """H -> H2 recompression.  factors: one (U_i, Z_i) per admissible leaf in the
+    order of block_tree_leaves (U_i |t| x k_i, Z_i |s| x k_i, rows in tree
+    order); near: one dense |t| x |s| block per inadmissible leaf.  Returns
+    (C, stats dict)."""
+    ranks = np.array([np.shape(u)[1] for u, _ in factors], dtype=np.int32)
+    cat = lambda blocks: (np.concatenate([np.ascontiguousarray(b, dtype=np.float64).ravel() for b in blocks])
+                          if len(blocks) else np.zeros(1))
+    U = cat([u for u, _ in factors])
+    Z = cat([z for _, z in factors])
+    N = cat(list(near))
+    st = MulStats()
+    h = _vp()
+    opt = options if options is not None else default_options()
+    _check(_lib.h2_recompress(ctx.h, rows.h, cols.h, float(eta), ranks.ctypes.data_as(_ip), _dptr(U), _dptr(Z),
+                              _dptr(N), float(eps), C.byref(opt), C.byref(h), C.byref(st)))
+    return Matrix(h, (ctx, rows, cols)), st.as_dict()
 
 
 def kernel_names():
