@@ -43,6 +43,7 @@ typedef enum {
 typedef struct h2_context_s* h2_context;
 typedef struct h2_tree_s* h2_tree;
 typedef struct h2_matrix_s* h2_matrix;
+typedef struct h2_job_s* h2_job;
 
 /* Context on HIP device `device` with its own stream. */
 h2_status h2_context_create(int device, h2_context* out);
@@ -168,6 +169,30 @@ h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld);
  * the admissible leaves, then the inadmissible ones, in the order of
  * h2_matrix_blocks).  out: |t| x |s| row-major in tree order. */
 h2_status h2_block_dense(h2_matrix M, int64_t b, double* out);
+
+/* Asynchronous products (batched and served products: many independent
+ * h2_mul calls whose device work overlaps). A context has `nlanes` lanes
+ * (1..8, default 4 at the first submit); a lane is a stream of its own plus
+ * two for the size classes of its QR/SVD steps. h2_mul_submit plans the
+ * product if its plan is not cached (host, synchronous), enqueues it and the
+ * copies of its result on a lane and returns: on the plan's lane while
+ * earlier jobs of that plan (same operand pair and precision) are in flight,
+ * since a plan's workspace admits one product at a time, else on the least
+ * loaded lane. At most 64 jobs may be in flight per lane (TOO_LARGE).
+ * X and Y must stay alive until the job is waited for or destroyed.
+ * h2_job_poll sets *done = 1 once the job's device work has finished.
+ * h2_job_wait blocks until then and returns the result and stats, as h2_mul
+ * would (per-kernel timing is not recorded on this path); a rank-cap overflow
+ * is resolved by the synchronous h2_mul path. Waiting twice is INVALID_ARG.
+ * h2_job_destroy releases a job (waiting for its device work first). The
+ * result of a job is the same, bit for bit, as that of h2_mul with the same
+ * arguments. Not thread-safe: one host thread per context. */
+h2_status h2_context_set_lanes(h2_context ctx, int nlanes);
+h2_status h2_mul_submit(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opts,
+                        h2_job* job);
+h2_status h2_job_poll(h2_job job, int* done);
+h2_status h2_job_wait(h2_job job, h2_matrix* C, h2_mul_stats* stats);
+void h2_job_destroy(h2_job job);
 
 /* Leaves of the block tree of (rows, cols) with admissibility parameter eta
  * (the condition max(diam) <= 2 eta dist of Section 2, the tree of every

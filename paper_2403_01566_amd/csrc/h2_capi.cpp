@@ -18,6 +18,10 @@ struct h2_tree_s {
 struct h2_matrix_s {
   std::unique_ptr<h2::Matrix> m;
 };
+struct h2_job_s {
+  h2::Job* j = nullptr;
+  h2_context ctx = nullptr;
+};
 
 namespace {
 thread_local std::string g_err;
@@ -187,6 +191,66 @@ h2_status h2_mul(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_
     }
     *C = m;
   });
+}
+
+h2_status h2_context_set_lanes(h2_context ctx, int nlanes) {
+  return guard([&] {
+    require(ctx != nullptr, "null argument");
+    require(nlanes >= 1 && nlanes <= 8, "nlanes must be in [1, 8]");
+    set_device(ctx);
+    for (auto& l : ctx->c.lanes) require(l->inflight == 0, "jobs still in flight");
+    ctx->c.set_lanes(nlanes);
+  });
+}
+
+h2_status h2_mul_submit(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opt,
+                        h2_job* job) {
+  if (job) *job = nullptr;
+  return guard([&] {
+    require(ctx && X && Y && job, "null argument");
+    require(X->m->ctx == &ctx->c && Y->m->ctx == &ctx->c, "matrices belong to another context");
+    h2_mul_options o;
+    h2_mul_default_options(&o);
+    if (opt) o = *opt;
+    require(o.precision == H2_PREC_FP64 || o.precision == H2_PREC_FP32_BULK, "unknown precision");
+    set_device(ctx);
+    h2::Job* j = h2::submit(&ctx->c, X->m.get(), Y->m.get(), eps, o);
+    auto* h = new h2_job_s;
+    h->j = j;
+    h->ctx = ctx;
+    *job = h;
+  });
+}
+
+h2_status h2_job_poll(h2_job job, int* done) {
+  return guard([&] {
+    require(job && job->j && done, "null argument");
+    set_device(job->ctx);
+    *done = h2::poll(*job->j) ? 1 : 0;
+  });
+}
+
+h2_status h2_job_wait(h2_job job, h2_matrix* C, h2_mul_stats* stats) {
+  if (C) *C = nullptr;
+  return guard([&] {
+    require(job && job->j && C, "null argument");
+    set_device(job->ctx);
+    auto* m = new h2_matrix_s;
+    try {
+      m->m = h2::wait(*job->j, stats);
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *C = m;
+  });
+}
+
+void h2_job_destroy(h2_job job) {
+  if (!job) return;
+  (void)hipSetDevice(job->ctx->c.device);
+  h2::destroy_job(job->j);
+  delete job;
 }
 
 h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld) {

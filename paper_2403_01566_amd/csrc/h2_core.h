@@ -127,6 +127,25 @@ struct Matrix {
 struct Plan;
 struct MvPlan;
 
+// Where a plan executes: a stream, two more streams (default priority) for
+// the size classes of one QR or SVD step, fork and join events and the
+// device flag the rank-capped kernels set on an overflow.
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipStream_t aux[2] = {nullptr, nullptr};
+  hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+  int* overflow = nullptr;
+};
+// An extra lane of the context (lane 0 is the context's own stream): its
+// streams and events, and overflow flags used round-robin by its jobs.
+struct LaneRes {
+  Lane l;
+  int* flags = nullptr;         // kFlagSlots device ints
+  std::vector<int> free_slots;  // flags not held by a job that is still to be waited for
+  int inflight = 0;
+};
+constexpr int kFlagSlots = 64;
+
 // Device, stream and plan cache.  Shared by the context handle and every
 // matrix created in it, so handles may be released in any order.
 struct Context {
@@ -143,6 +162,21 @@ struct Context {
   std::map<std::pair<uint64_t, uint64_t>, double> fp32_fail_eps;
   // matrix-vector plans: (matrix id, transposed, number of vectors)
   std::map<std::tuple<uint64_t, int, int64_t>, std::shared_ptr<MvPlan>> mvplans;
+  // lanes for asynchronous products: lanes[0] shares the context's stream
+  // (its flags are separate from `overflow`); created by set_lanes
+  std::vector<std::unique_ptr<LaneRes>> lanes;
+  Lane lane0() const {
+    Lane l;
+    l.stream = stream;
+    l.aux[0] = aux[0];
+    l.aux[1] = aux[1];
+    l.fork = fork;
+    l.join[0] = join[0];
+    l.join[1] = join[1];
+    l.overflow = overflow;
+    return l;
+  }
+  void set_lanes(int n);
   uint64_t next_id = 1;
   std::weak_ptr<Context> self;
   ~Context();
@@ -154,6 +188,15 @@ std::unique_ptr<Matrix> build_interpolated(Context* ctx, std::shared_ptr<Tree> r
 
 std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
                                  h2_mul_stats* stats);
+
+// Asynchronous products: submit enqueues on a lane and returns; wait
+// completes (a rank overflow falls back to multiply); destroy_job waits for
+// the device work of a job that is dropped without wait.
+struct Job;
+Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt);  // owned by the caller
+bool poll(Job& J);
+std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats);
+void destroy_job(Job* J);
 
 // H -> H2 recompression of an H-matrix on the block tree of (R, C, eta):
 // factors U_b (|t| x k_b) and Z_b (|s| x k_b) of the admissible leaves packed

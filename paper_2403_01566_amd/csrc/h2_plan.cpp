@@ -168,6 +168,10 @@ struct Step {
 
 struct Plan {
   std::deque<Step> steps;  // deque: references to earlier steps stay valid
+  // asynchronous use: jobs submitted and not yet waited for, and their lane
+  // (a plan's workspace admits one product at a time, so they share a lane)
+  int inflight = 0;
+  int lane = -1;
   int64_t wsd = 0, wsf = 0, wsi = 0;
   std::vector<int64_t> base_d, base_f;  // allocation starts in the planned (unshared) layout
   int64_t wsd_planned = 0, wsf_planned = 0;
@@ -2182,8 +2186,9 @@ static double qr_flops(double m, double w) {
 
 // timing: 0 none, 1 per-phase events, 2 also events around every kernel launch,
 // 3 also the algorithmic work from the sizes the QR / SVD kernels report.
-static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
-  hipStream_t s = ctx->stream;
+static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_phase) {
+  (void)ctx;
+  hipStream_t s = L.stream;
   char* base = (char*)P.desc.p;
   std::vector<hipEvent_t> ev;
   int cur_phase = -1;
@@ -2233,13 +2238,13 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
   // joined back into the main stream.
   auto classes = [&](int ncls, auto&& launch_class) {
     if (ncls > 1) {
-      H2_HIP(hipEventRecord(ctx->fork, s));
-      for (int c = 1; c < ncls; ++c) H2_HIP(hipStreamWaitEvent(ctx->aux[c - 1], ctx->fork, 0));
+      H2_HIP(hipEventRecord(L.fork, s));
+      for (int c = 1; c < ncls; ++c) H2_HIP(hipStreamWaitEvent(L.aux[c - 1], L.fork, 0));
     }
-    for (int c = 0; c < ncls; ++c) launch_class(c, c == 0 ? s : ctx->aux[c - 1]);
+    for (int c = 0; c < ncls; ++c) launch_class(c, c == 0 ? s : L.aux[c - 1]);
     for (int c = 1; c < ncls; ++c) {
-      H2_HIP(hipEventRecord(ctx->join[c - 1], ctx->aux[c - 1]));
-      H2_HIP(hipStreamWaitEvent(s, ctx->join[c - 1], 0));
+      H2_HIP(hipEventRecord(L.join[c - 1], L.aux[c - 1]));
+      H2_HIP(hipStreamWaitEvent(s, L.join[c - 1], 0));
     }
   };
   size_t si = 0;
@@ -2276,7 +2281,7 @@ static void execute(Context* ctx, Plan& P, int timing, double* t_phase) {
         if (st.ndesc > 0)
           classes(h2k::size_classes(st.wmax), [&](int c, hipStream_t on) {
             timed_on(on, h2k::K_SVD32 + c, si, [&] {
-              h2k::launch_svd_class((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, c, ctx->overflow, on);
+              h2k::launch_svd_class((const h2k::SvdTask*)(base + st.desc_off), st.ndesc, c, L.overflow, on);
             });
           });
         break;
@@ -2460,6 +2465,14 @@ static void count_work(Plan& P) {
   P.flops_alg = fl;
 }
 
+// Waits for the device work of asynchronous jobs still running on a plan, so
+// that the plan's descriptors and workspace may be changed or reused.
+static void quiesce(Context* ctx, Plan& P) {
+  if (P.inflight <= 0 || P.lane < 0) return;
+  const hipStream_t s = P.lane == 0 ? ctx->stream : ctx->lanes[P.lane]->l.stream;
+  H2_HIP(hipStreamSynchronize(s));
+}
+
 static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
                                        const h2_mul_options& opt, double eps) {
   auto P = std::make_shared<Plan>();
@@ -2560,11 +2573,12 @@ std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps,
     ctx->plans[key] = P;
     built = true;
   }
+  quiesce(ctx, *P);
   set_eps(*P, eps);
   double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
   double tph[8] = {0};
-  execute(ctx, *P, opt.timing, tph);
+  execute(ctx, ctx->lane0(), *P, opt.timing, tph);
   // while the device works: the result's block tree and one allocation for
   // its arrays (filled by device copies once the product is done)
   auto Cm = std::make_unique<Matrix>();
@@ -2804,7 +2818,7 @@ void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y) {
   std::vector<double> xt((size_t)Ti.n * nrhs), yt((size_t)To.n * nrhs);
   for (int64_t i = 0; i < Ti.n; ++i) std::memcpy(&xt[i * nrhs], x + Ti.perm[i] * nrhs, nrhs * sizeof(double));
   H2_HIP(hipMemcpyAsync(mv->in(), xt.data(), xt.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  execute(ctx, *mv->P, 0, nullptr);
+  execute(ctx, ctx->lane0(), *mv->P, 0, nullptr);
   H2_HIP(hipMemcpyAsync(yt.data(), mv->out(), yt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   H2_HIP(hipStreamSynchronize(s));
   for (int64_t i = 0; i < To.n; ++i) std::memcpy(y + To.perm[i] * nrhs, &yt[i * nrhs], nrhs * sizeof(double));
@@ -2859,25 +2873,25 @@ void product_error(Matrix* X, Matrix* Y, Matrix* C, int iters, const double* z0,
     for (int it = 0; it < iters; ++it) {
       // w = E z
       copy(pY->in(), z.as<double>(), nc);
-      execute(ctx, *pY->P, 0, nullptr);
+      execute(ctx, ctx->lane0(), *pY->P, 0, nullptr);
       copy(pX->in(), pY->out(), nm);
-      execute(ctx, *pX->P, 0, nullptr);
+      execute(ctx, ctx->lane0(), *pX->P, 0, nullptr);
       double* w = pX->out();
       if (withC) {
         copy(pC->in(), z.as<double>(), nc);
-        execute(ctx, *pC->P, 0, nullptr);
+        execute(ctx, ctx->lane0(), *pC->P, 0, nullptr);
         h2k::launch_axpby(pC->out(), w, nr, -1.0, 1.0, s);
       }
       sig = std::sqrt(dot(w, w, nr));
       // z = E^* w / ||E^* w||
       copy(pXt->in(), w, nr);
-      execute(ctx, *pXt->P, 0, nullptr);
+      execute(ctx, ctx->lane0(), *pXt->P, 0, nullptr);
       copy(pYt->in(), pXt->out(), nm);
-      execute(ctx, *pYt->P, 0, nullptr);
+      execute(ctx, ctx->lane0(), *pYt->P, 0, nullptr);
       double* zt = pYt->out();
       if (withC) {
         copy(pCt->in(), w, nr);
-        execute(ctx, *pCt->P, 0, nullptr);
+        execute(ctx, ctx->lane0(), *pCt->P, 0, nullptr);
         h2k::launch_axpby(pCt->out(), zt, nc, -1.0, 1.0, s);
       }
       const double nz = std::sqrt(dot(zt, zt, nc));
@@ -2992,7 +3006,7 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
                             hipMemcpyHostToDevice, ctx->stream));
   H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
   double tph[8] = {0};
-  execute(ctx, *P, opt.timing, tph);
+  execute(ctx, ctx->lane0(), *P, opt.timing, tph);
   int ovf = 0;
   H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   H2_HIP(hipStreamSynchronize(ctx->stream));
@@ -3057,5 +3071,213 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
     }
   }
   return Cm;
+}
+}  // namespace h2
+
+// ------------------------------------------------------------------ asynchronous products
+// submit() plans (or reuses the cached plan), enqueues the product and the
+// copies of its result arrays on a lane and returns; wait() completes it.
+// Products on different lanes overlap on the device; jobs of one plan share
+// its lane and run in order.
+namespace h2 {
+struct Job {
+  Context* ctx = nullptr;
+  Matrix* X = nullptr;
+  Matrix* Y = nullptr;
+  double eps = 0;
+  h2_mul_options opt{};
+  std::shared_ptr<Plan> P;
+  bool f32 = false, built = false;
+  int kc = 0, lane = 0;
+  int slot = -1;        // this job's overflow flag: a slot of the lane's flags
+  int* flag = nullptr;
+  double tplan = 0;
+  hipEvent_t done = nullptr;
+  std::unique_ptr<Matrix> C;
+  int* dev_ranks = nullptr;  // row then column ranks, copied out of the plan
+  bool finished = false;
+  // gives the flag slot back and drops the in-flight counts (once)
+  void release() {
+    if (finished) return;
+    finished = true;
+    if (ctx && slot >= 0) {
+      if (P) --P->inflight;
+      LaneRes& LR = *ctx->lanes[lane];
+      --LR.inflight;
+      LR.free_slots.push_back(slot);
+    }
+  }
+  ~Job() {
+    release();
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
+Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt) {
+  if (X->cols.get() != Y->rows.get()) throw Error(H2_ERR_INCOMPATIBLE, "X's column tree is not Y's row tree");
+  if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
+  if (X->kc > 64 || Y->kc > 64) throw Error(H2_ERR_TOO_LARGE, "operand rank above 64");
+  if (ctx->lanes.empty()) ctx->set_lanes(4);
+  auto J = std::make_unique<Job>();
+  J->ctx = ctx;
+  J->X = X;
+  J->Y = Y;
+  J->eps = eps;
+  J->opt = opt;
+  J->opt.timing = 0;  // no per-launch events on the asynchronous path
+  bool f32 = opt.precision == H2_PREC_FP32_BULK && eps >= 1e-5;
+  if (f32) {
+    auto f = ctx->fp32_fail_eps.find({X->id, Y->id});
+    if (f != ctx->fp32_fail_eps.end() && eps <= f->second) f32 = false;
+  }
+  const int kmax = std::max(X->kc, Y->kc);
+  const int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
+  const int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
+  if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
+  auto t0 = std::chrono::steady_clock::now();
+  const auto key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0));
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end() && it->second->kc == kc && it->second->kappa_cap == kcap &&
+      it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta)) {
+    J->P = it->second;
+  } else {
+    if (f32) {
+      X->ensure_fp32(ctx->stream);
+      Y->ensure_fp32(ctx->stream);
+      H2_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    J->P = make_plan(ctx, X, Y, f32, kc, kcap, opt, eps);
+    ctx->plans[key] = J->P;
+    J->built = true;
+  }
+  Plan& P = *J->P;
+  // lane: the plan's own while it has jobs in flight, else the least loaded
+  int lane = 0;
+  if (P.inflight > 0 && P.lane >= 0) {
+    lane = P.lane;
+  } else {
+    for (int i = 1; i < (int)ctx->lanes.size(); ++i)
+      if (ctx->lanes[i]->inflight < ctx->lanes[lane]->inflight) lane = i;
+  }
+  LaneRes& LR = *ctx->lanes[lane];
+  if (LR.free_slots.empty()) throw Error(H2_ERR_TOO_LARGE, "more than 64 jobs in flight on one lane");
+  if (P.eps_set != eps) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
+  set_eps(P, eps);
+  J->f32 = f32;
+  J->kc = kc;
+  J->lane = lane;
+  J->tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  J->slot = LR.free_slots.back();
+  LR.free_slots.pop_back();
+  J->flag = LR.flags + J->slot;
+  ++P.inflight;  // from here on release() undoes these
+  P.lane = lane;
+  ++LR.inflight;
+  Lane L = LR.l;
+  L.overflow = J->flag;
+  const hipStream_t s = L.stream;
+  H2_HIP(hipMemsetAsync(J->flag, 0, sizeof(int), s));
+  double tph[8] = {0};
+  execute(ctx, L, P, 0, tph);
+  // result arrays: one allocation, filled by copies queued behind the product
+  auto Cm = std::make_unique<Matrix>();
+  Cm->ctx = ctx;
+  Cm->hold = ctx->self.lock();
+  Cm->id = ctx->next_id++;
+  Cm->rows = X->rows;
+  Cm->cols = Y->cols;
+  build_block_tree(Cm->bt, *X->rows, *Y->cols, X->bt.eta);
+  Cm->kc = kc;
+  const int64_t n_vleaf = X->rows->n * kc, n_vtr = (int64_t)X->rows->ncl * kc * kc, n_wleaf = Y->cols->n * kc,
+                n_wtr = (int64_t)Y->cols->ncl * kc * kc, n_s = (int64_t)P.cbt.adm.size() * kc * kc,
+                n_n = P.cnsize, n_r = X->rows->ncl + Y->cols->ncl;
+  auto pad = [](int64_t c) { return (std::max<int64_t>(c, 1) + 31) & ~int64_t(31); };
+  Cm->bufs.emplace_back(new DevBuf);
+  Cm->bufs.back()->alloc((size_t)(pad(n_vleaf) + pad(n_vtr) + pad(n_wleaf) + pad(n_wtr) + pad(n_s) + pad(n_n) +
+                                  pad(n_r)) *
+                         sizeof(double));
+  double* carve = Cm->bufs.back()->as<double>();
+  auto take = [&](int64_t c) {
+    double* d = carve;
+    carve += pad(c);
+    return d;
+  };
+  Cm->V.leaf = take(n_vleaf);
+  Cm->V.transfer = take(n_vtr);
+  Cm->W.leaf = take(n_wleaf);
+  Cm->W.transfer = take(n_wtr);
+  Cm->S = take(n_s);
+  Cm->N = take(n_n);
+  J->dev_ranks = (int*)take(n_r);
+  auto cp = [&](void* d, const void* src, int64_t bytes) {
+    if (bytes) H2_HIP(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, s));
+  };
+  cp(Cm->V.leaf, res(P.res_vleaf, P), n_vleaf * 8);
+  cp(Cm->V.transfer, res(P.res_vtr, P), n_vtr * 8);
+  cp(Cm->W.leaf, res(P.res_wleaf, P), n_wleaf * 8);
+  cp(Cm->W.transfer, res(P.res_wtr, P), n_wtr * 8);
+  cp(Cm->S, res(P.res_S, P), n_s * 8);
+  cp(Cm->N, res(P.res_N, P), n_n * 8);
+  cp(J->dev_ranks, res(P.res_rank_row, P), X->rows->ncl * sizeof(int));
+  cp(J->dev_ranks + X->rows->ncl, res(P.res_rank_col, P), Y->cols->ncl * sizeof(int));
+  Cm->noff = P.cnoff;
+  Cm->nsize = P.cnsize;
+  J->C = std::move(Cm);
+  H2_HIP(hipEventCreateWithFlags(&J->done, hipEventDisableTiming));
+  H2_HIP(hipEventRecord(J->done, s));
+  return J.release();
+}
+
+bool poll(Job& J) {
+  if (J.finished) return true;
+  const hipError_t e = hipEventQuery(J.done);
+  if (e == hipSuccess) return true;
+  if (e == hipErrorNotReady) return false;
+  H2_HIP(e);
+  return false;
+}
+
+std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
+  if (J.finished) throw Error(H2_ERR_INVALID_ARG, "job already waited for");
+  Context* ctx = J.ctx;
+  H2_HIP(hipEventSynchronize(J.done));
+  int ovf = 0;
+  H2_HIP(hipMemcpy(&ovf, J.flag, sizeof(int), hipMemcpyDeviceToHost));
+  J.release();
+  if (ovf) {
+    // a rank cap was exceeded: the synchronous path decides (FP64 bulk, the
+    // largest result cap) exactly as for h2_mul
+    J.C.reset();
+    J.P.reset();
+    h2_mul_options o = J.opt;
+    return multiply(ctx, J.X, J.Y, J.eps, o, stats);
+  }
+  Matrix& C = *J.C;
+  const int nr = J.X->rows->ncl, nc = J.Y->cols->ncl;
+  std::vector<int> rk(nr + nc);
+  H2_HIP(hipMemcpy(rk.data(), J.dev_ranks, rk.size() * sizeof(int), hipMemcpyDeviceToHost));
+  C.rank_row.assign(rk.begin(), rk.begin() + nr);
+  C.rank_col.assign(rk.begin() + nr, rk.end());
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    const Plan& P = *J.P;
+    stats->t_plan_ms = J.built ? J.tplan : 0.0;
+    stats->bytes_alg = P.bytes_alg;
+    stats->flops_alg = P.flops_alg;
+    stats->prec_used = J.f32 ? H2_PREC_FP32_BULK : H2_PREC_FP64;
+    stats->rank_max_row = C.rank_row.empty() ? 0 : *std::max_element(C.rank_row.begin(), C.rank_row.end());
+    stats->rank_max_col = C.rank_col.empty() ? 0 : *std::max_element(C.rank_col.begin(), C.rank_col.end());
+    stats->coarse_rank_max = P.max_coarse_K;
+    stats->n_adm = P.n_adm;
+    stats->n_inadm = P.n_inadm;
+  }
+  return std::move(J.C);
+}
+
+void destroy_job(Job* J) {
+  if (!J) return;
+  if (!J->finished && J->done) (void)hipEventSynchronize(J->done);  // buffers in use until then
+  J->release();
+  delete J;
 }
 }  // namespace h2

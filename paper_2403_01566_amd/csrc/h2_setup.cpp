@@ -168,11 +168,49 @@ Matrix::~Matrix() {
   bufs.clear();
 }
 
+void Context::set_lanes(int n) {
+  H2_HIP(hipSetDevice(device));
+  for (auto& l : lanes)  // no job may still run on a lane that goes away
+    for (hipStream_t s : {l->l.stream, l->l.aux[0], l->l.aux[1]})
+      if (s) H2_HIP(hipStreamSynchronize(s));
+  while ((int)lanes.size() > n) {
+    auto& r = lanes.back();
+    if (lanes.size() > 1) {
+      for (auto& a : r->l.aux) (void)hipStreamDestroy(a);
+      (void)hipStreamDestroy(r->l.stream);
+      (void)hipEventDestroy(r->l.fork);
+      for (auto& e : r->l.join) (void)hipEventDestroy(e);
+    }
+    (void)hipFree(r->flags);
+    lanes.pop_back();
+  }
+  while ((int)lanes.size() < n) {
+    auto r = std::make_unique<LaneRes>();
+    if (lanes.empty()) {
+      r->l = lane0();  // the context's own streams and events
+    } else {
+      H2_HIP(hipStreamCreateWithFlags(&r->l.stream, hipStreamNonBlocking));
+      for (auto& a : r->l.aux) H2_HIP(hipStreamCreateWithFlags(&a, hipStreamNonBlocking));
+      H2_HIP(hipEventCreateWithFlags(&r->l.fork, hipEventDisableTiming));
+      for (auto& e : r->l.join) H2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    H2_HIP(hipMalloc((void**)&r->flags, kFlagSlots * sizeof(int)));
+    for (int i = kFlagSlots - 1; i >= 0; --i) r->free_slots.push_back(i);
+    lanes.push_back(std::move(r));
+  }
+}
+
 Context::~Context() {
   (void)hipSetDevice(device);
   if (stream) (void)hipStreamSynchronize(stream);
+  for (auto& l : lanes)
+    if (l->l.stream) (void)hipStreamSynchronize(l->l.stream);
   plans.clear();
   mvplans.clear();
+  try {
+    set_lanes(0);
+  } catch (...) {
+  }
   if (overflow) (void)hipFree(overflow);
   for (auto& a : aux)
     if (a) {

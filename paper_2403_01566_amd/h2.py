@@ -31,6 +31,7 @@ EXPORTS = [
     "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
     "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error", "h2_block_tree_leaves", "h2_recompress",
+    "h2_context_set_lanes", "h2_mul_submit", "h2_job_poll", "h2_job_wait", "h2_job_destroy",
 ]
 NKERNEL = 13
 
@@ -86,6 +87,11 @@ _sig = {
     "h2_matvec": (C.c_int, [_vp, C.c_int, C.c_int64, _dp, _dp]),
     "h2_product_error": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp, _dp]),
     "h2_block_tree_leaves": (C.c_int, [_vp, _vp, C.c_double, _lp, _lp, _ip]),
+    "h2_context_set_lanes": (C.c_int, [_vp, C.c_int]),
+    "h2_mul_submit": (C.c_int, [_vp, _vp, _vp, C.c_double, C.POINTER(MulOptions), C.POINTER(_vp)]),
+    "h2_job_poll": (C.c_int, [_vp, _ip]),
+    "h2_job_wait": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(MulStats)]),
+    "h2_job_destroy": (None, [_vp]),
     "h2_recompress": (C.c_int, [_vp, _vp, _vp, C.c_double, _ip, _dp, _dp, _dp, C.c_double, C.POINTER(MulOptions),
                                 C.POINTER(_vp), C.POINTER(MulStats)]),
 }
@@ -268,6 +274,60 @@ def product_error(X: Matrix, Y: Matrix, Cm: Matrix | None, z0, iters: int = 10):
     _check(_lib.h2_product_error(X.h, Y.h, None if Cm is None else Cm.h, int(iters), _dptr(z), C.byref(e),
                                  C.byref(nxy)))
     return e.value, nxy.value
+
+
+class Job:
+    """An asynchronous product (h2_mul_submit): poll() / wait() -> (C, stats)."""
+
+    def __init__(self, h, keep):
+        self.h, self._keep = h, keep
+
+    def poll(self):
+        d = C.c_int()
+        _check(_lib.h2_job_poll(self.h, C.byref(d)))
+        return bool(d.value)
+
+    def wait(self):
+        st = MulStats()
+        h = _vp()
+        _check(_lib.h2_job_wait(self.h, C.byref(h), C.byref(st)))
+        X, Y = self._keep[1], self._keep[2]
+        return Matrix(h, (self._keep[0],) + X._keep[1:2] + Y._keep[2:3]), st.as_dict()
+
+    def close(self):
+        if self.h:
+            _lib.h2_job_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_lanes(ctx: Context, nlanes: int):
+    _check(_lib.h2_context_set_lanes(ctx.h, int(nlanes)))
+
+
+def submit(ctx: Context, X: Matrix, Y: Matrix, eps: float, options: MulOptions | None = None) -> Job:
+    """Enqueue C = X Y on one of the context's lanes and return at once."""
+    h = _vp()
+    opt = options if options is not None else default_options()
+    _check(_lib.h2_mul_submit(ctx.h, X.h, Y.h, float(eps), C.byref(opt), C.byref(h)))
+    return Job(h, (ctx, X, Y))
+
+
+def mul_batch(ctx: Context, pairs, eps, options: MulOptions | None = None):
+    """Many independent products at once (their device work overlaps on the
+    lanes): pairs = [(X, Y), ...], eps a number or one per pair.  Returns
+    [(C, stats), ...] in order."""
+    epss = list(eps) if hasattr(eps, "__len__") else [eps] * len(pairs)
+    jobs = [submit(ctx, X, Y, e, options) for (X, Y), e in zip(pairs, epss)]
+    out = [j.wait() for j in jobs]
+    for j in jobs:
+        j.close()
+    return out
 
 
 def block_tree_leaves(rows: Tree, cols: Tree, eta: float):

@@ -1,0 +1,126 @@
+"""Asynchronous products (batched and served products): each result is the
+same, bit for bit, alone (h2_mul) and in a mix of overlapping products on the
+context's lanes; the mix holds different operands, precisions and tolerances,
+and one operand pair at several tolerances in flight at once."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2403_01566_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h2():
+    from paper_2403_01566_amd import h2 as mod
+    return mod
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _operands(h2, ctx):
+    ops = []
+    for n, p, seed in [(900, 3, 11), (1500, 4, 12), (2500, 5, 13), (700, 6, 14)]:
+        T = h2.Tree(ctx, W.uniform2d(n, seed), 32 if p <= 4 else 64)
+        ops.append((T, h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, p, 0.5, h2.DIAG_ZERO)))
+    P, nrm = W.icosphere(3)
+    T = h2.Tree(ctx, P, 64)
+    A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_LAPLACE_SLP, 3, 1.0, h2.DIAG_ROW_NEARFIELD_MEAN, nrm)
+    B = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_LAPLACE_DLP, 3, 1.0, h2.DIAG_ZERO, nrm)
+    return ops, (T, A, B)
+
+
+def _same(h2, C1, C2, n):
+    return np.array_equal(C1.to_dense(n, n), C2.to_dense(n, n))
+
+
+def test_batch_equals_products_alone(h2):
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, 4)
+    ops, (Ts, A, B) = _operands(h2, ctx)
+    reqs = [(X, X, eps, prec, T.n) for (T, X) in ops for eps, prec in [(1e-4, 0), (1e-6, 0)]]
+    reqs += [(A, B, 1e-4, 1, Ts.n), (A, A, 1e-6, 0, Ts.n), (ops[0][1], ops[0][1], 1e-5, 1, ops[0][0].n)]
+    _say(f"[batch] {len(reqs)} products alone")
+    alone = [h2.mul(ctx, X, Y, eps, h2.default_options(precision=prec)) for X, Y, eps, prec, n in reqs]
+    _say("[batch] the same products submitted together")
+    jobs = [h2.submit(ctx, X, Y, eps, h2.default_options(precision=prec)) for X, Y, eps, prec, n in reqs]
+    got = [j.wait() for j in jobs]
+    for (X, Y, eps, prec, n), (Ca, sa), (Cb, sb) in zip(reqs, alone, got):
+        assert sb["prec_used"] == sa["prec_used"]
+        assert sb["rank_max_row"] == sa["rank_max_row"] and sb["rank_max_col"] == sa["rank_max_col"]
+        assert _same(h2, Ca, Cb, n), (n, eps, prec)
+    # in reverse order, all in flight before the first wait
+    jobs = [h2.submit(ctx, X, Y, eps, h2.default_options(precision=prec)) for X, Y, eps, prec, n in reqs[::-1]]
+    for (X, Y, eps, prec, n), (Ca, _), j in zip(reqs[::-1], alone[::-1], jobs):
+        Cb, _ = j.wait()
+        assert _same(h2, Ca, Cb, n)
+
+
+def test_one_pair_at_several_tolerances_in_flight(h2):
+    """Jobs of one plan share its lane; a new eps waits for the earlier jobs."""
+    ctx = h2.Context(0)
+    T = h2.Tree(ctx, W.grid2d(32), 32)
+    A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, 3, 0.5)
+    epss = [1e-3, 1e-4, 1e-4, 1e-6, 1e-3, 1e-8]
+    alone = [h2.mul(ctx, A, A, e)[0] for e in epss]
+    jobs = [h2.submit(ctx, A, A, e) for e in epss]
+    for Ca, j in zip(alone, jobs):
+        Cb, _ = j.wait()
+        assert _same(h2, Ca, Cb, T.n)
+
+
+def test_batched_result_meets_the_bound(h2):
+    ctx = h2.Context(0)
+    P = W.uniform2d(900, 11)
+    T = h2.Tree(ctx, P, 24)
+    A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, 4, 0.5)
+    out = h2.mul_batch(ctx, [(A, A)] * 3, [1e-4, 1e-5, 1e-6])
+    To = O.ClusterTree(P, 24)
+    Ao = O.build_interpolated(To, O.KERNEL_NEG_LOG, 4, 0.5)
+    D = Ao.to_dense()
+    Ex = D @ D
+    perm = T.permutation()
+    b, e, _, _ = T.clusters()
+    for (C, st), eps in zip(out, [1e-4, 1e-5, 1e-6]):
+        Cd = C.to_dense(T.n, T.n)
+        blocks, nadm = C.blocks()
+        worst = 0.0
+        for (t, r) in blocks[:nadm]:
+            I, J = perm[b[t]:e[t]], perm[b[r]:e[r]]
+            ex = Ex[np.ix_(I, J)]
+            nn = np.linalg.norm(ex, 2)
+            if nn > 0:
+                worst = max(worst, np.linalg.norm(ex - Cd[np.ix_(I, J)], 2) / nn)
+        _say(f"[batch] eps {eps}: worst block error {worst:.3e}")
+        assert worst <= eps
+
+
+def test_job_poll_wait_and_errors(h2):
+    ctx = h2.Context(0)
+    T = h2.Tree(ctx, W.grid2d(16), 32)
+    A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, 3, 0.5)
+    j = h2.submit(ctx, A, A, 1e-4)
+    with pytest.raises(h2.H2Error) as ei:
+        h2.set_lanes(ctx, 2)  # a job is in flight
+    assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    C, st = j.wait()
+    assert j.poll()
+    with pytest.raises(h2.H2Error) as ei:
+        j.wait()
+    assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    j.close()
+    j2 = h2.submit(ctx, A, A, 1e-4)
+    j2.close()  # dropped without wait: waits for its device work
+    h2.set_lanes(ctx, 2)
+    for bad in (0.0, 1.0):
+        with pytest.raises(h2.H2Error) as ei:
+            h2.submit(ctx, A, A, bad)
+        assert ei.value.code == h2.H2_ERR_INVALID_ARG
+    with pytest.raises(h2.H2Error):
+        h2.set_lanes(ctx, 9)
