@@ -32,6 +32,11 @@ product.  --sweep LEVELS instead times G*G, G*K and K*K over icosphere levels, a
 --sweep-cube M K*K on the cube surface with m x m squares per face, at eps
 1e-4, and reports time per degree of freedom, storage and error per n.
 
+--workload c4 times a batch of 64 independent products submitted at once
+(overlapping on the context's lanes) against the same products one at a
+time; --serve serves a seeded Poisson stream of requests on resident operands
+and reports throughput and p50/p99 latency.
+
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -259,12 +264,181 @@ def sweep(h2, ctx, jobs, steps, eps):
                        "operators": {k: v["desc"] for k, v in SWEEP.items()}}}
 
 
+def run_c4(h2, args):
+    """Many independent products (64 instances, n log-uniform in [1024, 32768],
+    orders 3..6, eps 1e-5, FP32 bulk): all submitted at once and overlapping
+    on the context's lanes; one step = one batch.  The same products one after
+    the other (h2_mul) are timed too."""
+    from paper_2403_01566_amd import workloads as W
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, args.lanes)
+    inst = W.batched_instances()
+    say(f"building {len(inst)} operands")
+    ops = []
+    for q in inst:
+        T = h2.Tree(ctx, W.uniform2d(q["n"], q["points_seed"]), q["leaf"])
+        ops.append((T, h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, q["order"], 0.5, h2.DIAG_ZERO)))
+    eps = 1e-5
+    opt = h2.default_options(precision=h2.PREC_FP32_BULK)
+    pairs = [(A, A) for _, A in ops]
+    say("first batch (plans built on the host)")
+    t0 = time.perf_counter()
+    out = h2.mul_batch(ctx, pairs, eps, opt)
+    t_first = time.perf_counter() - t0
+    prec = [st["prec_used"] for _, st in out]
+    del out
+    for _ in range(args.warmup):
+        h2.mul_batch(ctx, pairs, eps, opt)
+    say(f"timing {args.steps} batches")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = h2.mul_batch(ctx, pairs, eps, opt)
+        del out
+    total = time.perf_counter() - t0
+    say("the same products one at a time")
+    t0 = time.perf_counter()
+    for A, B in pairs:
+        C, _ = h2.mul(ctx, A, B, eps, opt)
+        del C
+    seq = time.perf_counter() - t0
+    ms = 1000.0 * total / args.steps
+    return {
+        "metric": "batched H2 products/s (64 independent products)",
+        "value": len(pairs) * args.steps / total,
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded uniform points, operands built by interpolation on the device)",
+        "config": {"workload": "64 products A_i A_i, n_i log-uniform in [1024, 32768] (PCG64 seed 2403), uniform "
+                               "points in [0,1]^2, -log|x-y|, Chebyshev order 3..6, leaf 32 (order <= 4) or 64, "
+                               "eta 1/2, eps 1e-5, FP32 bulk", "lanes": args.lanes, "total_n": sum(T.n for T, _ in ops),
+                   "fp32_bulk_products": int(sum(1 for x in prec if x == h2.PREC_FP32_BULK))},
+        "sequential_products_per_s": len(pairs) / seq,
+        "overlap_speedup": seq / (total / args.steps),
+        "first_batch_s": t_first,
+    }
+
+
+def run_serve(h2, args):
+    """Serving: a seeded Poisson stream of product requests on resident
+    operands.  Requests are admitted on arrival while fewer than
+    2 x lanes products are in flight (each product's plan is resident, so its
+    memory is known and already held: admission by footprint reduces to the
+    in-flight cap) and overlap on the lanes; latency = result ready - arrival."""
+    from collections import deque
+    from paper_2403_01566_amd import workloads as W
+    nreq = args.serve_requests + args.serve_warmup
+    reqs = W.serving_requests(nreq, rate=args.serve_rate, m_range=(12, args.serve_mmax))
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, args.lanes)
+    ops = {}
+    for r in reqs:
+        key = (r["geometry"], r["m"], r["order"])
+        if key in ops:
+            continue
+        P, nrm = W.serving_points(r["geometry"], r["m"])
+        if r["geometry"] == "2d":
+            T = h2.Tree(ctx, P, 32 if r["order"] ** 2 <= 32 else 64)
+            A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, r["order"], 0.5, h2.DIAG_ZERO)
+        else:
+            T = h2.Tree(ctx, P, 32 if r["order"] ** 3 <= 32 else 64)
+            A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_LAPLACE_SLP, r["order"], 1.0, h2.DIAG_ROW_NEARFIELD_MEAN,
+                                       nrm)
+        ops[key] = (T, A)
+    def options(eps):
+        return h2.default_options(precision=h2.PREC_FP32_BULK if eps >= 1e-5 else h2.PREC_FP64)
+    say(f"{len(ops)} operands; planning every (operand, precision) class once")
+    seen, rejected_cls = set(), {}
+    for r in reqs:
+        k = (r["geometry"], r["m"], r["order"], r["eps"])
+        if k not in seen:
+            seen.add(k)
+            if len(seen) % 10 == 0:
+                say(f"  {len(seen)} request classes ready")
+            try:
+                C, _ = h2.mul(ctx, ops[k[:3]][1], ops[k[:3]][1], r["eps"], options(r["eps"]))
+                del C
+            except h2.H2Error as e:  # e.g. a rank cap: the library refuses, the server reports it
+                rejected_cls[k] = str(e)
+    if rejected_cls:
+        say(f"{len(rejected_cls)} request classes refused by the library: {sorted(set(rejected_cls.values()))}")
+    cap = 2 * args.lanes
+    say(f"serving {nreq} requests at {args.serve_rate}/s, at most {cap} in flight")
+    pending = deque(reqs)
+    inflight = []
+    done, refused = [], []
+    t_start = time.perf_counter()
+    while pending or inflight:
+        now = time.perf_counter() - t_start
+        progressed = False
+        while pending and pending[0]["t"] <= now and len(inflight) < cap:
+            r = pending.popleft()
+            progressed = True
+            if (r["geometry"], r["m"], r["order"], r["eps"]) in rejected_cls:
+                refused.append(r)
+                continue
+            A = ops[(r["geometry"], r["m"], r["order"])][1]
+            inflight.append((r, h2.submit(ctx, A, A, r["eps"], options(r["eps"]))))
+        still = []
+        for r, j in inflight:
+            if j.poll():
+                try:
+                    C, st = j.wait()
+                    del C
+                    done.append((r, time.perf_counter() - t_start))
+                except h2.H2Error:
+                    refused.append(r)
+                j.close()
+                progressed = True
+                if (len(done) + len(refused)) % 50 == 0:
+                    say(f"  {len(done)} served, {len(refused)} refused, {len(pending)} not yet admitted at "
+                        f"t = {time.perf_counter() - t_start:.1f} s")
+            else:
+                still.append((r, j))
+        inflight = still
+        if not progressed:
+            time.sleep(0.0002)
+    order = {id(r): i for i, r in enumerate(reqs)}
+    measured = [(r, t) for r, t in done if order[id(r)] >= args.serve_warmup]
+    lat = sorted(1000.0 * (t - r["t"]) for r, t in measured)
+    t_first = min(r["t"] for r, _ in measured)
+    t_last = max(t for _, t in measured)
+    pct = lambda q: lat[min(len(lat) - 1, int(math.ceil(q * len(lat))) - 1)]
+    return {
+        "metric": "served H2 products/s and latency (Poisson stream)",
+        "value": len(measured) / (t_last - t_first),
+        "unit": "products/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "offered_rate": args.serve_rate,
+        "requests": len(measured),
+        "warmup_requests": args.serve_warmup,
+        "refused_requests": sum(1 for r in refused if order[id(r)] >= args.serve_warmup),
+        "refused_reasons": sorted(set(rejected_cls.values())),
+        "latency_ms": {"p50": pct(0.5), "p99": pct(0.99), "max": lat[-1]},
+        "saturated": len(measured) / (t_last - t_first) < 0.9 * args.serve_rate,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded request stream and operands)",
+        "config": {"workload": f"Poisson arrivals {args.serve_rate}/s (PCG64 seed 2404); geometry 2D uniform or "
+                               f"Fibonacci sphere, n = 2^m, m in 12..{args.serve_mmax}, order 2D 3..8 / sphere "
+                               f"3..4, eps in 1e-4, 1e-6, 1e-8 (FP32 bulk at eps >= 1e-5)",
+                   "operands": len(ops), "request_classes": len(seen), "lanes": args.lanes,
+                   "max_in_flight": cap},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-global-error", action="store_true",
@@ -276,6 +450,13 @@ def main():
     ap.add_argument("--sweep-cube", default="", metavar="M",
                     help="comma-separated squares per cube edge: K*K on the cube surface (n = 12 m^2)")
     ap.add_argument("--sweep-eps", type=float, default=1e-4)
+    ap.add_argument("--lanes", type=int, default=4, help="lanes (streams) for batched and served products")
+    ap.add_argument("--serve", action="store_true", help="serve a Poisson stream of requests instead")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=50)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-mmax", type=int, default=15,
+                    help="largest m (n = 2^m); the workload names 17, whose plans exceed the memory here")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -291,6 +472,12 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     from paper_2403_01566_amd import h2
+    if args.serve:
+        print(json.dumps(run_serve(h2, args)), flush=True)
+        return
+    if args.workload == "c4":
+        print(json.dumps(run_c4(h2, args)), flush=True)
+        return
     if args.sweep or args.sweep_cube:
         ctx = h2.Context(0)
         jobs = [(k, "ico", int(x)) for k in ("slp", "slp_dlp", "dlp") for x in args.sweep.split(",") if x]

@@ -143,6 +143,9 @@ struct LaneRes {
   int* flags = nullptr;         // kFlagSlots device ints
   std::vector<int> free_slots;  // flags not held by a job that is still to be waited for
   int inflight = 0;
+  DevBuf arena;        // workspaces of the product plans bound to this lane
+  int nplans = 0;      // plans bound to this lane
+  uint64_t epoch = 0;  // changes whenever the arena is (re)allocated
 };
 constexpr int kFlagSlots = 64;
 
@@ -165,6 +168,7 @@ struct Context {
   // lanes for asynchronous products: lanes[0] shares the context's stream
   // (its flags are separate from `overflow`); created by set_lanes
   std::vector<std::unique_ptr<LaneRes>> lanes;
+  uint64_t arena_epoch = 0;  // source of LaneRes::epoch values (unique per allocation)
   Lane lane0() const {
     Lane l;
     l.stream = stream;

@@ -176,6 +176,16 @@ struct Plan {
   std::vector<int64_t> base_d, base_f;  // allocation starts in the planned (unshared) layout
   int64_t wsd_planned = 0, wsf_planned = 0;
   DevBuf bufd, buff, bufi, desc;
+  // workspace base pointers that descriptors are resolved against: the
+  // plan's own buffers, or the arena of the lane it is bound to (product
+  // plans: the plans of one lane run one at a time and share its arena)
+  double* wd = nullptr;
+  float* wf = nullptr;
+  int* wi = nullptr;
+  size_t ws_bytes = 0;  // FP64, FP32 and int workspaces, each 256-byte aligned
+  bool keep_protos = false;
+  int bound_lane = -1;
+  uint64_t bound_epoch = 0;
   std::vector<char> hdesc;
   int kc = 0, kappa_cap = 0;
   DRef<double> res_vleaf, res_vtr, res_wleaf, res_wtr, res_S, res_N;
@@ -1734,9 +1744,9 @@ void Planner::couplings() {
 template <typename T>
 static T* res(const DRef<T>& r, const Plan& P) {
   if (r.ws == WS_NONE) return r.ext ? r.ext + r.off : nullptr;
-  if (r.ws == WS_D) return reinterpret_cast<T*>(P.bufd.as<double>() + r.off);
-  if (r.ws == WS_F) return reinterpret_cast<T*>(P.buff.as<float>() + r.off);
-  return reinterpret_cast<T*>(P.bufi.as<int>() + r.off);
+  if (r.ws == WS_D) return reinterpret_cast<T*>(P.wd + r.off);
+  if (r.ws == WS_F) return reinterpret_cast<T*>(P.wf + r.off);
+  return reinterpret_cast<T*>(P.wi + r.off);
 }
 
 template <typename T>
@@ -1804,7 +1814,7 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     v[i].w_dev = res(s.w_dev, P);
     v[i].w_dev2 = res(s.w_dev2, P);
     v[i].split_dev = res(s.split_dev, P);
-    v[i].stat = P.bufi.as<int>() + st.stat_off + 4 * i;
+    v[i].stat = P.wi + st.stat_off + 4 * i;
     v[i].urows = s.urows;
     v[i].qrcp = P.qrcp;
     v[i].sigma = res(s.sigma, P);
@@ -2052,7 +2062,11 @@ static double ref_scale(const Plan& P, const PRefMat& m, double eps) {
   return m.approx ? 1.0 / (1.0 + eps * P.budget[0]) : 1.0;
 }
 
-static void finalize(Plan& P, double eps) {
+// Sizes of the workspaces (the QR / SVD size reports go after the int
+// buffers) and their total in bytes.
+static size_t ws_part(int64_t count, size_t elem) { return ((size_t)std::max<int64_t>(count, 1) * elem + 255) & ~size_t(255); }
+
+static void layout(Plan& P) {
   for (auto& st : P.steps) {
     const int per = st.kind == SK_QR ? 2 : (st.kind == SK_SVD ? 4 : 0);
     const size_t n = st.kind == SK_QR ? st.qr.size() : st.svd.size();
@@ -2060,12 +2074,22 @@ static void finalize(Plan& P, double eps) {
     st.stat_off = P.wsi;
     P.wsi += ((int64_t)(per * n) + 63) & ~int64_t(63);
   }
+  P.ws_bytes = ws_part(P.wsd, sizeof(double)) + ws_part(P.wsf, sizeof(float)) + ws_part(P.wsi, sizeof(int));
   if (std::getenv("H2_TRACE"))
     std::fprintf(stderr, "[h2 plan] workspace %.3f GB fp64, %.3f GB fp32, %.3f GB int, %zu steps\n",
                  P.wsd * 8e-9, P.wsf * 4e-9, P.wsi * 4e-9, P.steps.size());
-  P.bufd.alloc(std::max<int64_t>(P.wsd, 1) * sizeof(double));
-  P.buff.alloc(std::max<int64_t>(P.wsf, 1) * sizeof(float));
-  P.bufi.alloc(std::max<int64_t>(P.wsi, 1) * sizeof(int));
+}
+
+// Points the workspaces at `base` (ws_bytes long).
+static void set_base(Plan& P, char* base) {
+  P.wd = reinterpret_cast<double*>(base);
+  P.wf = reinterpret_cast<float*>(base + ws_part(P.wsd, sizeof(double)));
+  P.wi = reinterpret_cast<int*>(base + ws_part(P.wsd, sizeof(double)) + ws_part(P.wsf, sizeof(float)));
+}
+
+// Descriptors of every step, resolved against the current workspace
+// pointers, uploaded to the device.
+static void emit(Plan& P, double eps) {
   std::vector<char> blob;
   auto align = [&](size_t a) {
     while (blob.size() % a) blob.push_back(0);
@@ -2079,7 +2103,7 @@ static void finalize(Plan& P, double eps) {
         st.desc_off = blob.size();
         for (size_t i = 0; i < st.qr.size(); ++i) {
           const PQr& q = st.qr[i];
-          int* stat = P.bufi.as<int>() + st.stat_off + 2 * i;
+          int* stat = P.wi + st.stat_off + 2 * i;
           h2k::QrTask t{res(q.a, P),  res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), res(q.m_dev, P), stat,
                         q.lda,        q.ldr,       q.m,               q.w,                q.trans_r,         q.mul_we,
                         q.part,       q.m_off};
@@ -2145,15 +2169,62 @@ static void finalize(Plan& P, double eps) {
     }
   }
   P.hdesc = blob;
-  P.desc.alloc(std::max<size_t>(blob.size(), 64));
+  if (P.desc.bytes < blob.size() || !P.desc.p) P.desc.alloc(std::max<size_t>(blob.size(), 64));
   H2_HIP(hipMemcpy(P.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
   P.eps_set = eps;
-  // descriptors are on the device; drop the host-side proto lists of GEMM steps
-  for (auto& st : P.steps) {
-    st.itd.clear(); st.itd.shrink_to_fit();
-    st.tkd.clear(); st.tkd.shrink_to_fit();
-    st.itf.clear(); st.itf.shrink_to_fit();
-    st.tkf.clear(); st.tkf.shrink_to_fit();
+  if (!P.keep_protos) {
+    // descriptors are on the device for good; drop the host-side proto lists of GEMM steps
+    for (auto& st : P.steps) {
+      st.itd.clear(); st.itd.shrink_to_fit();
+      st.tkd.clear(); st.tkd.shrink_to_fit();
+      st.itf.clear(); st.itf.shrink_to_fit();
+      st.tkf.clear(); st.tkf.shrink_to_fit();
+    }
+  }
+}
+
+// A plan with workspaces of its own (matrix-vector products, recompression).
+static void finalize(Plan& P, double eps) {
+  layout(P);
+  P.bufd.alloc(P.ws_bytes);
+  set_base(P, P.bufd.as<char>());
+  emit(P, eps);
+}
+
+// A product plan bound to a lane: its workspaces are the lane's arena, grown
+// to the plan's size if needed (after the lane's work has finished; the
+// plans bound to it before are re-emitted at their next use). Only a plan
+// without jobs in flight changes lanes.
+static void bind(Context* ctx, Plan& P, int lane, double eps) {
+  LaneRes& LR = *ctx->lanes[lane];
+  if (LR.arena.bytes < P.ws_bytes) {
+    for (hipStream_t s : {LR.l.stream, LR.l.aux[0], LR.l.aux[1]}) H2_HIP(hipStreamSynchronize(s));
+    LR.arena.release();
+    LR.epoch = 0;
+    try {
+      LR.arena.alloc(P.ws_bytes);
+    } catch (const Error& e) {
+      if (e.code != H2_ERR_OUT_OF_MEMORY) throw;
+      // make room: the arenas of idle lanes go (their plans are re-emitted later)
+      for (auto& o : ctx->lanes)
+        if (o.get() != &LR && o->inflight == 0 && o->arena.p) {
+          for (hipStream_t s : {o->l.stream, o->l.aux[0], o->l.aux[1]}) H2_HIP(hipStreamSynchronize(s));
+          o->arena.release();
+          o->epoch = 0;
+        }
+      LR.arena.alloc(P.ws_bytes);
+    }
+    LR.epoch = ++ctx->arena_epoch;
+  }
+  if (P.bound_lane != lane || P.bound_epoch != LR.epoch || LR.epoch == 0 || !P.desc.p) {
+    if (P.bound_lane != lane) {
+      if (P.bound_lane >= 0 && P.bound_lane < (int)ctx->lanes.size()) --ctx->lanes[P.bound_lane]->nplans;
+      ++LR.nplans;
+    }
+    set_base(P, LR.arena.as<char>());
+    P.bound_lane = lane;
+    P.bound_epoch = LR.epoch;
+    emit(P, eps);
   }
 }
 
@@ -2359,7 +2430,7 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
         const size_t n = kind == SK_QR ? st.qr.size() : st.svd.size();
         stat.resize(per * n);
         if (n)
-          H2_HIP(hipMemcpy(stat.data(), P.bufi.as<int>() + st.stat_off, per * n * sizeof(int),
+          H2_HIP(hipMemcpy(stat.data(), P.wi + st.stat_off, per * n * sizeof(int),
                            hipMemcpyDeviceToHost));
         if (kind == SK_SVD && n && std::getenv("H2_TRACE")) {  // per-step shape summary
           double sm[4] = {0, 0, 0, 0};
@@ -2535,148 +2606,14 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   if (std::getenv("H2_TRACE"))
     std::fprintf(stderr, "[h2 plan] shared workspace: fp64 %.3f GB of %.3f GB, fp32 %.3f GB of %.3f GB\n",
                  P->wsd * 8e-9, P->wsd_planned * 8e-9, P->wsf * 4e-9, P->wsf_planned * 4e-9);
-  finalize(*P, eps);
+  layout(*P);
+  P->keep_protos = true;  // descriptors are emitted when the plan is bound to a lane
   ws("final");
   return P;
 }
 
-std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
-                                 h2_mul_stats* stats) {
-  if (X->cols.get() != Y->rows.get()) throw Error(H2_ERR_INCOMPATIBLE, "X's column tree is not Y's row tree");
-  if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
-  if (X->kc > 64 || Y->kc > 64) throw Error(H2_ERR_TOO_LARGE, "operand rank above 64");
-  // FP32 bulk only where its rounding (about 1e-7 of a block's norm) stays well
-  // below the truncation tolerances; tighter eps runs the bulk in FP64.
-  bool f32 = opt.precision == H2_PREC_FP32_BULK && eps >= 1e-5;
-  if (f32) {
-    auto f = ctx->fp32_fail_eps.find({X->id, Y->id});
-    if (f != ctx->fp32_fail_eps.end() && eps <= f->second) f32 = false;
-  }
-  const int kmax = std::max(X->kc, Y->kc);
-  int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
-  int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
-  if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
-  auto t0 = std::chrono::steady_clock::now();
-  auto key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0) + 0);
-  std::shared_ptr<Plan> P;
-  auto it = ctx->plans.find(key);
-  bool built = false;
-  if (it != ctx->plans.end() && it->second->kc == kc && it->second->kappa_cap == kcap &&
-      it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta)) {
-    P = it->second;
-  } else {
-    if (f32) {
-      X->ensure_fp32(ctx->stream);
-      Y->ensure_fp32(ctx->stream);
-    }
-    P = make_plan(ctx, X, Y, f32, kc, kcap, opt, eps);
-    ctx->plans[key] = P;
-    built = true;
-  }
-  quiesce(ctx, *P);
-  set_eps(*P, eps);
-  double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  H2_HIP(hipMemsetAsync(ctx->overflow, 0, sizeof(int), ctx->stream));
-  double tph[8] = {0};
-  execute(ctx, ctx->lane0(), *P, opt.timing, tph);
-  // while the device works: the result's block tree and one allocation for
-  // its arrays (filled by device copies once the product is done)
-  auto Cm = std::make_unique<Matrix>();
-  Cm->ctx = ctx;
-  Cm->hold = ctx->self.lock();
-  Cm->id = ctx->next_id++;
-  Cm->rows = X->rows;
-  Cm->cols = Y->cols;
-  build_block_tree(Cm->bt, *X->rows, *Y->cols, X->bt.eta);
-  Cm->kc = kc;
-  Cm->w_is_v = false;
-  const int64_t n_vleaf = X->rows->n * kc, n_vtr = (int64_t)X->rows->ncl * kc * kc, n_wleaf = Y->cols->n * kc,
-                n_wtr = (int64_t)Y->cols->ncl * kc * kc, n_s = (int64_t)P->cbt.adm.size() * kc * kc,
-                n_n = P->cnsize;
-  auto pad = [](int64_t c) { return (std::max<int64_t>(c, 1) + 31) & ~int64_t(31); };
-  Cm->bufs.emplace_back(new DevBuf);
-  Cm->bufs.back()->alloc((size_t)(pad(n_vleaf) + pad(n_vtr) + pad(n_wleaf) + pad(n_wtr) + pad(n_s) + pad(n_n)) *
-                         sizeof(double));
-  double* carve = Cm->bufs.back()->as<double>();
-  auto take = [&](int64_t c) {
-    double* d = carve;
-    carve += pad(c);
-    return d;
-  };
-  Cm->V.leaf = take(n_vleaf);
-  Cm->V.transfer = take(n_vtr);
-  Cm->W.leaf = take(n_wleaf);
-  Cm->W.transfer = take(n_wtr);
-  Cm->S = take(n_s);
-  Cm->N = take(n_n);
-  int ovf = 0;
-  H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  H2_HIP(hipStreamSynchronize(ctx->stream));
-  if (ovf) {
-    if (f32) {
-      // FP32 rounding of the exact blocks reached the truncation tolerance
-      // (cancellation in the product): rounding noise would be kept as rank.
-      // Run this product, and tighter ones on the same pair, in FP64.
-      double& fe = ctx->fp32_fail_eps[{X->id, Y->id}];
-      fe = std::max(fe, eps);
-      ctx->plans.erase(key);
-      P.reset();
-      h2_mul_options o2 = opt;
-      o2.precision = H2_PREC_FP64;
-      return multiply(ctx, X, Y, eps, o2, stats);
-    }
-    if ((ovf & 2) && opt.max_rank == 0 && kc < 64) {
-      // the default cap was too small for this product: retry once with the largest cap
-      h2_mul_options o2 = opt;
-      o2.max_rank = 64;
-      return multiply(ctx, X, Y, eps, o2, stats);
-    }
-    throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "coarsened rank above coarse_rank cap"
-                                             : "basis rank above max_rank cap");
-  }
-  // the result matrix owns copies of the result arrays
-  auto cp = [&](double* d, const DRef<double>& src, int64_t count) {
-    if (count) H2_HIP(hipMemcpyAsync(d, res(src, *P), count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  };
-  cp(Cm->V.leaf, P->res_vleaf, n_vleaf);
-  cp(Cm->V.transfer, P->res_vtr, n_vtr);
-  cp(Cm->W.leaf, P->res_wleaf, n_wleaf);
-  cp(Cm->W.transfer, P->res_wtr, n_wtr);
-  cp(Cm->S, P->res_S, n_s);
-  cp(Cm->N, P->res_N, n_n);
-  Cm->noff = P->cnoff;
-  Cm->nsize = P->cnsize;
-  Cm->rank_row.resize(X->rows->ncl);
-  Cm->rank_col.resize(Y->cols->ncl);
-  H2_HIP(hipMemcpyAsync(Cm->rank_row.data(), res(P->res_rank_row, *P), X->rows->ncl * sizeof(int),
-                        hipMemcpyDeviceToHost, ctx->stream));
-  H2_HIP(hipMemcpyAsync(Cm->rank_col.data(), res(P->res_rank_col, *P), Y->cols->ncl * sizeof(int),
-                        hipMemcpyDeviceToHost, ctx->stream));
-  H2_HIP(hipStreamSynchronize(ctx->stream));
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    for (int i = 0; i < 8; ++i) stats->t_phase[i] = tph[i];
-    stats->t_plan_ms = built ? tplan : 0.0;
-    stats->bytes_alg = P->bytes_alg;
-    stats->flops_alg = P->flops_alg;
-    stats->prec_used = f32 ? H2_PREC_FP32_BULK : H2_PREC_FP64;
-    stats->rank_max_row = Cm->rank_row.empty() ? 0 : *std::max_element(Cm->rank_row.begin(), Cm->rank_row.end());
-    stats->rank_max_col = Cm->rank_col.empty() ? 0 : *std::max_element(Cm->rank_col.begin(), Cm->rank_col.end());
-    stats->coarse_rank_max = P->max_coarse_K;
-    stats->n_adm = P->n_adm;
-    stats->n_inadm = P->n_inadm;
-    stats->launches = P->launches;
-    static_assert(h2k::K_COUNT == H2_NKERNEL, "kernel count");
-    for (int i = 0; i < h2k::K_COUNT; ++i) {
-      stats->t_kernel[i] = P->t_k[i];
-      stats->launches_kernel[i] = P->launches_k[i];
-      stats->units_kernel[i] = P->units_k[i];
-      stats->flops_kernel[i] = P->flops_k[i];
-      stats->bytes_kernel[i] = P->bytes_k[i];
-    }
-  }
-  return Cm;
-}
+// multiply() (the synchronous product) is submit + wait, defined with the
+// asynchronous products below.
 
 // ------------------------------------------------------------------ matrix-vector products
 // y = M x for an H2-matrix (Section 2: O(nk) with the nested bases), as
@@ -2693,8 +2630,8 @@ struct MvPlan {
   const Tree* tin = nullptr;
   const Tree* tout = nullptr;
   int64_t nrhs = 1;
-  double* in() const { return P->bufd.as<double>() + in_off; }
-  double* out() const { return P->bufd.as<double>() + out_off; }
+  double* in() const { return P->wd + in_off; }
+  double* out() const { return P->wd + out_off; }
 };
 
 static std::shared_ptr<MvPlan> build_mv(Matrix* M, int trans, int64_t nrhs) {
@@ -3087,11 +3024,13 @@ struct Job {
   double eps = 0;
   h2_mul_options opt{};
   std::shared_ptr<Plan> P;
+  std::pair<uint64_t, uint64_t> key;
   bool f32 = false, built = false;
   int kc = 0, lane = 0;
   int slot = -1;        // this job's overflow flag: a slot of the lane's flags
   int* flag = nullptr;
   double tplan = 0;
+  double tph[8] = {0};
   hipEvent_t done = nullptr;
   std::unique_ptr<Matrix> C;
   int* dev_ranks = nullptr;  // row then column ranks, copied out of the plan
@@ -3124,7 +3063,8 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   J->Y = Y;
   J->eps = eps;
   J->opt = opt;
-  J->opt.timing = 0;  // no per-launch events on the asynchronous path
+  // FP32 bulk only where its rounding (about 1e-7 of a block's norm) stays well
+  // below the truncation tolerances; tighter eps runs the bulk in FP64.
   bool f32 = opt.precision == H2_PREC_FP32_BULK && eps >= 1e-5;
   if (f32) {
     auto f = ctx->fp32_fail_eps.find({X->id, Y->id});
@@ -3135,50 +3075,58 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   const int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
   if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
   auto t0 = std::chrono::steady_clock::now();
-  const auto key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0));
-  auto it = ctx->plans.find(key);
+  J->key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0));
+  auto it = ctx->plans.find(J->key);
   if (it != ctx->plans.end() && it->second->kc == kc && it->second->kappa_cap == kcap &&
       it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta)) {
     J->P = it->second;
   } else {
+    if (it != ctx->plans.end()) quiesce(ctx, *it->second);
     if (f32) {
       X->ensure_fp32(ctx->stream);
       Y->ensure_fp32(ctx->stream);
       H2_HIP(hipStreamSynchronize(ctx->stream));
     }
     J->P = make_plan(ctx, X, Y, f32, kc, kcap, opt, eps);
-    ctx->plans[key] = J->P;
+    ctx->plans[J->key] = J->P;
     J->built = true;
   }
   Plan& P = *J->P;
-  // lane: the plan's own while it has jobs in flight, else the least loaded
-  int lane = 0;
+  // lane: the one the plan is bound to (moving re-emits all its
+  // descriptors); a plan not bound yet goes to the lane with the fewest
+  // plans bound to it, then the fewest jobs in flight
+  int lane;
   if (P.inflight > 0 && P.lane >= 0) {
     lane = P.lane;
+  } else if (P.bound_lane >= 0 && P.bound_lane < (int)ctx->lanes.size()) {
+    lane = P.bound_lane;
   } else {
-    for (int i = 1; i < (int)ctx->lanes.size(); ++i)
-      if (ctx->lanes[i]->inflight < ctx->lanes[lane]->inflight) lane = i;
+    lane = 0;
+    for (int i = 1; i < (int)ctx->lanes.size(); ++i) {
+      const LaneRes &a = *ctx->lanes[i], &b = *ctx->lanes[lane];
+      if (a.nplans < b.nplans || (a.nplans == b.nplans && a.inflight < b.inflight)) lane = i;
+    }
   }
   LaneRes& LR = *ctx->lanes[lane];
   if (LR.free_slots.empty()) throw Error(H2_ERR_TOO_LARGE, "more than 64 jobs in flight on one lane");
   if (P.eps_set != eps) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
+  bind(ctx, P, lane, eps);
   set_eps(P, eps);
   J->f32 = f32;
   J->kc = kc;
   J->lane = lane;
-  J->tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   J->slot = LR.free_slots.back();
   LR.free_slots.pop_back();
   J->flag = LR.flags + J->slot;
   ++P.inflight;  // from here on release() undoes these
   P.lane = lane;
   ++LR.inflight;
+  J->tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   Lane L = LR.l;
   L.overflow = J->flag;
   const hipStream_t s = L.stream;
   H2_HIP(hipMemsetAsync(J->flag, 0, sizeof(int), s));
-  double tph[8] = {0};
-  execute(ctx, L, P, 0, tph);
+  execute(ctx, L, P, opt.timing, J->tph);
   // result arrays: one allocation, filled by copies queued behind the product
   auto Cm = std::make_unique<Matrix>();
   Cm->ctx = ctx;
@@ -3245,12 +3193,27 @@ std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
   H2_HIP(hipMemcpy(&ovf, J.flag, sizeof(int), hipMemcpyDeviceToHost));
   J.release();
   if (ovf) {
-    // a rank cap was exceeded: the synchronous path decides (FP64 bulk, the
-    // largest result cap) exactly as for h2_mul
     J.C.reset();
-    J.P.reset();
-    h2_mul_options o = J.opt;
-    return multiply(ctx, J.X, J.Y, J.eps, o, stats);
+    if (J.f32) {
+      // FP32 rounding of the exact blocks reached the truncation tolerance
+      // (cancellation in the product): rounding noise would be kept as rank.
+      // Run this product, and tighter ones on the same pair, in FP64.
+      double& fe = ctx->fp32_fail_eps[{J.X->id, J.Y->id}];
+      fe = std::max(fe, J.eps);
+      ctx->plans.erase(J.key);
+      J.P.reset();
+      h2_mul_options o2 = J.opt;
+      o2.precision = H2_PREC_FP64;
+      return multiply(ctx, J.X, J.Y, J.eps, o2, stats);
+    }
+    if ((ovf & 2) && J.opt.max_rank == 0 && J.kc < 64) {
+      // the default cap was too small for this product: retry once with the largest cap
+      h2_mul_options o2 = J.opt;
+      o2.max_rank = 64;
+      return multiply(ctx, J.X, J.Y, J.eps, o2, stats);
+    }
+    throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "coarsened rank above coarse_rank cap"
+                                             : "basis rank above max_rank cap");
   }
   Matrix& C = *J.C;
   const int nr = J.X->rows->ncl, nc = J.Y->cols->ncl;
@@ -3259,8 +3222,9 @@ std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
   C.rank_row.assign(rk.begin(), rk.begin() + nr);
   C.rank_col.assign(rk.begin() + nr, rk.end());
   if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
     const Plan& P = *J.P;
+    std::memset(stats, 0, sizeof(*stats));
+    for (int i = 0; i < 8; ++i) stats->t_phase[i] = J.tph[i];
     stats->t_plan_ms = J.built ? J.tplan : 0.0;
     stats->bytes_alg = P.bytes_alg;
     stats->flops_alg = P.flops_alg;
@@ -3270,8 +3234,23 @@ std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
     stats->coarse_rank_max = P.max_coarse_K;
     stats->n_adm = P.n_adm;
     stats->n_inadm = P.n_inadm;
+    stats->launches = P.launches;
+    static_assert(h2k::K_COUNT == H2_NKERNEL, "kernel count");
+    for (int i = 0; i < h2k::K_COUNT; ++i) {
+        stats->t_kernel[i] = P.t_k[i];
+        stats->launches_kernel[i] = P.launches_k[i];
+        stats->units_kernel[i] = P.units_k[i];
+        stats->flops_kernel[i] = P.flops_k[i];
+        stats->bytes_kernel[i] = P.bytes_k[i];
+    }
   }
   return std::move(J.C);
+}
+
+std::unique_ptr<Matrix> multiply(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt,
+                                 h2_mul_stats* stats) {
+  std::unique_ptr<Job> J(submit(ctx, X, Y, eps, opt));
+  return wait(*J, stats);
 }
 
 void destroy_job(Job* J) {

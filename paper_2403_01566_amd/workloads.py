@@ -12,6 +12,8 @@ Workloads (stand-ins for the paper's Galerkin meshes, Section 6):
     midpoints projected to the unit sphere; returns the 20*4^level triangle
     centroids (not projected) and the outward unit face normals.
   * ``fibsphere(n)``: Fibonacci lattice on the unit sphere; normals = points.
+  * ``batched_instances``, ``serving_requests``, ``serving_points``: the
+    parameters of the many-products and the serving workloads (seeded).
   * ``cube_surface(m)``: surface of [-1,1]^3, every face cut into m x m
     squares and every square into two triangles; returns the 12*m^2 triangle
     centroids and the outward face normals (the double-layer geometry of the
@@ -157,6 +159,33 @@ def batched_instances(count: int = 64, seed: int = 2403):
         pseed = int(rng.integers(0, 2**31 - 1))
         out.append({"n": n, "order": p, "leaf": 32 if p <= 4 else 64, "points_seed": pseed})
     return out
+
+
+def serving_requests(count: int, rate: float = 200.0, seed: int = 2404, m_range=(12, 17)):
+    """Seeded request stream of the serving workload: Poisson arrivals (mean
+    `rate` per second; times in seconds from 0), each request picks the
+    geometry ("2d": uniform points in [0,1]^2, or "sphere": Fibonacci lattice),
+    n = 2^m with m uniform in m_range, the Chebyshev order (2D: 3..8, sphere:
+    3..4) and eps in {1e-4, 1e-6, 1e-8}, all uniformly."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    for _ in range(count):
+        t += rng.exponential(1.0 / rate)
+        geo = "2d" if rng.integers(0, 2) == 0 else "sphere"
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        p = int(rng.integers(3, 9)) if geo == "2d" else int(rng.integers(3, 5))
+        eps = float([1e-4, 1e-6, 1e-8][int(rng.integers(0, 3))])
+        out.append({"t": t, "geometry": geo, "m": m, "order": p, "eps": eps})
+    return out
+
+
+def serving_points(geometry: str, m: int):
+    """Points (and normals or None) of a serving operand: 2D uniform points
+    with seed 2405 + m, or the Fibonacci sphere with 2^m points."""
+    if geometry == "2d":
+        return uniform2d(2 ** m, 2405 + m), None
+    return fibsphere(2 ** m)
 
 
 def start_vector(n: int, seed: int) -> np.ndarray:
