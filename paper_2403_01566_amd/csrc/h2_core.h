@@ -163,6 +163,9 @@ struct Context {
   // operand pairs whose FP32 bulk exceeded a rank cap: largest such eps (those
   // products, and tighter ones, run the bulk in FP64)
   std::map<std::pair<uint64_t, uint64_t>, double> fp32_fail_eps;
+  // operand pairs whose products needed the largest result rank cap: later
+  // products of the pair start there (one plan, not a plan per cap)
+  std::map<std::pair<uint64_t, uint64_t>, int> kc_raised;
   // matrix-vector plans: (matrix id, transposed, number of vectors)
   std::map<std::tuple<uint64_t, int, int64_t>, std::shared_ptr<MvPlan>> mvplans;
   // lanes for asynchronous products: lanes[0] shares the context's stream

@@ -3071,7 +3071,11 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
     if (f != ctx->fp32_fail_eps.end() && eps <= f->second) f32 = false;
   }
   const int kmax = std::max(X->kc, Y->kc);
-  const int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
+  int kc = opt.max_rank > 0 ? opt.max_rank : std::min(64, std::max(32, (2 * kmax + 15) / 16 * 16));
+  if (opt.max_rank == 0) {
+    auto f = ctx->kc_raised.find({X->id, Y->id});
+    if (f != ctx->kc_raised.end()) kc = std::max(kc, f->second);
+  }
   const int kcap = opt.coarse_rank > 0 ? opt.coarse_rank : 64;
   if (kc > 64 || kcap > 64 || kc < 1 || kcap < 1) throw Error(H2_ERR_INVALID_ARG, "rank caps out of range");
   auto t0 = std::chrono::steady_clock::now();
@@ -3207,10 +3211,12 @@ std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
       return multiply(ctx, J.X, J.Y, J.eps, o2, stats);
     }
     if ((ovf & 2) && J.opt.max_rank == 0 && J.kc < 64) {
-      // the default cap was too small for this product: retry once with the largest cap
-      h2_mul_options o2 = J.opt;
-      o2.max_rank = 64;
-      return multiply(ctx, J.X, J.Y, J.eps, o2, stats);
+      // the default cap was too small for this product: retry once with the
+      // largest cap, and start there for later products of the pair
+      ctx->kc_raised[{J.X->id, J.Y->id}] = 64;
+      ctx->plans.erase(J.key);
+      J.P.reset();
+      return multiply(ctx, J.X, J.Y, J.eps, J.opt, stats);
     }
     throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "coarsened rank above coarse_rank cap"
                                              : "basis rank above max_rank cap");

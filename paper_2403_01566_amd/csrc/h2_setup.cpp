@@ -232,6 +232,10 @@ void Context::evict(uint64_t matrix_id) {
     if (std::get<0>(it->first) == matrix_id) it = mvplans.erase(it);
     else ++it;
   }
+  for (auto it = kc_raised.begin(); it != kc_raised.end();) {
+    if (it->first.first == matrix_id || it->first.second == matrix_id) it = kc_raised.erase(it);
+    else ++it;
+  }
   for (auto it = fp32_fail_eps.begin(); it != fp32_fail_eps.end();) {
     if (it->first.first == matrix_id || it->first.second == matrix_id) it = fp32_fail_eps.erase(it);
     else ++it;
