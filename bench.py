@@ -14,7 +14,8 @@ both legs compute in FP64 and `value` is the FP64 rate; the JSON says which
 precision each leg used.
 
 Timing: `value`, ms_per_step and the latencies come from the timed steps
-without instrumentation. The same number of products then runs again with
+without instrumentation (each product replays its HIP graph, captured in
+the warm-up). The same number of products then runs again with
 HIP events around every kernel launch, on the stream of the launch (timing
 mode 2): that pass gives the per-kernel device times of the roofline; the
 dominant kernel is the one with the largest device time.  Its algorithmic flops (or bytes) per
@@ -96,7 +97,7 @@ def say(*a):
 def run_mode(h2, ctx, A, B, eps, prec, steps, warmup):
     nk = h2.NKERNEL
     for _ in range(warmup):
-        C, _ = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))
+        C, _ = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec, graph=1))  # also captures the graph
         del C
     # untimed: algorithmic work of every kernel from the sizes the kernels report
     C, cnt = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec, timing=3))
@@ -106,7 +107,7 @@ def run_mode(h2, ctx, A, B, eps, prec, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         t1 = time.perf_counter()
-        C, st = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))  # returns when the device is done
+        C, st = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec, graph=1))  # returns when the device is done
         lat.append(time.perf_counter() - t1)
         del C
     total = time.perf_counter() - t0
@@ -292,7 +293,7 @@ def run_c4(h2, args):
         T = h2.Tree(ctx, W.uniform2d(q["n"], q["points_seed"]), q["leaf"])
         ops.append((T, h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, q["order"], 0.5, h2.DIAG_ZERO)))
     eps = 1e-5
-    opt = h2.default_options(precision=h2.PREC_FP32_BULK)
+    opt = h2.default_options(precision=h2.PREC_FP32_BULK, graph=1)
     pairs = [(A, A) for _, A in ops]
     say("first batch (plans built on the host)")
     t0 = time.perf_counter()
@@ -365,7 +366,7 @@ def run_serve(h2, args):
                                        nrm)
         ops[key] = (T, A)
     def options(eps):
-        return h2.default_options(precision=h2.PREC_FP32_BULK if eps >= 1e-5 else h2.PREC_FP64)
+        return h2.default_options(precision=h2.PREC_FP32_BULK if eps >= 1e-5 else h2.PREC_FP64, graph=1)
     say(f"{len(ops)} operands; planning every (operand, precision) class once")
     seen, rejected_cls = set(), {}
     for r in reqs:

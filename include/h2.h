@@ -111,6 +111,10 @@ typedef struct {
                           launch (events around each); 3: as 2, plus the algorithmic work of
                           every kernel from the sizes the kernels report (one extra
                           device-to-host copy after the product)                         */
+  int graph;           /* 1: run the product's launches as a HIP graph, captured at the
+                          first such call for the plan and replayed afterwards (fewer
+                          launch gaps for small products); needs timing = 0. 0: launch
+                          every kernel from the host.                                    */
 } h2_mul_options;
 
 /* Number of kernels in the per-kernel statistics; h2_kernel_name(i) names kernel i. */

@@ -186,6 +186,17 @@ struct Plan {
   bool keep_protos = false;
   int bound_lane = -1;
   uint64_t bound_epoch = 0;
+  // HIP graph of the product's launches (captured from the plan's streams).
+  // Kernels read the descriptors from device memory, so eps patches and
+  // re-emission into the same descriptor buffer keep it valid; a new buffer
+  // needs a new capture. Graph runs report overflows in gflag (a kernel
+  // argument fixed in the graph), copied to the job's flag afterwards.
+  hipGraphExec_t gexec = nullptr;
+  const void* g_desc = nullptr;
+  DevBuf gflag;
+  ~Plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+  }
   std::vector<char> hdesc;
   int kc = 0, kappa_cap = 0;
   DRef<double> res_vleaf, res_vtr, res_wleaf, res_wtr, res_S, res_N;
@@ -3130,7 +3141,36 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   L.overflow = J->flag;
   const hipStream_t s = L.stream;
   H2_HIP(hipMemsetAsync(J->flag, 0, sizeof(int), s));
-  execute(ctx, L, P, opt.timing, J->tph);
+  if (opt.graph && opt.timing == 0) {
+    if (!P.gflag.p) P.gflag.alloc(sizeof(int));
+    if (!P.gexec || P.g_desc != P.desc.p) {
+      if (P.gexec) {
+        H2_HIP(hipGraphExecDestroy(P.gexec));
+        P.gexec = nullptr;
+      }
+      Lane G = L;
+      G.overflow = P.gflag.as<int>();
+      hipGraph_t graph = nullptr;
+      H2_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      try {
+        execute(ctx, G, P, 0, J->tph);
+      } catch (...) {
+        (void)hipStreamEndCapture(s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      H2_HIP(hipStreamEndCapture(s, &graph));
+      const hipError_t e = hipGraphInstantiate(&P.gexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      H2_HIP(e);
+      P.g_desc = P.desc.p;
+    }
+    H2_HIP(hipMemsetAsync(P.gflag.p, 0, sizeof(int), s));
+    H2_HIP(hipGraphLaunch(P.gexec, s));
+    H2_HIP(hipMemcpyAsync(J->flag, P.gflag.p, sizeof(int), hipMemcpyDeviceToDevice, s));
+  } else {
+    execute(ctx, L, P, opt.timing, J->tph);
+  }
   // result arrays: one allocation, filled by copies queued behind the product
   auto Cm = std::make_unique<Matrix>();
   Cm->ctx = ctx;

@@ -124,3 +124,31 @@ def test_job_poll_wait_and_errors(h2):
         assert ei.value.code == h2.H2_ERR_INVALID_ARG
     with pytest.raises(h2.H2Error):
         h2.set_lanes(ctx, 9)
+
+
+def test_graph_replays_match_eager(h2):
+    """A product captured as a HIP graph and replayed: every replay equals
+    the eager product bit for bit, with other eager work, a tolerance change
+    and host synchronisations between the replays."""
+    ctx = h2.Context(0)
+    P, nrm = W.icosphere(3)
+    T = h2.Tree(ctx, P, 64)
+    A = h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_LAPLACE_SLP, 3, 1.0, h2.DIAG_ROW_NEARFIELD_MEAN, nrm)
+    T2 = h2.Tree(ctx, W.uniform2d(900, 11), 24)
+    B = h2.Matrix.interpolated(ctx, T2, T2, h2.KERNEL_NEG_LOG, 4, 0.5)
+    ref = {eps: h2.mul(ctx, A, A, eps)[0].to_dense(T.n, T.n) for eps in (1e-4, 1e-6)}
+    refB = h2.mul(ctx, B, B, 1e-5)[0].to_dense(T2.n, T2.n)
+    g = h2.default_options(graph=1)
+    for rep, eps in enumerate([1e-4, 1e-4, 1e-6, 1e-4, 1e-6, 1e-6]):
+        C, st = h2.mul(ctx, A, A, eps, g)
+        assert np.array_equal(C.to_dense(T.n, T.n), ref[eps]), (rep, eps)
+        # eager work on another plan and a matrix-vector product in between
+        CB, _ = h2.mul(ctx, B, B, 1e-5)
+        assert np.array_equal(CB.to_dense(T2.n, T2.n), refB)
+        A.matvec(np.ones(T.n))
+    # graph replays of two plans submitted together
+    jobs = [h2.submit(ctx, A, A, 1e-6, g), h2.submit(ctx, B, B, 1e-5, h2.default_options(graph=1))]
+    CA, _ = jobs[0].wait()
+    CB, _ = jobs[1].wait()
+    assert np.array_equal(CA.to_dense(T.n, T.n), ref[1e-6])
+    assert np.array_equal(CB.to_dense(T2.n, T2.n), refB)
