@@ -254,38 +254,45 @@ class H2Matrix:
 
 
 def build_interpolated(tree: ClusterTree, kernel: int, order: int, eta: float,
-                       diag: int = DIAG_ZERO, normals=None) -> H2Matrix:
-    """Operand construction of Section 2 (eq. interpolation, vsw, transfer)."""
+                       diag: int = DIAG_ZERO, normals=None, cols: ClusterTree | None = None) -> H2Matrix:
+    """Operand construction of Section 2 (eq. interpolation, vsw, transfer).
+    Rows on `tree`, columns on `cols` (default: the same tree); normals belong
+    to the column points; the diagonal rule needs rows and columns on one
+    tree."""
     T = tree
+    TC = T if cols is None else cols
     if kernel == KERNEL_DLP and normals is None:
         raise ValueError("double layer needs normals")
-    blocks = BlockTree(T, T, eta)
+    if diag != DIAG_ZERO and TC is not T:
+        raise ValueError("the diagonal rule needs one tree for rows and columns")
+    blocks = BlockTree(T, TC, eta)
     ip = Interp(T, order)
+    ipc = ip if TC is T else Interp(TC, order)
     Pp = T.points[T.perm]
-    Np = None if normals is None else np.asarray(normals, dtype=np.float64)[T.perm]
-    Vleaf, Wleaf, E = {}, {}, {}
-    for t in range(T.ncl):
-        if T.is_leaf(t):
-            X = Pp[T.begin[t]:T.end[t]]
-            Vleaf[t] = ip.lagrange(t, X)
-            if kernel == KERNEL_DLP:
-                Wleaf[t] = ip.lagrange_normal_deriv(t, X, Np[T.begin[t]:T.end[t]])
-            else:
-                Wleaf[t] = Vleaf[t]
-        if T.parent[t] >= 0:
-            E[t] = ip.lagrange(int(T.parent[t]), ip.nodes(t))
-    ranks = {t: ip.k for t in range(T.ncl)}
-    V = ClusterBasis(T, Vleaf, E, ranks)
-    W = V if kernel != KERNEL_DLP else ClusterBasis(T, Wleaf, E, ranks)
+    Pc = TC.points[TC.perm]
+    Np = None if normals is None else np.asarray(normals, dtype=np.float64)[TC.perm]
+
+    def basis(tr, itp, pts, deriv):
+        leaf, E = {}, {}
+        for t in range(tr.ncl):
+            if tr.is_leaf(t):
+                X = pts[tr.begin[t]:tr.end[t]]
+                leaf[t] = itp.lagrange_normal_deriv(t, X, Np[tr.begin[t]:tr.end[t]]) if deriv else itp.lagrange(t, X)
+            if tr.parent[t] >= 0:
+                E[t] = itp.lagrange(int(tr.parent[t]), itp.nodes(t))
+        return ClusterBasis(tr, leaf, E, {t: itp.k for t in range(tr.ncl)})
+
+    V = basis(T, ip, Pp, False)
+    W = basis(TC, ipc, Pc, kernel == KERNEL_DLP) if (kernel == KERNEL_DLP or TC is not T) else V
     gk = KERNEL_SLP if kernel == KERNEL_DLP else kernel
     S = {}
     for (t, s) in blocks.adm:
-        S[(t, s)] = kernel_matrix(gk, ip.nodes(t), ip.nodes(s))
+        S[(t, s)] = kernel_matrix(gk, ip.nodes(t), ipc.nodes(s))
     N = {}
     for (t, s) in blocks.inadm:
         X = Pp[T.begin[t]:T.end[t]]
-        Y = Pp[T.begin[s]:T.end[s]]
-        ny = None if Np is None else Np[T.begin[s]:T.end[s]]
+        Y = Pc[TC.begin[s]:TC.end[s]]
+        ny = None if Np is None else Np[TC.begin[s]:TC.end[s]]
         N[(t, s)] = kernel_matrix(kernel, X, Y, ny)
     if diag == DIAG_ROW_MEAN:
         # row i: mean of g(x_i, x_j) over j != i in the nearfield blocks of row i
@@ -301,7 +308,7 @@ def build_interpolated(tree: ClusterTree, kernel: int, order: int, eta: float,
             if t == s:
                 for i in range(T.begin[t], T.end[t]):
                     M[i - T.begin[t], i - T.begin[t]] = ssum[i] / cnt[i] if cnt[i] > 0 else 0.0
-    return H2Matrix(T, T, blocks, V, W, S, N)
+    return H2Matrix(T, TC, blocks, V, W, S, N)
 
 
 def identity_h2(tree: ClusterTree, eta: float, k: int) -> H2Matrix:

@@ -133,13 +133,22 @@ class ClusterTree:
         return out
 
 
+def dist2_between(tree_r: ClusterTree, t: int, tree_c: ClusterTree, s: int) -> float:
+    """Squared distance of the boxes of cluster t of tree_r and cluster s of
+    tree_c (the same arithmetic as ClusterTree.dist2)."""
+    gap = np.maximum(0.0, np.maximum(tree_r.lo[t] - tree_c.hi[s], tree_c.lo[s] - tree_r.hi[t]))
+    acc = 0.0
+    for g in gap:
+        acc += float(g) * float(g)
+    return acc
+
+
 def admissible(tree_r: ClusterTree, tree_c: ClusterTree, t: int, s: int, eta: float) -> bool:
     """eq. (admissibility): max(diam) <= 2*eta*dist, decided on the squares:
-    max(diam^2) <= (2 eta)^2 dist^2."""
-    if tree_r is not tree_c:
-        raise NotImplementedError
+    max(diam^2) <= (2 eta)^2 dist^2.  Row and column clusters may come from
+    different trees (the index sets I, J, K of the product)."""
     e2 = (2.0 * eta) * (2.0 * eta)
-    return max(tree_r.diam2(t), tree_c.diam2(s)) <= e2 * tree_r.dist2(t, s)
+    return max(tree_r.diam2(t), tree_c.diam2(s)) <= e2 * dist2_between(tree_r, t, tree_c, s)
 
 
 class BlockTree:

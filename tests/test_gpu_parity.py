@@ -183,3 +183,40 @@ def test_handles_released_in_any_order(h2):
     d = C.to_dense(T.n, T.n)
     assert np.isfinite(d).all()
     del A, C, T
+
+
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_rectangular_product_three_trees(h2, ctx, eps):
+    """X (I x J) Y (J x K) on three different point sets."""
+    _say(f"[parity] rectangular eps={eps}")
+    pts = [W.uniform2d(700, 31), W.uniform2d(900, 32), W.uniform2d(500, 33)]
+    Tg = [h2.Tree(ctx, P, 24) for P in pts]
+    To = [O.ClusterTree(P, 24) for P in pts]
+    X = h2.Matrix.interpolated(ctx, Tg[0], Tg[1], h2.KERNEL_NEG_LOG, 4, 0.5)
+    Y = h2.Matrix.interpolated(ctx, Tg[1], Tg[2], h2.KERNEL_NEG_LOG, 4, 0.5)
+    Xo = O.build_interpolated(To[0], O.KERNEL_NEG_LOG, 4, 0.5, cols=To[1])
+    Yo = O.build_interpolated(To[1], O.KERNEL_NEG_LOG, 4, 0.5, cols=To[2])
+    assert np.abs(X.to_dense(Tg[0].n, Tg[1].n) - Xo.to_dense()).max() <= 1e-12 * np.abs(Xo.to_dense()).max()
+    Cg, st = h2.mul(ctx, X, Y, eps)
+    Co, info = O.mul(Xo, Yo, eps)
+    Ex = Xo.to_dense() @ Yo.to_dense()
+    Cd = Cg.to_dense(Tg[0].n, Tg[2].n)
+    Cod = Co.to_dense()
+    blocks, nadm = Cg.blocks()
+    b0, e0, _, _ = Tg[0].clusters()
+    b2, e2, _, _ = Tg[2].clusters()
+    p0, p2 = Tg[0].permutation(), Tg[2].permutation()
+    worst = worst_o = 0.0
+    for i, (t, r) in enumerate(blocks):
+        I, J = p0[b0[t]:e0[t]], p2[b2[r]:e2[r]]
+        ex = Ex[np.ix_(I, J)]
+        if i < nadm:
+            nn = np.linalg.norm(ex, 2)
+            worst = max(worst, np.linalg.norm(ex - Cd[np.ix_(I, J)], 2) / nn)
+            worst_o = max(worst_o, np.linalg.norm(Cod[np.ix_(I, J)] - Cd[np.ix_(I, J)], 2) / nn)
+        else:
+            assert np.abs(ex - Cd[np.ix_(I, J)]).max() <= 1e-11 * np.abs(Ex).max()
+    _say(f"  worst block error {worst:.3e} (eps {eps}), distance to oracle {worst_o:.3e}")
+    assert worst <= eps and worst_o <= 2 * eps
+    x = np.random.default_rng(4).standard_normal(Tg[2].n)
+    assert np.abs(Cg.matvec(x) - Cd @ x).max() <= 1e-12 * np.abs(Cd).sum(axis=1).max() * np.abs(x).max()

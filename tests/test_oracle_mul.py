@@ -231,3 +231,37 @@ def test_incompatible_and_invalid_arguments():
         O.mul(A, A, 0.0)
     with pytest.raises(ValueError):
         O.mul(A, A, 1.5)
+
+
+def test_rectangular_product_three_trees():
+    """X (I x J) times Y (J x K) on three different point sets (the index sets
+    of Section 3): the cross-tree admissibility matches brute force, the
+    block trees partition the index products, and every admissible block of
+    the result meets the bound against the dense product."""
+    P1, P2, P3 = W.uniform2d(300, 21), W.uniform2d(400, 22), W.uniform2d(250, 23)
+    T1, T2, T3 = (O.ClusterTree(P, 20) for P in (P1, P2, P3))
+    # admissibility across trees against a direct box computation
+    for t in range(T1.ncl):
+        for s in range(T2.ncl):
+            gap = np.maximum(0.0, np.maximum(T1.lo[t] - T2.hi[s], T2.lo[s] - T1.hi[t]))
+            d = float(np.sqrt((gap ** 2).sum()))
+            dm = max(float(np.linalg.norm(T1.hi[t] - T1.lo[t])), float(np.linalg.norm(T2.hi[s] - T2.lo[s])))
+            if abs(dm - d) > 1e-9 * max(dm, 1.0):  # away from exact ties
+                assert O.admissible(T1, T2, t, s, 0.5) == (dm <= d)
+    X = O.build_interpolated(T1, O.KERNEL_NEG_LOG, 4, 0.5, cols=T2)
+    Y = O.build_interpolated(T2, O.KERNEL_NEG_LOG, 4, 0.5, cols=T3)
+    for M, A, B in ((X, T1, T2), (Y, T2, T3)):
+        cover = np.zeros((A.n, B.n), dtype=int)
+        for (t, s) in M.blocks.adm + M.blocks.inadm:
+            cover[A.begin[t]:A.end[t], B.begin[s]:B.end[s]] += 1
+        assert (cover == 1).all()
+    Xd, Yd = X.to_dense(), Y.to_dense()
+    K = O.kernel_matrix(O.KERNEL_NEG_LOG, P1, P2)
+    assert np.abs(Xd - K).max() <= 1e-3 * np.abs(K).max()   # interpolation, order 4
+    C, info = O.mul(X, Y, 1e-5)
+    assert C.rows is T1 and C.cols is T3
+    errs = O.block_errors(X, Y, C)
+    assert all(e <= 1e-5 * n for (b, (e, n)) in errs.items() if b in C.blocks.adm)
+    D = C.to_dense()
+    E = Xd @ Yd
+    assert np.linalg.norm(D - E, 2) <= 1e-5 * np.linalg.norm(E, 2) * 10
