@@ -187,10 +187,11 @@ struct Plan {
   int bound_lane = -1;
   uint64_t bound_epoch = 0;
   // HIP graph of the product's launches (captured from the plan's streams).
-  // Kernels read the descriptors from device memory, so eps patches and
-  // re-emission into the same descriptor buffer keep it valid; a new buffer
-  // needs a new capture. Graph runs report overflows in gflag (a kernel
-  // argument fixed in the graph), copied to the job's flag afterwards.
+  // Most kernels read their descriptors from device memory, so eps patches
+  // keep it valid; emit() (new workspace pointers) drops it, because the
+  // conversion kernels take workspace pointers as arguments. Graph runs
+  // report overflows in gflag (a kernel argument fixed in the graph),
+  // copied to the job's flag afterwards.
   hipGraphExec_t gexec = nullptr;
   const void* g_desc = nullptr;
   DevBuf gflag;
@@ -2101,6 +2102,12 @@ static void set_base(Plan& P, char* base) {
 // Descriptors of every step, resolved against the current workspace
 // pointers, uploaded to the device.
 static void emit(Plan& P, double eps) {
+  // a captured graph holds workspace pointers as kernel arguments (the
+  // FP32 -> FP64 conversions): new pointers need a new capture
+  if (P.gexec) {
+    H2_HIP(hipGraphExecDestroy(P.gexec));
+    P.gexec = nullptr;
+  }
   std::vector<char> blob;
   auto align = [&](size_t a) {
     while (blob.size() % a) blob.push_back(0);

@@ -152,3 +152,25 @@ def test_graph_replays_match_eager(h2):
     CB, _ = jobs[1].wait()
     assert np.array_equal(CA.to_dense(T.n, T.n), ref[1e-6])
     assert np.array_equal(CB.to_dense(T2.n, T2.n), refB)
+
+
+def test_graph_recaptured_after_the_arena_moves(h2):
+    """Regression: an FP32-bulk plan replayed from its graph after a larger
+    plan has grown the (single) lane's arena, which re-emits the first plan
+    against the new workspace: the graph is captured again and the results
+    equal the eager ones."""
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, 1)
+    T1 = h2.Tree(ctx, W.uniform2d(1200, 41), 32)
+    A = h2.Matrix.interpolated(ctx, T1, T1, h2.KERNEL_NEG_LOG, 4, 0.5)
+    T2 = h2.Tree(ctx, W.uniform2d(6000, 42), 32)
+    B = h2.Matrix.interpolated(ctx, T2, T2, h2.KERNEL_NEG_LOG, 4, 0.5)
+    f32g = h2.default_options(precision=h2.PREC_FP32_BULK, graph=1)
+    refA = h2.mul(ctx, A, A, 1e-4, h2.default_options(precision=h2.PREC_FP32_BULK))[0].to_dense(T1.n, T1.n)
+    C, st = h2.mul(ctx, A, A, 1e-4, f32g)               # captured on the small arena
+    assert st["prec_used"] == h2.PREC_FP32_BULK
+    assert np.array_equal(C.to_dense(T1.n, T1.n), refA)
+    h2.mul(ctx, B, B, 1e-4, f32g)                        # the arena grows
+    for _ in range(3):
+        C, _ = h2.mul(ctx, A, A, 1e-4, f32g)             # re-emitted: a new capture
+        assert np.array_equal(C.to_dense(T1.n, T1.n), refA)
