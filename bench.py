@@ -341,10 +341,13 @@ def run_c4(h2, args):
 
 def run_serve(h2, args):
     """Serving: a seeded Poisson stream of product requests on resident
-    operands.  Requests are admitted on arrival while fewer than
-    2 x lanes products are in flight (each product's plan is resident, so its
-    memory is known and already held: admission by footprint reduces to the
-    in-flight cap) and overlap on the lanes; latency = result ready - arrival."""
+    operands.  Requests are admitted on arrival while fewer than 2 x lanes
+    products are in flight and overlap on the lanes.  Each product's plan is
+    resident, so its workspace is already held by the lane arenas; a request
+    whose submission still runs out of device memory (its result, or an arena
+    that must grow) waits until products in flight have finished, and is
+    refused only if it fails with none in flight.  Latency = result ready -
+    arrival."""
     from collections import deque
     from paper_2403_01566_amd import workloads as W
     nreq = args.serve_requests + args.serve_warmup
@@ -387,6 +390,8 @@ def run_serve(h2, args):
     pending = deque(reqs)
     inflight = []
     done, refused = [], []
+    refused_reasons = set(rejected_cls.values())
+    memory_waits = 0
     t_start = time.perf_counter()
     while pending or inflight:
         now = time.perf_counter() - t_start
@@ -398,7 +403,16 @@ def run_serve(h2, args):
                 refused.append(r)
                 continue
             A = ops[(r["geometry"], r["m"], r["order"])][1]
-            inflight.append((r, h2.submit(ctx, A, A, r["eps"], options(r["eps"]))))
+            try:
+                inflight.append((r, h2.submit(ctx, A, A, r["eps"], options(r["eps"]))))
+            except h2.H2Error as e:
+                if e.code == h2.H2_ERR_OUT_OF_MEMORY and inflight:
+                    # memory held by products in flight: admit it once some have finished
+                    pending.appendleft(r)
+                    memory_waits += 1
+                    break
+                refused.append(r)
+                refused_reasons.add(str(e))
         still = []
         for r, j in inflight:
             if j.poll():
@@ -434,7 +448,8 @@ def run_serve(h2, args):
         "requests": len(measured),
         "warmup_requests": args.serve_warmup,
         "refused_requests": sum(1 for r in refused if order[id(r)] >= args.serve_warmup),
-        "refused_reasons": sorted(set(rejected_cls.values())),
+        "refused_reasons": sorted(refused_reasons),
+        "admissions_deferred_for_memory": memory_waits,
         "latency_ms": {"p50": pct(0.5), "p99": pct(0.99), "max": lat[-1]},
         "saturated": len(measured) / (t_last - t_first) < 0.9 * args.serve_rate,
         "dtype": "f32+f64",

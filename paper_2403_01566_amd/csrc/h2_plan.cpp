@@ -3178,7 +3178,9 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   } else {
     execute(ctx, L, P, opt.timing, J->tph);
   }
-  // result arrays: one allocation, filled by copies queued behind the product
+  // result arrays: one allocation while the device works, filled by copies
+  // queued behind the product (if it fails, the queued work is waited for
+  // before the job is released)
   auto Cm = std::make_unique<Matrix>();
   Cm->ctx = ctx;
   Cm->hold = ctx->self.lock();
@@ -3192,9 +3194,14 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
                 n_n = P.cnsize, n_r = X->rows->ncl + Y->cols->ncl;
   auto pad = [](int64_t c) { return (std::max<int64_t>(c, 1) + 31) & ~int64_t(31); };
   Cm->bufs.emplace_back(new DevBuf);
-  Cm->bufs.back()->alloc((size_t)(pad(n_vleaf) + pad(n_vtr) + pad(n_wleaf) + pad(n_wtr) + pad(n_s) + pad(n_n) +
-                                  pad(n_r)) *
-                         sizeof(double));
+  try {
+    Cm->bufs.back()->alloc((size_t)(pad(n_vleaf) + pad(n_vtr) + pad(n_wleaf) + pad(n_wtr) + pad(n_s) + pad(n_n) +
+                                    pad(n_r)) *
+                           sizeof(double));
+  } catch (...) {
+    for (hipStream_t q : {LR.l.stream, LR.l.aux[0], LR.l.aux[1]}) (void)hipStreamSynchronize(q);
+    throw;
+  }
   double* carve = Cm->bufs.back()->as<double>();
   auto take = [&](int64_t c) {
     double* d = carve;
