@@ -35,7 +35,7 @@ product.  --sweep LEVELS instead times G*G, G*K and K*K over icosphere levels, a
 --sweep-cube M K*K on the cube surface with m x m squares per face, at eps
 1e-4, and reports time per degree of freedom, storage and error per n.
 
---workload c4 times a batch of 64 independent products submitted at once
+--workload batch64 times a batch of 64 independent products submitted at once
 (overlapping on the context's lanes) against the same products one at a
 time (run it with GPU_MAX_HW_QUEUES=16 in the environment: 4 lanes of 3
 streams each share the default 4 in-order hardware queues otherwise); --serve serves a seeded Poisson stream of requests on resident operands
@@ -61,13 +61,13 @@ FP64_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU (vector F
 ALU_KERNELS = ("qr_kernel", "svd_kernel", "chol_kernel")
 
 WORKLOADS = {
-    "c1": dict(desc="32x32 grid in [0,1]^2, -log|x-y| (diag 0), leaf 32, eta 1/2, Chebyshev order 3 (k=9), "
+    "grid32": dict(desc="32x32 grid in [0,1]^2, -log|x-y| (diag 0), leaf 32, eta 1/2, Chebyshev order 3 (k=9), "
                     "A*A, eps 1e-4",
                eps=1e-4, geom=("grid", 32), kernel=0, leaf=32, order=3, eta=0.5, diag=0, sample=None),
-    "c2": dict(desc="icosphere level 5 (n=20480 centroids), 1/(4 pi |x-y|) (diag = row nearfield mean), leaf 64, "
+    "icosphere5_slp": dict(desc="icosphere level 5 (n=20480 centroids), 1/(4 pi |x-y|) (diag = row nearfield mean), leaf 64, "
                     "eta 1, Chebyshev order 4 (k=64), A*A, eps 1e-6",
                eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1, sample=("ico", 4)),
-    "c3": dict(desc="icosphere level 6 (n=81920 centroids), single layer 1/(4 pi |x-y|) times double layer "
+    "icosphere6_slp_dlp": dict(desc="icosphere level 6 (n=81920 centroids), single layer 1/(4 pi |x-y|) times double layer "
                     "(x-y).n_y/(4 pi |x-y|^3), leaf 64, eta 1, Chebyshev order 4 (k=64), eps 1e-4",
                eps=1e-4, geom=("ico", 6), kernel=1, leaf=64, order=4, eta=1.0, diag=1, dlp=True,
                sample=("ico", 4)),
@@ -147,7 +147,7 @@ def measured_traffic(workload, kernel):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
-COUNTER_FILES = {"c2": "c2_icosphere5"}
+COUNTER_FILES = {"icosphere5_slp": "icosphere5_slp"}
 
 
 def roofline(names, r, steps, workload):
@@ -278,7 +278,7 @@ def sweep(h2, ctx, jobs, steps, eps):
                        "operators": {k: v["desc"] for k, v in SWEEP.items()}}}
 
 
-def run_c4(h2, args):
+def run_batch64(h2, args):
     """Many independent products (64 instances, n log-uniform in [1024, 32768],
     orders 3..6, eps 1e-5, FP32 bulk): all submitted at once and overlapping
     on the context's lanes; one step = one batch.  The same products one after
@@ -467,7 +467,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"])
+    ap.add_argument("--workload", default="icosphere5_slp", choices=sorted(WORKLOADS) + ["batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-global-error", action="store_true",
@@ -504,8 +504,8 @@ def main():
     if args.serve:
         print(json.dumps(run_serve(h2, args)), flush=True)
         return
-    if args.workload == "c4":
-        print(json.dumps(run_c4(h2, args)), flush=True)
+    if args.workload == "batch64":
+        print(json.dumps(run_batch64(h2, args)), flush=True)
         return
     if args.sweep or args.sweep_cube:
         ctx = h2.Context(0)

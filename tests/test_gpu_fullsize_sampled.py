@@ -26,8 +26,8 @@ from paper_2403_01566_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 CASES = {
-    "c2": dict(level=5, kx=1, ky=1, eps=1e-6, prec=0),
-    "c3": dict(level=6, kx=1, ky=2, eps=1e-4, prec=1),
+    "icosphere5_slp": dict(level=5, kx=1, ky=1, eps=1e-6, prec=0),
+    "icosphere6_slp_dlp": dict(level=6, kx=1, ky=2, eps=1e-4, prec=1),
 }
 
 

@@ -29,7 +29,7 @@ def _say(*a):
 
 
 def _case(h2, ctx, case):
-    if case == "c1":
+    if case == "grid32":
         P, nrm, leaf, kern, order, eta, diag = W.grid2d(32), None, 32, 0, 3, 0.5, 0
     elif case == "sphere3":
         (P, nrm), leaf, kern, order, eta, diag = W.icosphere(3), 64, 1, 3, 1.0, 1
@@ -56,7 +56,7 @@ def _check_mv(A, D, x, trans):
     assert np.abs(y - ref).max() <= bound, (np.abs(y - ref).max(), bound)
 
 
-@pytest.mark.parametrize("case", ["c1", "sphere3", "dlp2", "random2d", "tiny"])
+@pytest.mark.parametrize("case", ["grid32", "sphere3", "dlp2", "random2d", "tiny"])
 def test_matvec_against_oracle(h2, ctx, case):
     _say(f"[matvec] {case}")
     T, A, To, Ao = _case(h2, ctx, case)
@@ -72,7 +72,7 @@ def test_matvec_against_oracle(h2, ctx, case):
     assert np.abs(Ao.rmatvec(x1) - A.matvec(x1, trans=True)).max() <= 1e-13 * np.abs(D).sum(axis=0).max()
 
 
-@pytest.mark.parametrize("case,eps", [("c1", 1e-4), ("sphere3", 1e-5), ("dlp2", 1e-4)])
+@pytest.mark.parametrize("case,eps", [("grid32", 1e-4), ("sphere3", 1e-5), ("dlp2", 1e-4)])
 def test_matvec_of_a_product(h2, ctx, case, eps):
     """The result of h2_mul has its own (induced) block tree and bases."""
     _say(f"[matvec product] {case} eps={eps}")
@@ -85,7 +85,7 @@ def test_matvec_of_a_product(h2, ctx, case, eps):
         _check_mv(Cg, Cd, rng.standard_normal((T.n, 3)), trans)
 
 
-@pytest.mark.parametrize("case,eps", [("c1", 1e-4), ("sphere3", 1e-6), ("random2d", 1e-5)])
+@pytest.mark.parametrize("case,eps", [("grid32", 1e-4), ("sphere3", 1e-6), ("random2d", 1e-5)])
 def test_product_error_against_oracle(h2, ctx, case, eps):
     _say(f"[product error] {case} eps={eps}")
     T, A, To, Ao = _case(h2, ctx, case)
@@ -134,7 +134,7 @@ def test_product_error_of_distinct_operands(h2, ctx):
 
 def test_matvec_and_error_paths(h2, ctx):
     _say("[matvec] error paths")
-    T, A, To, Ao = _case(h2, ctx, "c1")
+    T, A, To, Ao = _case(h2, ctx, "grid32")
     x = np.ones(T.n)
     y = np.zeros(T.n)
     xp = x.ctypes.data_as(h2._dp)

@@ -2,7 +2,7 @@
 
 For every case the oracle builds its own trees and operands from the same
 seeded points.  Checked per leaf block b of the result:
-  * the benchmark spec's bound  ||(XY)|_b - C|_b||_2 <= eps ||(XY)|_b||_2  against the
+  * the block-relative bound  ||(XY)|_b - C|_b||_2 <= eps ||(XY)|_b||_2  against the
     exact product of the dense operands;
   * the distance to the oracle's result  ||C|_b - C_oracle|_b||_2 <= 2 eps ||(XY)|_b||_2;
   * inadmissible blocks equal the exact product to rounding.
@@ -37,7 +37,7 @@ def _say(*a):
 
 
 def _geometry(case):
-    if case == "c1":
+    if case == "grid32":
         return dict(P=W.grid2d(32), nrm=None, leaf=32, kern=0, order=3, eta=0.5, diag=0)
     if case == "sphere3":
         P, n = W.icosphere(3)
@@ -101,7 +101,7 @@ def _compare(h2, T, Cg, Ao, Bo, Co, eps, prec=0):
 
 
 CASES = [
-    ("c1", 1e-4, 0),
+    ("grid32", 1e-4, 0),
     ("sphere3", 1e-6, 0),
     ("sphere3", 1e-4, 1),
     ("sphere2dlp", 1e-4, 0),
@@ -150,7 +150,7 @@ def test_repeat_is_bitwise_identical_and_plan_cached(h2, ctx):
 
 def test_error_paths(h2, ctx):
     _say("[parity] error paths")
-    T, A, B, To, Ao, Bo = _build(h2, ctx, "c1")
+    T, A, B, To, Ao, Bo = _build(h2, ctx, "grid32")
     for bad in (0.0, 1.0, -1e-3, float("nan")):
         with pytest.raises(h2.H2Error) as ei:
             h2.mul(ctx, A, A, bad)

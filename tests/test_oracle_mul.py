@@ -11,7 +11,7 @@ from paper_2403_01566_amd import workloads as W
 
 
 def _case(name):
-    if name == "c1":
+    if name == "grid32":
         T = O.ClusterTree(W.grid2d(32), 32)
         A = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
         return T, A, A
@@ -45,7 +45,7 @@ def _run(name, eps):
     return _cache[key]
 
 
-CASES = [("c1", 1e-4), ("sphere", 1e-6), ("slp_dlp", 1e-4), ("random2d", 1e-5)]
+CASES = [("grid32", 1e-4), ("sphere", 1e-6), ("slp_dlp", 1e-4), ("random2d", 1e-5)]
 
 
 @pytest.mark.parametrize("name,eps", CASES)
@@ -143,7 +143,7 @@ def test_error_decomposition_sum():
     """sum over s in desc(t) of the weighted local errors stays below
     eps_r^2 nu^2 / (1 - sigma theta) (Section 5.3): checked through the final
     projection error, which is bounded by that sum."""
-    T, A, B, C, info = _run("c1", 1e-4)
+    T, A, B, C, info = _run("grid32", 1e-4)
     bound = info.tol_r / math.sqrt(1 - 2 * info.theta)
     for b in C.blocks.adm:
         t, r = b
@@ -193,7 +193,7 @@ def test_identity_right_factor():
 
 
 def test_scaling_keeps_ranks():
-    T, A, B, C, info = _run("c1", 1e-4)
+    T, A, B, C, info = _run("grid32", 1e-4)
     A2 = O.build_interpolated(T, O.KERNEL_NEG_LOG, 3, 0.5)
     for k in A2.S:
         A2.S[k] = 3.0 * A2.S[k]
@@ -205,7 +205,7 @@ def test_scaling_keeps_ranks():
 
 
 def test_symmetric_square_gives_symmetric_result():
-    T, A, B, C, info = _run("c1", 1e-4)
+    T, A, B, C, info = _run("grid32", 1e-4)
     D = C.to_dense()
     ref = A.to_dense() @ A.to_dense()
     assert np.linalg.norm(D - D.T, 2) <= 2e-4 * np.linalg.norm(ref, 2)

@@ -8,7 +8,7 @@ import pytest
 import oracle as O
 from paper_2403_01566_amd import workloads as W
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "c1_cluster_tree.txt")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "grid32_cluster_tree.txt")
 
 
 def _golden():
@@ -20,7 +20,7 @@ def _golden():
     return rows
 
 
-def test_c1_tree_closed_form():
+def test_grid32_tree_closed_form():
     T = O.ClusterTree(W.grid2d(32), 32)
     assert T.ncl == 63 and T.depth == 6
     for lev, ncl, px, py, sx, sy, diam in _golden():
@@ -100,8 +100,8 @@ def test_block_tree_invariants(eta):
     assert cover.min() == 1 and cover.max() == 1
 
 
-def test_c1_admissibility_pattern():
-    """With eta = 1/2 on the C1 grid no block at levels 1-2 is admissible, and
+def test_grid32_admissibility_pattern():
+    """With eta = 1/2 on the 32x32 grid no block at levels 1-2 is admissible, and
     at level 3 the admissible pairs are three columns of clusters apart."""
     T = O.ClusterTree(W.grid2d(32), 32)
     bt = O.BlockTree(T, T, 0.5)
