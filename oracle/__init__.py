@@ -11,3 +11,4 @@ from .h2 import (H2Matrix, ClusterBasis, Interp, build_interpolated, identity_h2
                  kernel_matrix, KERNEL_NEG_LOG, KERNEL_SLP, KERNEL_DLP, DIAG_ZERO, DIAG_ROW_MEAN)
 from .mul import mul, recompress, block_errors, basis_products, MulInfo
 from .error import power_norm, product_error
+from .coarsen import agglomerate_sequential
