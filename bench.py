@@ -552,11 +552,17 @@ def main():
         "roofline": roofline(names, r, args.steps, args.workload),
         "phase_ms": {k: v for k, v in zip(["prep", "exact", "leaf", "coarsen", "bases", "-", "couple", "total"],
                                            r["phase"]) if k != "-"},
+        # per kernel: device time per product (events, on the launch's stream),
+        # algorithmic work per product and the rates they give
         "kernels": {names[i]: {"ms_per_step": r["t_k"][i] / args.steps,
                                "launches_per_step": r["cnt"]["launches_kernel"][i],
                                "units_per_step": r["cnt"]["units_kernel"][i],
                                "gflop_per_step": r["cnt"]["flops_kernel"][i] * 1e-9,
-                               "gbyte_per_step": r["cnt"]["bytes_kernel"][i] * 1e-9}
+                               "gbyte_per_step": r["cnt"]["bytes_kernel"][i] * 1e-9,
+                               "achieved_gbs": r["cnt"]["bytes_kernel"][i] * 1e-9
+                               / max(1e-12, r["t_k"][i] / args.steps * 1e-3),
+                               "achieved_tflops": r["cnt"]["flops_kernel"][i] * 1e-12
+                               / max(1e-12, r["t_k"][i] / args.steps * 1e-3)}
                     for i in range(len(names)) if r["cnt"]["launches_kernel"][i]},
         "headline_mode": head,
         "modes": {name: {"products_per_s": args.steps / x["total"],
