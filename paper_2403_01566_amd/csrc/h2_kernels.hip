@@ -307,9 +307,9 @@ __device__ inline int pk(int j, int l, int w) { return j * w - (j * (j - 1)) / 2
 template <int WMAX, int NT>
 __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks, int wlo) {
   constexpr int TPC = NT / WMAX;  // lanes per column
-  constexpr int RPT = 32;         // chunk rows per lane
-  constexpr int CH = RPT * TPC;   // chunk rows
-  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 64, "lanes per column");
+  constexpr int CH = 64;          // chunk rows
+  constexpr int RPT = CH / TPC;   // chunk rows per lane
+  static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 16 && RPT * TPC == CH, "lanes per column");
   __shared__ double R[WMAX * (WMAX + 1) / 2];
   constexpr int VS = RPT + 2;  // padded run per lane: the TPC runs start on different LDS banks
   __shared__ double vb[2][TPC * VS];
@@ -416,9 +416,9 @@ int size_classes(int wmax) { return wmax > 64 ? 3 : (wmax > 32 ? 2 : 1); }
 void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s) {
   if (ntasks <= 0) return;
   // each workgroup exits unless its task's effective width falls into the class
-  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, 0);
-  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 32);
-  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 64);
+  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 0);
+  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 32);
+  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
 }
 
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
 void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, hipStream_t s) {
   if (ntasks <= 0) return;
   if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
-  if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 128>), dim3(ntasks), dim3(128), 0, s, tasks, overflow, 32);
+  if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 32);
   if (cls == 2) hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
 }
 
@@ -1058,9 +1058,9 @@ void launch_scan(const ScanTask* tasks, const int* const* src, int ntasks, hipSt
 
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
-      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 64>",
-      "qr_kernel<64, 128>",        "qr_kernel<128, 256>",    "svd_kernel<32, 64>",
-      "svd_kernel<64, 128>",       "svd_kernel<128, 512>",       "chol_kernel",
+      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 128>",
+      "qr_kernel<64, 256>",        "qr_kernel<128, 512>",    "svd_kernel<32, 64>",
+      "svd_kernel<64, 256>",       "svd_kernel<128, 512>",        "chol_kernel",
       "fill_kernel",               "convert kernels",            "ref_kernel",
       "scan_kernel"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "";

@@ -2439,6 +2439,7 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
     H2_HIP(hipStreamSynchronize(s));
     std::vector<int> stat;
     double svs[3][5] = {{0}};
+    double qrs[3][4] = {{0}};  // per QR class: tasks, sum m, sum w, max m
     size_t stepno = 0;
     for (auto& st : P.steps) {
       ++stepno;
@@ -2469,6 +2470,11 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
             const double m = stat[2 * i], w = stat[2 * i + 1];
             if (w <= 0) continue;
             const int kid = h2k::K_QR32 + (w > 64 ? 2 : (w > 32 ? 1 : 0));
+            double* q = qrs[kid - h2k::K_QR32];
+            q[0] += 1;
+            q[1] += m;
+            q[2] += w;
+            q[3] = std::max(q[3], m);
             P.units_k[kid] += 1;
             P.flops_k[kid] += qr_flops(m, w);
             P.bytes_k[kid] += 8.0 * (m * w + (double)st.qr[i].w * st.qr[i].w);
@@ -2502,6 +2508,11 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
         P.bytes_k[kid] += st.bytes;
       }
     }
+    if (std::getenv("H2_TRACE"))
+      for (int c = 0; c < 3; ++c)
+        if (qrs[c][0] > 0)
+          std::fprintf(stderr, "[h2 qr class %d] tasks %.0f  mean rows %.1f (max %.0f) cols %.1f\n", c, qrs[c][0],
+                       qrs[c][1] / qrs[c][0], qrs[c][3], qrs[c][2] / qrs[c][0]);
     if (std::getenv("H2_TRACE"))
       for (int c = 0; c < 3; ++c)
         if (svs[c][0] > 0)
