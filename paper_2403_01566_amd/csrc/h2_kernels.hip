@@ -538,15 +538,23 @@ __device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot) 
 //
 // Jacobi: M[c * LD + r] holds column c (contiguous rows); the odd stride keeps
 // lanes that read different columns on different LDS banks.
-template <int WMAX, int NT>
-__global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo) {
+//
+// RMAX < WMAX gives the narrow first pass of a size class: LDS for RMAX
+// revealed columns only (two workgroups per CU instead of one) and the
+// reflector re-read from LDS instead of held in registers.  A matrix whose
+// rank reveal would go past RMAX columns is left to the full kernel: the
+// narrow pass writes rank -1, and the full kernel, launched after it with
+// `deferred` set, takes exactly those matrices.
+template <int WMAX, int NT, int RMAX>
+__device__ __forceinline__ void svd_task(const SvdTask& tk, int* overflow, int wlo, int deferred) {
+  constexpr bool NARROW = RMAX < WMAX;
   constexpr int LD = WMAX + 1;
   constexpr int TPC = NT / WMAX;  // lanes per column of A^T in the rank reveal
   constexpr int RPL = WMAX / TPC; // rows per lane
   constexpr int NR = NT / 16;     // DPP rows of the workgroup
   constexpr int NW = NT / 64;     // waves of the workgroup
   static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && NT % 64 == 0, "launch shape");
-  __shared__ double M[WMAX * LD];
+  __shared__ double M[RMAX * LD];
   __shared__ double nrm[WMAX], snrm[WMAX], inv[WMAX];
   __shared__ int order[WMAX];
   constexpr int VS = RPL + 2;  // padded run per lane: the TPC runs start on different LDS banks
@@ -555,7 +563,6 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   __shared__ int widx[NR];
   __shared__ int sh_rot, sh_keep;
   __shared__ double sh_tau, sh_scal;
-  const SvdTask tk = tasks[blockIdx.x];
   const bool sq = tk.w_dev || tk.w_dev2;
   const int we = eff_width(tk.cols, tk.w_dev, tk.w_dev2);
   const int rows = sq ? we : tk.rows;
@@ -564,9 +571,15 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   // another launch handles this size class; the smallest class also takes
   // empty tasks (both children of rank 0), which report rank 0 and zero vectors
   if ((wlo > 0 && wcls <= wlo) || wcls > WMAX) return;
+  if (deferred && *tk.rank != -1) return;  // finished by the narrow pass
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const double ref = tk.tol_ptr ? tk.tol_scale * *tk.tol_ptr : 0.0;
   const bool qr = tk.qrcp && tk.tol_rel == 0.0;
+  if (NARROW && !qr) {  // the whole matrix would go to the Jacobi
+    if (tid == 0) *tk.rank = -1;
+    return;
+  }
+  bool defer = false;
   const int cols_in = cols;
   int sweeps = 0;
   double jthr_scale = 1.0;
@@ -665,6 +678,10 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
           }
         }
         if (tot <= tq * tq) break;
+        if (NARROW && j >= RMAX) {
+          defer = true;
+          break;
+        }
         r = j + 1;
         if (l == p) {  // reflector of the pivot column on rows >= j
           const double xj = group_sum<TPC>(sub == sj ? x[0] : 0.0);
@@ -695,19 +712,31 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
           const double xj = group_sum<TPC>(sub == sj ? x[0] : 0.0);
           double rjl = xj;  // R entry of row j
           if (tau != 0.0) {
-            double w[RPL];
             double d4[4] = {0.0, 0.0, 0.0, 0.0};
+            if constexpr (NARROW) {
 #pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-              w[q] = vb[sub * VS + q];
-              d4[q & 3] += w[q] * x[q];
+              for (int q = 0; q < RPL; ++q) d4[q & 3] += vb[sub * VS + q] * x[q];
+              const double dot = group_sum<TPC>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+              const double full = xj + scal * dot;
+              const double f = tau * scal * full;
+              __asm__ volatile("" ::: "memory");  // read the reflector again: no registers held across the sum
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) x[q] -= f * vb[sub * VS + q];
+              rjl = xj - tau * full;
+            } else {
+              double w[RPL];
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) {
+                w[q] = vb[sub * VS + q];
+                d4[q & 3] += w[q] * x[q];
+              }
+              const double dot = group_sum<TPC>((d4[0] + d4[1]) + (d4[2] + d4[3]));
+              const double full = xj + scal * dot;
+              const double f = tau * scal * full;
+#pragma unroll
+              for (int q = 0; q < RPL; ++q) x[q] -= f * w[q];
+              rjl = xj - tau * full;
             }
-            const double dot = group_sum<TPC>((d4[0] + d4[1]) + (d4[2] + d4[3]));
-            const double full = xj + scal * dot;
-            const double f = tau * scal * full;
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) x[q] -= f * w[q];
-            rjl = xj - tau * full;
           }
           if (sub == 0) M[j * LD + l] = rjl;
           if (sub == sj) x[0] = 0.0;
@@ -725,14 +754,23 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
       jthr_scale = 0.75;
     }
     __syncthreads();
+    if (defer) {  // uniform: every thread took the same break
+      if (tid == 0) *tk.rank = -1;
+      return;
+    }
   }
   if (!empty) {
     // G lanes per pair, at most a DPP row of 16, all pairs of a round at once
     // (2 TPC lanes per pair always fit: at most WMAX / 2 pairs)
     const int npairs = ((cols + 1) & ~1) / 2;
-    if (npairs * 16 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
-    else if (npairs * 8 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 8>(M, rows, cols, &sh_rot);
-    else sweeps = jacobi_sweeps<WMAX, NT, (2 * TPC < 8 ? 2 * TPC : 8)>(M, rows, cols, &sh_rot);
+    if constexpr (NARROW) {
+      static_assert(RMAX / 2 * 16 <= NT, "narrow pass: 16 lanes for every pair");
+      sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
+    } else {
+      if (npairs * 16 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
+      else if (npairs * 8 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 8>(M, rows, cols, &sh_rot);
+      else sweeps = jacobi_sweeps<WMAX, NT, (2 * TPC < 8 ? 2 * TPC : 8)>(M, rows, cols, &sh_rot);
+    }
   }
   if (tk.stat && tid == 0) {
     tk.stat[0] = rows;
@@ -815,11 +853,26 @@ __global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tas
   }
 }
 
+template <int WMAX, int NT>
+__global__ __launch_bounds__(NT) void svd_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo,
+                                                 int deferred) {
+  svd_task<WMAX, NT, WMAX>(tasks[blockIdx.x], overflow, wlo, deferred);
+}
+
+// two workgroups per CU: 4 waves per SIMD at NT = 512, at most 128 VGPRs
+template <int WMAX, int NT, int RMAX>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void svd_narrow_kernel(const SvdTask* __restrict__ tasks, int* overflow, int wlo) {
+  svd_task<WMAX, NT, RMAX>(tasks[blockIdx.x], overflow, wlo, 0);
+}
+
 void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, hipStream_t s) {
   if (ntasks <= 0) return;
-  if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0);
-  if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 32);
-  if (cls == 2) hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
+  if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0, 0);
+  if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 32, 0);
+  if (cls == 2) {  // narrow pass, then the full kernel for the matrices it left (rank -1)
+    hipLaunchKernelGGL((svd_narrow_kernel<128, 512, 64>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
+    hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64, 1);
+  }
 }
 
 void launch_svd(const SvdTask* tasks, int ntasks, int wmax, int* overflow, hipStream_t s) {
@@ -1060,7 +1113,7 @@ const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
       "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 128>",
       "qr_kernel<64, 256>",        "qr_kernel<128, 512>",    "svd_kernel<32, 64>",
-      "svd_kernel<64, 256>",       "svd_kernel<128, 512>",        "chol_kernel",
+      "svd_kernel<64, 256>",       "svd_narrow_kernel<128, 512, 64> + svd_kernel<128, 512>",       "chol_kernel",
       "fill_kernel",               "convert kernels",            "ref_kernel",
       "scan_kernel"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "";
