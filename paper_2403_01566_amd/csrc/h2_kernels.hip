@@ -869,9 +869,14 @@ void launch_svd_class(const SvdTask* tasks, int ntasks, int cls, int* overflow, 
   if (ntasks <= 0) return;
   if (cls == 0) hipLaunchKernelGGL((svd_kernel<32, 64>), dim3(ntasks), dim3(64), 0, s, tasks, overflow, 0, 0);
   if (cls == 1) hipLaunchKernelGGL((svd_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, overflow, 32, 0);
-  if (cls == 2) {  // narrow pass, then the full kernel for the matrices it left (rank -1)
-    hipLaunchKernelGGL((svd_narrow_kernel<128, 512, 64>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
-    hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64, 1);
+  if (cls == 2) {
+    // Narrow pass, then the full kernel for the matrices it left (rank -1).
+    // A launch of fewer matrices leaves CUs idle anyway; there the narrow
+    // pass would only repeat the rank reveal of the matrices it defers.
+    const bool narrow = ntasks >= 1024;
+    if (narrow)
+      hipLaunchKernelGGL((svd_narrow_kernel<128, 512, 64>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64);
+    hipLaunchKernelGGL((svd_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, overflow, 64, narrow ? 1 : 0);
   }
 }
 

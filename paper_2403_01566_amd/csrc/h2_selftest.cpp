@@ -191,7 +191,11 @@ double svd_empty_test(hipStream_t s, int* overflow) {
   return err;
 }
 
-double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0, double decades = 10.0) {
+// copies > 1: the same matrix as `copies` tasks of one launch, each with its
+// own outputs (a launch that large takes the narrow first pass of the widest
+// class); the first copy is checked as above and every other copy must
+// reproduce its outputs exactly.
+double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0, double decades = 10.0, int copies = 1) {
   std::vector<void*> keep;
   Lcg g(7 + w);
   // A = U diag(sig) V^T with decaying singular values, formed densely
@@ -221,21 +225,34 @@ double svd_test(hipStream_t s, int w, int* overflow, int qrcp = 0, double decade
     for (int j = 0; j < w; ++j)
       for (int q = 0; q < w; ++q) A[(size_t)i * w + j] += X[(size_t)i * w + q] * sig[q] * Y[(size_t)j * w + q];
   double* da = up(A, keep);
-  std::vector<double> U0((size_t)w * w, 0.0), S0(w, 0.0);
+  const size_t nu = (size_t)w * w;
+  std::vector<double> U0(nu * copies, 0.0), S0((size_t)w * copies, 0.0);
   double* du = up(U0, keep);
   double* ds = up(S0, keep);
-  std::vector<int> rk0(1, 0);
+  std::vector<int> rk0(copies, 0);
   int* dk = up(rk0, keep);
   const double tau = 1e-5;
-  h2k::SvdTask t{da, du, nullptr, ds, dk, nullptr, nullptr, nullptr, nullptr, nullptr, qrcp ? tau : 0.0, qrcp ? 0.0 : 1e-6, 0.0,
-                 w, w, w, w, w, 0, qrcp, 1, 0, qrcp};
-  auto* dt = up(std::vector<h2k::SvdTask>{t}, keep);
-  h2k::launch_svd(dt, 1, w, overflow, s);
+  std::vector<h2k::SvdTask> tv;
+  for (int c = 0; c < copies; ++c)
+    tv.push_back(h2k::SvdTask{da, du + nu * c, nullptr, ds + (size_t)w * c, dk + c, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, qrcp ? tau : 0.0, qrcp ? 0.0 : 1e-6, 0.0,
+                              w, w, w, w, w, 0, qrcp, 1, 0, qrcp});
+  auto* dt = up(tv, keep);
+  h2k::launch_svd(dt, copies, w, overflow, s);
   H2_HIP(hipStreamSynchronize(s));
-  auto U = down(du, U0.size());
-  auto S = down(ds, S0.size());
-  auto rk = down(dk, 1);
+  auto Uall = down(du, U0.size());
+  auto Sall = down(ds, S0.size());
+  auto rkall = down(dk, copies);
+  std::vector<double> U(Uall.begin(), Uall.begin() + nu), S(Sall.begin(), Sall.begin() + w);
+  std::vector<int> rk(rkall.begin(), rkall.begin() + 1);
   double err = 0;
+  for (int c = 1; c < copies; ++c) {
+    if (rkall[c] != rk[0]) err = 1.0;
+    for (size_t e = 0; e < nu; ++e)
+      if (Uall[nu * c + e] != U[e]) err = 1.0;
+    for (int i = 0; i < w; ++i)
+      if (Sall[(size_t)w * c + i] != S[i]) err = 1.0;
+  }
   if (qrcp) {
     const int k = rk[0];
     for (int a = 0; a < k; ++a)
@@ -353,6 +370,12 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(chol_test(s, 32, 300));
   e.push_back(chol_test(s, 50, 400));
   e.push_back(svd_empty_test(s, overflow));
+  // launches of 1024 matrices: the narrow first pass of the 128-wide class
+  // finishes the short rank, defers the full one at 64 columns and the
+  // relative-threshold form at once
+  e.push_back(svd_test(s, 100, overflow, 1, 30.0, 1024));
+  e.push_back(svd_test(s, 128, overflow, 1, 10.0, 1024));
+  e.push_back(svd_test(s, 128, overflow, 0, 10.0, 1024));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
   return (int)e.size();
 }
