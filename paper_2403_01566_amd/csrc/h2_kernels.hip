@@ -283,6 +283,26 @@ __device__ inline int dpp_mov_int(int v) {
   return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
 }
 
+// Reciprocal and reciprocal square root from the hardware approximations
+// (v_rcp_f64, v_rsq_f64), each refined by two Newton steps (the error
+// squares per step): a short dependent chain in place of the compiler's
+// correctly rounded division and square root, for the Jacobi rotations.
+// Arguments are normal and positive (rsq) or nonzero (rcp) where used.
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  double h = 0.5 * x * y;
+  y = fma(y, fma(-h, y, 0.5), y);  // y (3 - x y^2) / 2
+  h = 0.5 * x * y;
+  y = fma(y, fma(-h, y, 0.5), y);
+  return y;
+}
+
 // ---------------------------------------------------------------------------
 // Streaming Householder QR (R only), one workgroup per matrix.
 // ---------------------------------------------------------------------------
@@ -500,9 +520,14 @@ __device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot) 
         b = dpp_group_sum(b, G);
         c = dpp_group_sum(c, G);
         if (c != 0.0 && c * c > 1e-30 * (a * b)) {
-          const double zeta = (b - a) / (2.0 * c);
-          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          // tan of the rotation angle: sign(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+          // zeta = (b - a) / 2c; c^2 > 0 keeps 2c normal.  Above 1e150,
+          // sqrt(1 + zeta^2) is |zeta| in FP64 (and zeta^2 may overflow).
+          const double zeta = (b - a) * rcp_nr(2.0 * c);
+          const double az = fabs(zeta), u = 1.0 + zeta * zeta;
+          const double root = az > 1e150 ? az : u * rsq_nr(u);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) * rcp_nr(az + root);
+          const double cs = rsq_nr(1.0 + t * t), sn = cs * t;
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             const int r = gl + k * G;
