@@ -61,6 +61,11 @@ class MulInfo:
         self.coarse = {}         # b -> (U'_b, Z'_b, sigma_kappa)
         self.row_sv = {}         # cluster -> singular values of weighted matrix
         self.col_sv = {}
+        # (cluster s, block b) -> (spectral, Frobenius) norm of the part of
+        # the unweighted piece G^_{s,b} that the truncation at s drops,
+        # ||(I - V^_s V^_s^*) G^_{s,b}|| (the local errors of Section 5.3)
+        self.row_local = {}
+        self.col_local = {}
         self.counts = defaultdict(int)
         self.induced_P = []      # (t, r, [s]) for every visited node with P_tr non-empty
 
@@ -231,7 +236,7 @@ def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
         raise ValueError("theta must satisfy theta < 1/sigma")
     scale = math.sqrt(1.0 - sigma_br * th)
 
-    def build_basis(T, blocks_of, piece, lvl_block, tol, sv_store):
+    def build_basis(T, blocks_of, piece, lvl_block, tol, sv_store, local):
         """blocks_of(s): adm result leaves whose cluster on this side is s;
         piece(b): condensed block (rows = that cluster's indices)."""
         leaf, transfer, rank, proj = {}, {}, {}, {}
@@ -275,6 +280,8 @@ def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
                     a = lvl_block(b)
                     pc = piece(b)[_sub(T, a, s):_sub(T, a, s) + T.size(s)]
                     proj[(s, b)] = Vs.T @ pc
+                    d = pc - Vs @ proj[(s, b)]
+                    local[(s, b)] = (float(np.linalg.norm(d, 2)) if d.size else 0.0, float(np.linalg.norm(d)))
             else:
                 off = 0
                 for c in T.children[s]:
@@ -283,6 +290,8 @@ def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
                 for b in bl:
                     stacked = np.vstack([proj[(c, b)] for c in T.children[s]])
                     proj[(s, b)] = Vs.T @ stacked
+                    d = stacked - Vs @ proj[(s, b)]
+                    local[(s, b)] = (float(np.linalg.norm(d, 2)) if d.size else 0.0, float(np.linalg.norm(d)))
         return ClusterBasis(T, leaf, transfer, rank), proj
 
     row_blocks = defaultdict(list)
@@ -292,9 +301,10 @@ def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
         col_blocks[b[1]].append(b)
     tol_r = dr * scale
     tol_w = dw * scale
-    Vc, projV = build_basis(TI, row_blocks, lambda b: coarse[b][0], lambda b: b[0], tol_r, info.row_sv)
+    Vc, projV = build_basis(TI, row_blocks, lambda b: coarse[b][0], lambda b: b[0], tol_r, info.row_sv,
+                            info.row_local)
     Wc, projW = build_basis(TK, col_blocks, lambda b: coarse[b][1] * coarse[b][2], lambda b: b[1],
-                            tol_w, info.col_sv)
+                            tol_w, info.col_sv, info.col_local)
 
     # ---------------- coupling matrices (Section 5.2) ----------------
     S = {}
@@ -306,6 +316,7 @@ def _recompress(TI, TK, TC, finals, near, eps, theta, budget, info):
     info.counts["adm_blocks"] = len(TC.adm)
     info.counts["inadm_blocks"] = len(TC.inadm)
     info.theta, info.tol_r, info.tol_w, info.delta_c = th, tol_r, tol_w, dc
+    info.sigma_br = sigma_br
     return C, info
 
 

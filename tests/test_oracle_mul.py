@@ -139,18 +139,59 @@ def test_row_and_column_projection_errors(name, eps):
         assert ec <= eps / 4 * nu * (1 + 1e-8)
 
 
-def test_error_decomposition_sum():
-    """sum over s in desc(t) of the weighted local errors stays below
-    eps_r^2 nu^2 / (1 - sigma theta) (Section 5.3): checked through the final
-    projection error, which is bounded by that sum."""
-    T, A, B, C, info = _run("grid32", 1e-4)
-    bound = info.tol_r / math.sqrt(1 - 2 * info.theta)
-    for b in C.blocks.adm:
-        t, r = b
-        Uc, Zc, sk = info.coarse[b]
-        Vt = C.V.full(t)
-        e = np.linalg.norm(Uc - Vt @ (Vt.T @ Uc), 2)
-        assert e <= bound * info.nu[b] * (1 + 1e-8)
+@pytest.mark.parametrize("name,eps", CASES)
+def test_error_decomposition_sum(name, eps):
+    """Section 5.3's error decomposition, formed per descendant.  For every
+    admissible block b = (t, r) and every cluster s in desc(t) (t included)
+    let e_{s,b} be the part of the unweighted piece G^_{s,b} dropped by the
+    truncation at s (recorded by the oracle).  Then
+      (a) e_{s,b} <= omega_{s,b} eps_r with omega_{s,b} = theta^{(level s -
+          level t)/2} nu_b (the weighted SVD truncation keeps every dropped
+          singular value of the weighted matrix below eps_r);
+      (b) sum_{s in desc(t)} e_{s,b}^2 <= eps_r^2 nu_b^2 / (1 - sigma theta);
+      (c) in the Frobenius norm the decomposition is exact: the projection
+          error ||G~_b - V_t V_t^* G~_b||_F^2 equals sum_s ||.||_F^2 of the
+          local errors (the nested isometric bases make the terms orthogonal);
+      (d) in the spectral norm it is an upper bound of that projection error.
+    Both sides, rows and (on the adjoint) columns."""
+    T, A, B, C, info = _run(name, eps)
+    th, sg = info.theta, info.sigma_br
+
+    def desc(t):
+        out, stack = [], [t]
+        while stack:
+            s = stack.pop()
+            out.append(s)
+            stack.extend(T.children[s])
+        return out
+
+    checked = 0
+    for side in ("row", "col"):
+        local = info.row_local if side == "row" else info.col_local
+        tol = info.tol_r if side == "row" else info.tol_w
+        for b in C.blocks.adm:
+            nu = info.nu[b]
+            if nu == 0.0 or info.kappa[b] == 0:
+                continue
+            t = b[0] if side == "row" else b[1]
+            Uc, Zc, sk = info.coarse[b]
+            G = Uc @ Zc.T if side == "row" else Zc @ Uc.T   # G~_b = U'_b Z'_b^*, or its adjoint
+            V = C.V.full(t) if side == "row" else C.W.full(t)
+            P = G - V @ (V.T @ G)
+            s2 = f2 = 0.0
+            for s in desc(t):
+                e_spec, e_frob = local[(s, b)]
+                w = th ** ((T.level[s] - T.level[t]) / 2.0) * nu
+                assert e_spec <= w * tol * (1 + 1e-9) + 1e-14 * nu, (side, b, s)      # (a)
+                s2 += e_spec ** 2
+                f2 += e_frob ** 2
+            assert s2 <= tol ** 2 * nu ** 2 / (1.0 - sg * th) * (1 + 1e-9)          # (b)
+            pf = np.linalg.norm(P)
+            # (rounding: P is a difference of terms of size nu)
+            assert abs(pf - math.sqrt(f2)) <= 1e-6 * math.sqrt(f2) + 1e-12 * nu, (side, b)   # (c)
+            assert np.linalg.norm(P, 2) <= math.sqrt(s2) * (1 + 1e-6) + 1e-12 * nu          # (d)
+            checked += 1
+    assert checked > 0
 
 
 def test_lemma6_product_admissibility():
