@@ -328,7 +328,7 @@ def run_batch64(h2, args):
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32+f64",
-        "data": "synthetic (seeded uniform points, operands built by interpolation on the device)",
+        "data": "synthetic (seeded uniform points, operands built by interpolation on the host, resident on the device)",
         "config": {"workload": "64 products A_i A_i, n_i log-uniform in [1024, 32768] (PCG64 seed 2403), uniform "
                                "points in [0,1]^2, -log|x-y|, Chebyshev order 3..6, leaf 32 (order <= 4) or 64, "
                                "eta 1/2, eps 1e-5, FP32 bulk", "lanes": args.lanes, "total_n": sum(T.n for T, _ in ops),
@@ -544,7 +544,7 @@ def main():
         "scaling": "strong",
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "fp32_bulk" else "f64",
-        "data": "synthetic (seeded geometry, operands built by interpolation on the device)",
+        "data": "synthetic (seeded geometry, operands built by interpolation on the host, resident on the device)",
         "config": {"workload": cfg["desc"], "n": int(T.n), "eps": eps, "n_adm": st["n_adm"],
                    "n_inadm": st["n_inadm"], "rank_max": [st["rank_max_row"], st["rank_max_col"]]},
         "latency_ms": {"p50": p50, "p99": p99},

@@ -6,7 +6,8 @@
  * the admissibility condition, with isometric nested row and column bases
  * (Section 5.2) chosen adaptively so that every admissible block b satisfies
  * ||(XY)|_b - C|_b||_2 <= eps ||(XY)|_b||_2 (Section 5.3, block-relative error
- * control).  Inadmissible blocks are stored exactly.
+ * control).  Inadmissible blocks are the exact product up to FP64 rounding
+ * (with the FP32 bulk: up to the FP32 rounding of the exact product).
  *
  * Conventions
  *  - Every call returns h2_status; no exception crosses the ABI.  On failure
@@ -37,7 +38,7 @@ typedef enum {
   H2_ERR_DEVICE = 3,        /* HIP error (message holds the HIP string) */
   H2_ERR_INCOMPATIBLE = 4,  /* X's column tree is not Y's row tree */
   H2_ERR_TOO_LARGE = 5,     /* size above a documented limit (rank cap, dense size) */
-  H2_ERR_NOT_CONVERGED = 6  /* reserved */
+  H2_ERR_NOT_CONVERGED = 6  /* a Jacobi SVD of a truncation still rotated after its sweep cap */
 } h2_status;
 
 typedef struct h2_context_s* h2_context;
@@ -115,6 +116,10 @@ typedef struct {
                           first such call for the plan and replayed afterwards (fewer
                           launch gaps for small products); needs timing = 0. 0: launch
                           every kernel from the host.                                    */
+  int jacobi_sweeps;   /* sweep cap of the one-sided Jacobi SVDs (0 => 40).  A truncation
+                          whose Jacobi still rotates after the cap makes the product fail
+                          with H2_ERR_NOT_CONVERGED instead of returning vectors that are
+                          not singular vectors.                                          */
 } h2_mul_options;
 
 /* Number of kernels in the per-kernel statistics; h2_kernel_name(i) names kernel i. */
@@ -148,7 +153,10 @@ typedef struct {
   double bytes_kernel[H2_NKERNEL];
 } h2_mul_stats;
 
-/* Default options (all fields as documented above). */
+/* Default options (all fields as documented above).  h2_mul and h2_mul_submit
+ * reject (INVALID_ARG) a budget that is negative or not finite, resolved
+ * budgets (0 => 1/4) summing above 1, theta outside [0, 1/sigma), a negative
+ * jacobi_sweeps. */
 void h2_mul_default_options(h2_mul_options* opt);
 
 /* Name of kernel i of the per-kernel statistics (the kernel's template
@@ -166,7 +174,10 @@ h2_status h2_mul(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_
                  h2_matrix* C, h2_mul_stats* stats);
 
 /* Dense matrix (rows x cols, row-major, leading dimension ld >= cols, original
- * index order), for small cases: rows*cols <= 2^26, else TOO_LARGE. */
+ * index order) of an H2-matrix as Definition 4 defines it: V_t S_b W_s^* on
+ * every admissible leaf b = (t,s) (V_t, W_s expanded from the leaf bases and
+ * transfer matrices) and the stored nearfield block on every inadmissible
+ * leaf.  For small cases only: rows*cols <= 2^26, else TOO_LARGE. */
 h2_status h2_to_dense(h2_matrix M, double* out, int64_t ld);
 
 /* One leaf block of M as dense: block index b in [0, n_adm + n_inadm) (first
@@ -259,6 +270,46 @@ h2_status h2_matrix_info(h2_matrix M, int64_t* n_adm, int64_t* n_inadm, int* kca
 h2_status h2_matrix_blocks(h2_matrix M, int* pairs);
 /* Ranks of the row and column cluster bases (nclusters entries each). */
 h2_status h2_matrix_ranks(h2_matrix M, int* row_ranks, int* col_ranks);
+/* Packed arrays of an H2-matrix (Definition 4: leaf bases, transfer matrices,
+ * coupling matrices of the admissible leaves, dense nearfield of the
+ * inadmissible leaves), copied to host memory, e.g. to check that the row and
+ * column bases of a product are isometric and nested (Section 5.2).
+ * All arrays are row-major, rows in tree order (cluster t covers positions
+ * begin(t) .. end(t)-1, see h2_tree_clusters), coefficients padded to kc:
+ *   v_leaf      n_rows x kc.  For a leaf cluster t, rows begin(t)..end(t)-1
+ *               hold V_t; columns k_t .. kc-1 are zero (k_t = rank_row[t]).
+ *   v_transfer  ncl_rows x kc x kc.  Entry t holds E_t (k_t x k_parent in its
+ *               top left corner, zero elsewhere): V_parent restricted to t's
+ *               rows equals V_t E_t.  The root's entry is zero.
+ *   w_leaf, w_transfer   the same for the column basis (W, F; rank_col).
+ *   couplings   n_adm x kc x kc: S_b (k_t x k_s in its top left corner) of
+ *               admissible leaf b in the order of h2_matrix_blocks.
+ *   near        near_size doubles: inadmissible leaf i's |t| x |s| block at
+ *               offset near_offset[i] (n_inadm + 1 offsets, the last one is
+ *               near_size).
+ *   rank_row, rank_col   ncl_rows / ncl_cols ranks.
+ * The call always fills the size fields; it copies every array whose pointer
+ * is not NULL (caller-allocated with the sizes above), so a first call with
+ * all pointers NULL learns the sizes.  Synchronous (waits for the context's
+ * device work).  Errors: INVALID_ARG (null M or view), DEVICE. */
+typedef struct {
+  int64_t n_rows, n_cols;  /* filled: points of the row and column trees */
+  int ncl_rows, ncl_cols;  /* filled: clusters of the row and column trees */
+  int kc;                  /* filled: padded rank of every coefficient array */
+  int64_t n_adm, n_inadm;  /* filled: admissible and inadmissible leaves */
+  int64_t near_size;       /* filled: doubles of the packed nearfield */
+  double* v_leaf;
+  double* v_transfer;
+  double* w_leaf;
+  double* w_transfer;
+  double* couplings;
+  double* near;
+  int64_t* near_offset;
+  int* rank_row;
+  int* rank_col;
+} h2_host_view;
+h2_status h2_export_host(h2_matrix M, h2_host_view* view);
+
 /* Storage of M in bytes (bases, transfers, couplings, nearfield). */
 h2_status h2_matrix_storage(h2_matrix M, int64_t* bytes);
 void h2_matrix_destroy(h2_matrix M);

@@ -399,6 +399,48 @@ h2_status h2_matrix_ranks(h2_matrix M, int* row_ranks, int* col_ranks) {
   });
 }
 
+h2_status h2_export_host(h2_matrix M, h2_host_view* view) {
+  return guard([&] {
+    require(M && view, "null argument");
+    const auto& m = *M->m;
+    const auto& R = *m.rows;
+    const auto& C = *m.cols;
+    const int kc = m.kc;
+    view->n_rows = R.n;
+    view->n_cols = C.n;
+    view->ncl_rows = R.ncl;
+    view->ncl_cols = C.ncl;
+    view->kc = kc;
+    view->n_adm = (int64_t)m.bt.adm.size();
+    view->n_inadm = (int64_t)m.bt.inadm.size();
+    view->near_size = m.nsize;
+    H2_HIP(hipSetDevice(m.ctx->device));
+    H2_HIP(hipStreamSynchronize(m.ctx->stream));
+    auto get = [](double* dst, const double* src, int64_t count) {
+      if (dst && count > 0) H2_HIP(hipMemcpy(dst, src, count * sizeof(double), hipMemcpyDeviceToHost));
+    };
+    const int64_t kk = (int64_t)kc * kc;
+    get(view->v_leaf, m.V.leaf, R.n * kc);
+    get(view->w_leaf, m.W.leaf, C.n * kc);
+    get(view->v_transfer, m.V.transfer, R.ncl * kk);
+    get(view->w_transfer, m.W.transfer, C.ncl * kk);
+    get(view->couplings, m.S, view->n_adm * kk);
+    get(view->near, m.N, m.nsize);
+    // the root has no parent: its transfer slot is never written
+    for (int t = 0; t < R.ncl; ++t)
+      if (view->v_transfer && R.parent[t] < 0) std::memset(view->v_transfer + t * kk, 0, kk * sizeof(double));
+    for (int t = 0; t < C.ncl; ++t)
+      if (view->w_transfer && C.parent[t] < 0) std::memset(view->w_transfer + t * kk, 0, kk * sizeof(double));
+    if (view->near_offset) {
+      for (int64_t i = 0; i < view->n_inadm; ++i) view->near_offset[i] = m.noff[i];
+      view->near_offset[view->n_inadm] = m.nsize;
+    }
+    // interpolated operands have the full rank kc on every cluster
+    for (int t = 0; t < R.ncl && view->rank_row; ++t) view->rank_row[t] = m.rank_row.empty() ? kc : m.rank_row[t];
+    for (int t = 0; t < C.ncl && view->rank_col; ++t) view->rank_col[t] = m.rank_col.empty() ? kc : m.rank_col[t];
+  });
+}
+
 h2_status h2_matrix_storage(h2_matrix M, int64_t* bytes) {
   return guard([&] {
     require(M && bytes, "null argument");

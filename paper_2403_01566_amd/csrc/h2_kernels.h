@@ -102,7 +102,13 @@ struct SvdTask {
   // 3 tau / 4.  The projection error of the result stays <= tau; sigma holds
   // the singular values of the factor (within tau/8 of those of A).
   int qrcp;
+  // Jacobi sweep cap (0 => 40).  A Jacobi that still rotates after the cap
+  // sets bit kOvfNotConverged in *overflow.
+  int maxsw;
 };
+// Overflow-word bit of a Jacobi that did not converge within its sweep cap
+// (bits 1 and 2 are the rank-cap overflows of the coarsening and the bases).
+constexpr int kOvfNotConverged = 4;
 
 // Lower bound of a block norm from factors of its pieces: for every group,
 // out = factor * max over its matrices of the largest row or column norm

@@ -473,10 +473,10 @@ __device__ inline double group_sum(double v) {
 // cols) with round-robin pair ordering.  The G consecutive lanes of a group
 // share a pair: each lane keeps its K rows of both columns in registers
 // between the three dot products and the rotation.  One barrier per round.
-// Returns the number of sweeps (at most 40; the last one without rotations
-// unless the cap was reached).
+// Returns the number of sweeps (at most maxsw; the last one without rotations
+// unless the cap was reached: then *sh_rot is still set on return).
 template <int WMAX, int NT, int G>
-__device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot) {
+__device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot, int maxsw) {
   constexpr int LD = WMAX + 1;
   constexpr int K = (WMAX + G - 1) / G;
   const int tid = threadIdx.x;
@@ -484,7 +484,7 @@ __device__ inline int jacobi_sweeps(double* M, int rows, int cols, int* sh_rot) 
   const int npairs = np / 2, m1 = np - 1;
   const int grp = tid / G, gl = tid % G;
   int sweeps = 0;
-  for (int sweep = 0; sweep < 40 && np > 1; ++sweep) {
+  for (int sweep = 0; sweep < maxsw && np > 1; ++sweep) {
     if (tid == 0) *sh_rot = 0;
     __syncthreads();
     for (int rnd = 0; rnd < m1; ++rnd) {
@@ -788,14 +788,18 @@ __device__ __forceinline__ void svd_task(const SvdTask& tk, int* overflow, int w
     // G lanes per pair, at most a DPP row of 16, all pairs of a round at once
     // (2 TPC lanes per pair always fit: at most WMAX / 2 pairs)
     const int npairs = ((cols + 1) & ~1) / 2;
+    const int maxsw = tk.maxsw > 0 ? tk.maxsw : 40;
     if constexpr (NARROW) {
       static_assert(RMAX / 2 * 16 <= NT, "narrow pass: 16 lanes for every pair");
-      sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
+      sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot, maxsw);
     } else {
-      if (npairs * 16 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot);
-      else if (npairs * 8 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 8>(M, rows, cols, &sh_rot);
-      else sweeps = jacobi_sweeps<WMAX, NT, (2 * TPC < 8 ? 2 * TPC : 8)>(M, rows, cols, &sh_rot);
+      if (npairs * 16 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 16>(M, rows, cols, &sh_rot, maxsw);
+      else if (npairs * 8 <= NT) sweeps = jacobi_sweeps<WMAX, NT, 8>(M, rows, cols, &sh_rot, maxsw);
+      else sweeps = jacobi_sweeps<WMAX, NT, (2 * TPC < 8 ? 2 * TPC : 8)>(M, rows, cols, &sh_rot, maxsw);
     }
+    // still rotating after the cap: the columns are not yet orthogonal, so
+    // they are not singular vectors (read after the last round's barrier)
+    if (sweeps >= maxsw && cols > 1 && sh_rot && tid == 0 && overflow) atomicOr(overflow, kOvfNotConverged);
   }
   if (tk.stat && tid == 0) {
     tk.stat[0] = rows;

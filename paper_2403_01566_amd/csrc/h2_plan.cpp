@@ -216,6 +216,7 @@ struct Plan {
   double theta = 0.25, sigma_br = 2.0;
   int qrcp = 1;  // pivoted-QR rank reveal before the Jacobi (square SVDs)
   double budget[3] = {0.25, 0.25, 0.25};
+  int sweeps = 40;  // Jacobi sweep cap of the SVD descriptors
   int64_t launches = 0;
   int max_coarse_K = 0;
   // per kernel (h2k::KernelId): device ms, launches; algorithmic units, flops, bytes
@@ -1829,6 +1830,7 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     v[i].stat = P.wi + st.stat_off + 4 * i;
     v[i].urows = s.urows;
     v[i].qrcp = P.qrcp;
+    v[i].maxsw = P.sweeps;
     v[i].sigma = res(s.sigma, P);
     v[i].rank = res(s.rank, P);
     v[i].tol_abs = 0.0;
@@ -2246,8 +2248,40 @@ static void bind(Context* ctx, Plan& P, int lane, double eps) {
   }
 }
 
-static void set_eps(Plan& P, double eps) {
-  if (P.eps_set == eps) return;
+// Resolved tolerance settings of a product: error budgets (fractions of eps
+// for coarsening, rows, columns) and the Jacobi sweep cap.
+struct Tol {
+  double budget[3];
+  int sweeps;
+};
+
+static Tol resolve_tol(const h2_mul_options& opt) {
+  Tol t;
+  const double b[3] = {opt.budget_coarse, opt.budget_row, opt.budget_col};
+  double sum = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    if (!std::isfinite(b[i]) || b[i] < 0.0) throw Error(H2_ERR_INVALID_ARG, "error budgets must be finite and >= 0");
+    t.budget[i] = b[i] > 0.0 ? b[i] : 0.25;
+    sum += t.budget[i];
+  }
+  if (sum > 1.0 + 1e-12) throw Error(H2_ERR_INVALID_ARG, "error budgets sum above 1");
+  if (opt.jacobi_sweeps < 0) throw Error(H2_ERR_INVALID_ARG, "jacobi_sweeps below 0");
+  if (!std::isfinite(opt.theta) || opt.theta < 0.0) throw Error(H2_ERR_INVALID_ARG, "theta must be finite and >= 0");
+  t.sweeps = opt.jacobi_sweeps > 0 ? opt.jacobi_sweeps : 40;
+  return t;
+}
+
+static bool tol_differs(const Plan& P, double eps, const Tol& t) {
+  return P.eps_set != eps || P.sweeps != t.sweeps || P.budget[0] != t.budget[0] || P.budget[1] != t.budget[1] ||
+         P.budget[2] != t.budget[2];
+}
+
+// Patches the descriptors that depend on eps, the budgets or the sweep cap
+// (SVD thresholds, block-norm scales) in place on the device.
+static void set_tolerances(Plan& P, double eps, const Tol& t) {
+  if (!tol_differs(P, eps, t)) return;
+  for (int i = 0; i < 3; ++i) P.budget[i] = t.budget[i];
+  P.sweeps = t.sweeps;
   for (auto& st : P.steps)
     if (st.kind == SK_SVD) {
       resolve_svd(P, st, P.hdesc, eps, true);
@@ -2266,6 +2300,12 @@ static void set_eps(Plan& P, double eps) {
                          hipMemcpyHostToDevice));
     }
   P.eps_set = eps;
+}
+
+// Overflow word of a finished product -> error.
+static void check_overflow_bits(int ovf) {
+  if (ovf & h2k::kOvfNotConverged)
+    throw Error(H2_ERR_NOT_CONVERGED, "a Jacobi SVD still rotated after its sweep cap (raise jacobi_sweeps)");
 }
 
 // Algorithmic flops of a Householder QR (R only) of an m x w matrix.
@@ -2585,9 +2625,11 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   P->sigma_br = sigma_br;
   P->theta = opt.theta > 0 ? opt.theta : 1.0 / (2.0 * sigma_br);
   if (!(P->theta * sigma_br < 1.0)) throw Error(H2_ERR_INVALID_ARG, "theta must be below 1/sigma");
-  P->budget[0] = opt.budget_coarse > 0 ? opt.budget_coarse : 0.25;
-  P->budget[1] = opt.budget_row > 0 ? opt.budget_row : 0.25;
-  P->budget[2] = opt.budget_col > 0 ? opt.budget_col : 0.25;
+  {
+    const Tol tol = resolve_tol(opt);
+    for (int i = 0; i < 3; ++i) P->budget[i] = tol.budget[i];
+    P->sweeps = tol.sweeps;
+  }
   build_block_tree(P->cbt, *X->rows, *Y->cols, X->bt.eta);
   Planner pl(ctx, X, Y, *P, kc, kcap);
   Builder& B = pl.B;
@@ -2900,9 +2942,11 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
   P->sigma_br = sigma_br;
   P->theta = opt.theta > 0 ? opt.theta : 1.0 / (2.0 * sigma_br);
   if (!(P->theta * sigma_br < 1.0)) throw Error(H2_ERR_INVALID_ARG, "theta must be below 1/sigma");
-  P->budget[0] = opt.budget_coarse > 0 ? opt.budget_coarse : 0.25;
-  P->budget[1] = opt.budget_row > 0 ? opt.budget_row : 0.25;
-  P->budget[2] = opt.budget_col > 0 ? opt.budget_col : 0.25;
+  {
+    const Tol tol = resolve_tol(opt);
+    for (int i = 0; i < 3; ++i) P->budget[i] = tol.budget[i];
+    P->sweeps = tol.sweeps;
+  }
   build_block_tree(P->cbt, *R, *Cc, eta);
   const BlockTree& bt = P->cbt;
   Planner pl(ctx, *R, *Cc, *P, kc, kcap);
@@ -2963,7 +3007,7 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
   P->bytes_alg = 8.0 * (double)(nu + nz + noff) + 2.0 * (double)P->wsd * 8.0;
   share_workspace(*P);
   finalize(*P, eps);
-  set_eps(*P, eps);
+  set_tolerances(*P, eps, resolve_tol(opt));
   const double tplan = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   const std::pair<const double*, int64_t> host_in[3] = {{U, nu}, {Z, nz}, {near, noff}};
   for (int i = 0; i < 3; ++i)
@@ -2976,6 +3020,7 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
   int ovf = 0;
   H2_HIP(hipMemcpyAsync(&ovf, ctx->overflow, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   H2_HIP(hipStreamSynchronize(ctx->stream));
+  check_overflow_bits(ovf);
   if (ovf)
     throw Error(H2_ERR_TOO_LARGE, (ovf & 1) ? "truncated block rank above coarse_rank cap"
                                              : "basis rank above max_rank cap");
@@ -3085,6 +3130,7 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   if (X->cols.get() != Y->rows.get()) throw Error(H2_ERR_INCOMPATIBLE, "X's column tree is not Y's row tree");
   if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
   if (X->kc > 64 || Y->kc > 64) throw Error(H2_ERR_TOO_LARGE, "operand rank above 64");
+  const Tol tol = resolve_tol(opt);  // validates budgets, theta and the sweep cap
   if (ctx->lanes.empty()) ctx->set_lanes(4);
   auto J = std::make_unique<Job>();
   J->ctx = ctx;
@@ -3142,9 +3188,9 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   }
   LaneRes& LR = *ctx->lanes[lane];
   if (LR.free_slots.empty()) throw Error(H2_ERR_TOO_LARGE, "more than 64 jobs in flight on one lane");
-  if (P.eps_set != eps) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
+  if (tol_differs(P, eps, tol)) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
   bind(ctx, P, lane, eps);
-  set_eps(P, eps);
+  set_tolerances(P, eps, tol);
   J->f32 = f32;
   J->kc = kc;
   J->lane = lane;
@@ -3261,6 +3307,8 @@ std::unique_ptr<Matrix> wait(Job& J, h2_mul_stats* stats) {
   int ovf = 0;
   H2_HIP(hipMemcpy(&ovf, J.flag, sizeof(int), hipMemcpyDeviceToHost));
   J.release();
+  if (ovf & h2k::kOvfNotConverged) J.C.reset();
+  check_overflow_bits(ovf);
   if (ovf) {
     J.C.reset();
     if (J.f32) {

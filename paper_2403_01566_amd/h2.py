@@ -32,6 +32,7 @@ EXPORTS = [
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
     "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error", "h2_block_tree_leaves", "h2_recompress",
     "h2_context_set_lanes", "h2_mul_submit", "h2_job_poll", "h2_job_wait", "h2_job_destroy",
+    "h2_export_host",
 ]
 NKERNEL = 13
 
@@ -39,7 +40,8 @@ NKERNEL = 13
 class MulOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("theta", C.c_double), ("budget_coarse", C.c_double),
                 ("budget_row", C.c_double), ("budget_col", C.c_double), ("max_rank", C.c_int),
-                ("coarse_rank", C.c_int), ("timing", C.c_int), ("graph", C.c_int)]
+                ("coarse_rank", C.c_int), ("timing", C.c_int), ("graph", C.c_int),
+                ("jacobi_sweeps", C.c_int)]
 
 
 class MulStats(C.Structure):
@@ -55,6 +57,16 @@ class MulStats(C.Structure):
         for f in ("t_phase", "t_kernel", "launches_kernel", "units_kernel", "flops_kernel", "bytes_kernel"):
             d[f] = list(getattr(self, f))
         return d
+
+
+class HostView(C.Structure):
+    _fields_ = [("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ncl_rows", C.c_int), ("ncl_cols", C.c_int),
+                ("kc", C.c_int), ("n_adm", C.c_int64), ("n_inadm", C.c_int64), ("near_size", C.c_int64),
+                ("v_leaf", C.POINTER(C.c_double)), ("v_transfer", C.POINTER(C.c_double)),
+                ("w_leaf", C.POINTER(C.c_double)), ("w_transfer", C.POINTER(C.c_double)),
+                ("couplings", C.POINTER(C.c_double)), ("near", C.POINTER(C.c_double)),
+                ("near_offset", C.POINTER(C.c_int64)), ("rank_row", C.POINTER(C.c_int)),
+                ("rank_col", C.POINTER(C.c_int))]
 
 
 _vp = C.c_void_p
@@ -92,6 +104,7 @@ _sig = {
     "h2_job_poll": (C.c_int, [_vp, _ip]),
     "h2_job_wait": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(MulStats)]),
     "h2_job_destroy": (None, [_vp]),
+    "h2_export_host": (C.c_int, [_vp, C.POINTER(HostView)]),
     "h2_recompress": (C.c_int, [_vp, _vp, _vp, C.c_double, _ip, _dp, _dp, _dp, C.c_double, C.POINTER(MulOptions),
                                 C.POINTER(_vp), C.POINTER(MulStats)]),
 }
@@ -224,6 +237,33 @@ class Matrix:
         y2 = np.zeros((nout, x2.shape[1]), dtype=np.float64)
         _check(_lib.h2_matvec(self.h, int(bool(trans)), x2.shape[1], _dptr(x2), _dptr(y2)))
         return y2[:, 0] if xa.ndim == 1 else y2
+
+    def export(self):
+        """Packed arrays (h2_export_host): dict with v_leaf (n_rows, kc),
+        v_transfer (ncl_rows, kc, kc), w_leaf, w_transfer, couplings
+        (n_adm, kc, kc), near, near_offset, rank_row, rank_col and the sizes."""
+        v = HostView()
+        _check(_lib.h2_export_host(self.h, C.byref(v)))
+        kc = v.kc
+        out = {"kc": kc, "n_adm": v.n_adm, "n_inadm": v.n_inadm}
+        arrs = {
+            "v_leaf": np.zeros((v.n_rows, kc)), "v_transfer": np.zeros((v.ncl_rows, kc, kc)),
+            "w_leaf": np.zeros((v.n_cols, kc)), "w_transfer": np.zeros((v.ncl_cols, kc, kc)),
+            "couplings": np.zeros((v.n_adm, kc, kc)), "near": np.zeros(max(v.near_size, 1)),
+        }
+        for k, a in arrs.items():
+            setattr(v, k, a.ctypes.data_as(_dp))
+        noff = np.zeros(v.n_inadm + 1, dtype=np.int64)
+        rr = np.zeros(v.ncl_rows, dtype=np.int32)
+        rc = np.zeros(v.ncl_cols, dtype=np.int32)
+        v.near_offset = noff.ctypes.data_as(_lp)
+        v.rank_row = rr.ctypes.data_as(_ip)
+        v.rank_col = rc.ctypes.data_as(_ip)
+        _check(_lib.h2_export_host(self.h, C.byref(v)))
+        out.update(arrs)
+        out["near"] = arrs["near"][: v.near_size]
+        out.update(near_offset=noff, rank_row=rr, rank_col=rc)
+        return out
 
     def block_dense(self, b, m, n):
         out = np.zeros((m, n), dtype=np.float64)

@@ -6,9 +6,18 @@ seeded points.  Checked per leaf block b of the result:
     exact product of the dense operands;
   * the distance to the oracle's result  ||C|_b - C_oracle|_b||_2 <= 2 eps ||(XY)|_b||_2;
   * inadmissible blocks equal the exact product to rounding.
-Bases are compared only through block values (they are unique only up to
-orthogonal transforms); rank differences are reported, not asserted.
+The result's packed arrays (h2_export_host) are checked as an H2-matrix
+(Definition 4, Section 5.2): every row and column cluster basis is isometric,
+V_t^* V_t = I, and nested with the exported ranks (leaf bases, transfers and
+couplings vanish outside their k_t x k_parent / k_t x k_s corners, so
+V_parent restricted to t is V_t E_t with k_t columns), and the blocks formed
+from these arrays are the blocks of h2_to_dense.
+Bases are compared with the oracle's only through block values (they are
+unique only up to orthogonal transforms).  Ranks may differ where a singular
+value lies near its threshold; every mismatch is reported with the oracle's
+singular value sigma at the boundary and |sigma - tau| / tau.
 """
+import math
 import sys
 
 import numpy as np
@@ -42,6 +51,11 @@ def _geometry(case):
     if case == "sphere3":
         P, n = W.icosphere(3)
         return dict(P=P, nrm=n, leaf=64, kern=1, order=3, eta=1.0, diag=1)
+    if case == "sphere4":
+        # the timed workload's construction one refinement level lower:
+        # icosphere 4 (n = 5120), leaf 64, eta 1, order 4 (k = 64)
+        P, n = W.icosphere(4)
+        return dict(P=P, nrm=n, leaf=64, kern=1, order=4, eta=1.0, diag=1)
     if case == "sphere2dlp":
         P, n = W.icosphere(2)
         return dict(P=P, nrm=n, leaf=20, kern=1, order=2, eta=1.0, diag=1, dlp=True)
@@ -69,8 +83,29 @@ def _build(h2, ctx, case):
     return T, A, B, To, Ao, Bo
 
 
-def _compare(h2, T, Cg, Ao, Bo, Co, eps, prec=0):
-    Ex = Ao.to_dense() @ Bo.to_dense()
+def _norm2(M):
+    """Spectral norm; large blocks through the largest eigenvalue of the
+    smaller Gram matrix (relative accuracy ~1e-15 of the value itself)."""
+    if M.size == 0:
+        return 0.0
+    if min(M.shape) <= 96:
+        return float(np.linalg.norm(M, 2))
+    G = M.T @ M if M.shape[0] >= M.shape[1] else M @ M.T
+    return math.sqrt(max(float(np.linalg.eigvalsh(G)[-1]), 0.0))
+
+
+_exact_cache = {}
+
+
+def _exact(case, Ao, Bo):
+    if case not in _exact_cache:
+        _exact_cache.clear()
+        _exact_cache[case] = Ao.to_dense() @ Bo.to_dense()
+    return _exact_cache[case]
+
+
+def _compare(h2, T, Cg, Ao, Bo, Co, eps, prec=0, case=None):
+    Ex = _exact(case, Ao, Bo) if case else Ao.to_dense() @ Bo.to_dense()
     Cd = Cg.to_dense(T.n, T.n)
     Cod = Co.to_dense()
     blocks, nadm = Cg.blocks()
@@ -83,33 +118,128 @@ def _compare(h2, T, Cg, Ao, Bo, Co, eps, prec=0):
         J = perm[b[r]:e[r]]
         ex = Ex[np.ix_(I, J)]
         cb = Cd[np.ix_(I, J)]
-        nn = np.linalg.norm(ex, 2)
         if i < nadm:
+            nn = _norm2(ex)
             if nn == 0:
                 assert np.abs(cb).max() <= 1e-12 * scale
                 continue
-            rel = np.linalg.norm(ex - cb, 2) / nn
-            ro = np.linalg.norm(cb - Cod[np.ix_(I, J)], 2) / nn
+            rel = _norm2(ex - cb) / nn
+            ro = _norm2(cb - Cod[np.ix_(I, J)]) / nn
             worst, worst_o = max(worst, rel), max(worst_o, ro)
         elif prec == 0:
             # inadmissible blocks are exact up to FP64 rounding
             assert np.abs(ex - cb).max() <= 1e-11 * scale, (t, r)
         else:
             # FP32 bulk: exact product rounded in FP32, still within eps per block
-            worst = max(worst, np.linalg.norm(ex - cb, 2) / nn)
-    return worst, worst_o
+            nn = _norm2(ex)
+            if nn == 0:
+                assert np.abs(cb).max() <= 1e-6 * scale, (t, r)
+                continue
+            worst = max(worst, _norm2(ex - cb) / nn)
+    return worst, worst_o, Cd
+
+
+def _full_bases(leaf, tr, rank, T):
+    """Explicit V_t (|t| x k_t) of every cluster from the exported leaf bases
+    and transfers, bottom-up; also checks the zero padding."""
+    b, e, par, lev = T.clusters()
+    kids = [[] for _ in range(T.ncl)]
+    for c in range(T.ncl):
+        if par[c] >= 0:
+            kids[par[c]].append(c)
+    kc = leaf.shape[1]
+    full = {}
+    for t in sorted(range(T.ncl), key=lambda c: -lev[c]):
+        k = int(rank[t])
+        if not kids[t]:
+            Vt = leaf[b[t]:e[t]]
+            assert np.all(Vt[:, k:] == 0.0), ("leaf basis beyond its rank", t)
+            full[t] = Vt[:, :k]
+        else:
+            parts = []
+            for c in kids[t]:
+                E = tr[c]
+                kcc = int(rank[c])
+                assert np.all(E[kcc:, :] == 0.0) and np.all(E[:, k:] == 0.0), ("transfer beyond its ranks", c)
+                parts.append(full[c] @ E[:kcc, :k])
+            full[t] = np.vstack(parts)
+    return full, kids
+
+
+def _check_result_arrays(Cg, T, Cd):
+    """Isometric nested bases with the exported ranks; blocks from the
+    exported arrays equal h2_to_dense.  Returns the worst ||V^*V - I||."""
+    ex = Cg.export()
+    assert ex["v_leaf"].shape == (T.n, ex["kc"]) and ex["couplings"].shape[0] == ex["n_adm"]
+    worst = 0.0
+    full = {}
+    for side, leaf, tr, rank in (("row", ex["v_leaf"], ex["v_transfer"], ex["rank_row"]),
+                                  ("col", ex["w_leaf"], ex["w_transfer"], ex["rank_col"])):
+        F, kids = _full_bases(leaf, tr, rank, T)
+        full[side] = F
+        for t in range(T.ncl):
+            k = int(rank[t])
+            if k == 0:
+                continue
+            # local form: orthonormal leaf basis, orthonormal stacked transfers
+            if not kids[t]:
+                L = F[t]
+            else:
+                L = np.vstack([tr[c][:int(rank[c]), :k] for c in kids[t]])
+            d_loc = np.abs(L.T @ L - np.eye(k)).max()
+            d = np.abs(F[t].T @ F[t] - np.eye(k)).max()
+            worst = max(worst, d, d_loc)
+            assert d_loc <= 1e-12 and d <= 1e-12, (side, t, d_loc, d)
+    blocks, nadm = Cg.blocks()
+    b, e, _, _ = T.clusters()
+    perm = T.permutation()
+    scale = np.abs(Cd).max()
+    for i in range(nadm):
+        t, r = blocks[i]
+        S = ex["couplings"][i]
+        kt, kr = int(ex["rank_row"][t]), int(ex["rank_col"][r])
+        assert np.all(S[kt:, :] == 0.0) and np.all(S[:, kr:] == 0.0), ("coupling beyond its ranks", t, r)
+        blk = full["row"][t] @ S[:kt, :kr] @ full["col"][r].T
+        ref = Cd[np.ix_(perm[b[t]:e[t]], perm[b[r]:e[r]])]
+        assert np.abs(blk - ref).max() <= 1e-12 * scale, (t, r)
+    for i in range(ex["n_inadm"]):
+        t, r = blocks[nadm + i]
+        o0, o1 = ex["near_offset"][i], ex["near_offset"][i + 1]
+        blk = ex["near"][o0:o1].reshape(e[t] - b[t], e[r] - b[r])
+        assert np.array_equal(blk, Cd[np.ix_(perm[b[t]:e[t]], perm[b[r]:e[r]])])
+    return worst
+
+
+def _rank_mismatches(rank_gpu, rank_oracle, sv, tol):
+    """Clusters whose GPU rank differs from the oracle's: (cluster, gpu, oracle,
+    |sigma - tau| / tau) with sigma the oracle's singular value at the GPU's cut."""
+    out = []
+    for t, ko in rank_oracle.items():
+        kg = int(rank_gpu[t])
+        if kg == ko:
+            continue
+        s = sv.get(t, np.zeros(0))
+        idx = kg - 1 if kg > ko else kg  # smallest value the GPU kept extra / largest it dropped
+        sig = float(s[idx]) if 0 <= idx < len(s) else 0.0
+        out.append((t, kg, ko, abs(sig - tol) / tol))
+    return out
 
 
 CASES = [
     ("grid32", 1e-4, 0),
     ("sphere3", 1e-6, 0),
     ("sphere3", 1e-4, 1),
+    ("sphere4", 1e-6, 0),
+    ("sphere4", 1e-4, 0),
     ("sphere2dlp", 1e-4, 0),
+    ("sphere2dlp", 1e-4, 1),
     ("random2d", 1e-5, 0),
     ("random2d", 1e-4, 1),
     ("cube_dlp", 1e-4, 0),
     ("cube_dlp", 1e-6, 0),
 ]
+
+_oracle_cache = {}
 
 
 @pytest.mark.parametrize("case,eps,prec", CASES)
@@ -117,12 +247,33 @@ def test_parity_against_oracle(h2, ctx, case, eps, prec):
     _say(f"[parity] {case} eps={eps} prec={prec}")
     T, A, B, To, Ao, Bo = _build(h2, ctx, case)
     Cg, st = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))
-    assert st["prec_used"] == prec
-    Co, info = O.mul(Ao, Bo, eps)
-    worst, worst_o = _compare(h2, T, Cg, Ao, Bo, Co, eps, prec)
+    if prec == 1 and case == "sphere2dlp":
+        # the single layer times the double layer cancels: where FP32 rounding
+        # of the exact blocks reaches the truncation tolerance the library
+        # reruns the bulk in FP64; the bound below holds either way
+        assert st["prec_used"] in (0, 1)
+    else:
+        assert st["prec_used"] == prec
+    key = (case, eps)
+    if key not in _oracle_cache:
+        _oracle_cache.clear()
+        _oracle_cache[key] = O.mul(Ao, Bo, eps)
+    Co, info = _oracle_cache[key]
+    worst, worst_o, Cd = _compare(h2, T, Cg, Ao, Bo, Co, eps, st["prec_used"], case)
+    iso = _check_result_arrays(Cg, T, Cd)
     rr, rc = Cg.ranks(T.ncl, T.ncl)
+    mm = _rank_mismatches(rr, Co.V.rank, info.row_sv, info.tol_r) + \
+        _rank_mismatches(rc, Co.W.rank, info.col_sv, info.tol_w)
+    ratios = sorted(x[3] for x in mm)
     _say(f"  worst block error {worst:.3e} (eps {eps}), distance to oracle {worst_o:.3e}, "
-         f"ranks gpu {rr.max()}/{rc.max()} oracle {max(Co.V.rank.values())}/{max(Co.W.rank.values())}")
+         f"prec_used {st['prec_used']}, ranks gpu {rr.max()}/{rc.max()} oracle "
+         f"{max(Co.V.rank.values())}/{max(Co.W.rank.values())}, bases ||V^*V - I|| <= {iso:.1e}")
+    above = sum(1 for x in mm if x[1] > x[2])
+    _say(f"  rank mismatches {len(mm)} of {2 * T.ncl} clusters ({above} with the GPU rank above the oracle's, "
+         f"by at most {max([abs(x[1] - x[2]) for x in mm], default=0)})"
+         + (f", |sigma - tau|/tau median {ratios[len(ratios) // 2]:.3f} max {ratios[-1]:.3f}" if mm else ""))
+    for t, kg, ko, q in mm[:8]:
+        _say(f"    cluster {t}: gpu {kg} oracle {ko} |sigma - tau|/tau {q:.3f}")
     assert worst <= eps
     assert worst_o <= 2 * eps
 
@@ -220,3 +371,34 @@ def test_rectangular_product_three_trees(h2, ctx, eps):
     assert worst <= eps and worst_o <= 2 * eps
     x = np.random.default_rng(4).standard_normal(Tg[2].n)
     assert np.abs(Cg.matvec(x) - Cd @ x).max() <= 1e-12 * np.abs(Cd).sum(axis=1).max() * np.abs(x).max()
+
+
+def test_budgets_sweep_cap_and_reuse_of_the_plan(h2, ctx):
+    """Error budgets and the Jacobi sweep cap are validated, take effect on a
+    cached plan, and are undone by the next default call: default, custom
+    budgets, a forced non-convergence (sweep cap 1: the product fails with
+    NOT_CONVERGED, the condition forced from the host), default again (bit for
+    bit the first result)."""
+    _say("[parity] budgets and sweep cap")
+    T, A, B, To, Ao, Bo = _build(h2, ctx, "grid32")
+    eps = 1e-5
+    C0, s0 = h2.mul(ctx, A, A, eps)
+    D0 = C0.to_dense(T.n, T.n)
+    Co, info = O.mul(Ao, Ao, eps)
+    C1, s1 = h2.mul(ctx, A, A, eps, h2.default_options(budget_coarse=0.5, budget_row=0.2, budget_col=0.2))
+    assert s1["t_plan_ms"] == 0.0
+    worst, worst_o, _ = _compare(h2, T, C1, Ao, Ao, Co, eps)
+    _say(f"  budgets 0.5/0.2/0.2: worst block error {worst:.3e}, ranks {s1['rank_max_row']} "
+         f"(default {s0['rank_max_row']})")
+    assert worst <= eps
+    with pytest.raises(h2.H2Error) as ei:
+        h2.mul(ctx, A, A, eps, h2.default_options(jacobi_sweeps=1))
+    assert ei.value.code == h2.H2_ERR_NOT_CONVERGED
+    for bad in (dict(budget_coarse=-0.1), dict(budget_row=float("nan")), dict(budget_coarse=0.5, budget_row=0.5),
+                dict(jacobi_sweeps=-1), dict(theta=float("inf"))):
+        with pytest.raises(h2.H2Error) as ei:
+            h2.mul(ctx, A, A, eps, h2.default_options(**bad))
+        assert ei.value.code == h2.H2_ERR_INVALID_ARG, bad
+    C2, s2 = h2.mul(ctx, A, A, eps)
+    assert s2["t_plan_ms"] == 0.0
+    assert np.array_equal(C2.to_dense(T.n, T.n), D0)
