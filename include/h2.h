@@ -248,6 +248,24 @@ h2_status h2_recompress(h2_context ctx, h2_tree rows, h2_tree cols, double eta, 
  * synchronous.  nrhs >= 1, else INVALID_ARG. */
 h2_status h2_matvec(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): h2_matvec
+ * with no device allocation at all.  Same arguments, errors and result as
+ * h2_matvec (bit for bit: the same kernels on the same launch descriptors).
+ * Every device buffer of the call (input and output vectors in tree order,
+ * the coefficient vectors of the nested bases, the launch descriptors) lives
+ * in one library-owned device array of H2_MATVEC_SCRATCH_BYTES per GPU,
+ * created when the library is loaded on that GPU and held until the process
+ * ends; its address is looked up by h2_context_create.  A call that needs
+ * more (8 (n_rows + n_cols) nrhs + 8 (ncl_rows + ncl_cols) kc nrhs bytes plus
+ * the descriptors, which grow with the number of blocks) fails with
+ * H2_ERR_TOO_LARGE before any device work.  The array keeps the last call's
+ * contents; nothing in it needs to start at zero.  All calls on one GPU share
+ * it (every context, every host thread): calls that overlap on one GPU race,
+ * so the caller serialises them.  Synchronous. */
+#define H2_MATVEC_SCRATCH_BYTES (32u * 1024u * 1024u)
+h2_status h2_matvec_noalloc(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y);
+
 /* Global error of a product as the experiments of Section 6 report it: the
  * relative spectral error ||XY - C||_2 / ||XY||_2, both norms estimated by
  * `iters` steps of the power iteration (the paper uses ten).  Each step on

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libh2mul.so")
 
-SOURCES = ["h2_kernels.hip", "h2_setup.cpp", "h2_plan.cpp", "h2_capi.cpp", "h2_selftest.cpp"]
+SOURCES = ["h2_kernels.hip", "h2_scratch.hip", "h2_setup.cpp", "h2_plan.cpp", "h2_capi.cpp", "h2_selftest.cpp"]
 ARCH = os.environ.get("H2_OFFLOAD_ARCH", "gfx950")
 
 

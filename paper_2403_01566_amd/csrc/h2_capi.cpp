@@ -71,6 +71,7 @@ h2_status h2_context_create(int device, h2_context* out) {
       H2_HIP(hipEventCreateWithFlags(&ctx->c.fork, hipEventDisableTiming));
       for (auto& e : ctx->c.join) H2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
       H2_HIP(hipMalloc((void**)&ctx->c.overflow, sizeof(int)));
+      (void)h2::scratch_address(device);  // once per device, with the device current
     } catch (...) {
       delete ctx;
       throw;
@@ -334,6 +335,17 @@ h2_status h2_matvec(h2_matrix M, int trans, int64_t nrhs, const double* x, doubl
     auto& m = *M->m;
     H2_HIP(hipSetDevice(m.ctx->device));
     h2::matvec(&m, trans, nrhs, x, y);
+  });
+}
+
+h2_status h2_matvec_noalloc(h2_matrix M, int trans, int64_t nrhs, const double* x, double* y) {
+  return guard([&] {
+    require(M && x && y, "null argument");
+    require(nrhs >= 1, "nrhs below 1");
+    require(trans == 0 || trans == 1, "trans must be 0 or 1");
+    auto& m = *M->m;
+    H2_HIP(hipSetDevice(m.ctx->device));
+    h2::matvec_scratch(&m, trans, nrhs, x, y, h2::scratch_address(m.ctx->device), h2::scratch_bytes());
   });
 }
 

@@ -168,6 +168,8 @@ struct Context {
   std::map<std::pair<uint64_t, uint64_t>, int> kc_raised;
   // matrix-vector plans: (matrix id, transposed, number of vectors)
   std::map<std::tuple<uint64_t, int, int64_t>, std::shared_ptr<MvPlan>> mvplans;
+  // host parts of the matrix-vector plans of the allocation-free entry point
+  std::map<std::tuple<uint64_t, int, int64_t>, std::shared_ptr<MvPlan>> mvhost;
   // lanes for asynchronous products: lanes[0] shares the context's stream
   // (its flags are separate from `overflow`); created by set_lanes
   std::vector<std::unique_ptr<LaneRes>> lanes;
@@ -216,6 +218,13 @@ std::unique_ptr<Matrix> recompress(Context* ctx, std::shared_ptr<Tree> R, std::s
 // y = M x (trans = 0) or M^T x (trans = 1) for nrhs vectors, host arrays in
 // the original point order, row-major (one vector per column).
 void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y);
+// The same product with every device buffer of the call inside `scratch`
+// (`bytes` long): TOO_LARGE if it does not fit; allocates no device memory.
+void matvec_scratch(Matrix* M, int trans, int64_t nrhs, const double* x, double* y, char* scratch, size_t bytes);
+// The library's static scratch array of this device (h2_scratch.hip): its
+// device address, resolved once per device with that device current, and size.
+char* scratch_address(int device);
+size_t scratch_bytes();
 // Power-iteration estimates of ||XY - C||_2 (C may be null: 0) and ||XY||_2,
 // started from z0 (cols(Y) entries, original order).
 void product_error(Matrix* X, Matrix* Y, Matrix* C, int iters, const double* z0, double* err, double* nxy);

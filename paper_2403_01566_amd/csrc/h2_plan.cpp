@@ -2103,13 +2103,9 @@ static void set_base(Plan& P, char* base) {
 
 // Descriptors of every step, resolved against the current workspace
 // pointers, uploaded to the device.
-static void emit(Plan& P, double eps) {
-  // a captured graph holds workspace pointers as kernel arguments (the
-  // FP32 -> FP64 conversions): new pointers need a new capture
-  if (P.gexec) {
-    H2_HIP(hipGraphExecDestroy(P.gexec));
-    P.gexec = nullptr;
-  }
+// Descriptors of every step resolved against the current workspace pointers
+// (host bytes; st.desc_off etc. are offsets into them).
+static std::vector<char> build_blob(Plan& P, double eps) {
   std::vector<char> blob;
   auto align = [&](size_t a) {
     while (blob.size() % a) blob.push_back(0);
@@ -2188,10 +2184,28 @@ static void emit(Plan& P, double eps) {
       case SK_CVT_F2D: break;
     }
   }
+  return blob;
+}
+
+static void drop_protos(Plan& P);
+
+// Descriptors uploaded to the plan's own descriptor buffer.
+static void emit(Plan& P, double eps) {
+  // a captured graph holds workspace pointers as kernel arguments (the
+  // FP32 -> FP64 conversions): new pointers need a new capture
+  if (P.gexec) {
+    H2_HIP(hipGraphExecDestroy(P.gexec));
+    P.gexec = nullptr;
+  }
+  std::vector<char> blob = build_blob(P, eps);
   P.hdesc = blob;
   if (P.desc.bytes < blob.size() || !P.desc.p) P.desc.alloc(std::max<size_t>(blob.size(), 64));
   H2_HIP(hipMemcpy(P.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
   P.eps_set = eps;
+  drop_protos(P);
+}
+
+static void drop_protos(Plan& P) {
   if (!P.keep_protos) {
     // descriptors are on the device for good; drop the host-side proto lists of GEMM steps
     for (auto& st : P.steps) {
@@ -2315,10 +2329,10 @@ static double qr_flops(double m, double w) {
 
 // timing: 0 none, 1 per-phase events, 2 also events around every kernel launch,
 // 3 also the algorithmic work from the sizes the QR / SVD kernels report.
-static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_phase) {
+static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_phase, char* desc_base = nullptr) {
   (void)ctx;
   hipStream_t s = L.stream;
-  char* base = (char*)P.desc.p;
+  char* base = desc_base ? desc_base : (char*)P.desc.p;
   std::vector<hipEvent_t> ev;
   int cur_phase = -1;
   if (timing) {
@@ -2705,7 +2719,8 @@ struct MvPlan {
   double* out() const { return P->wd + out_off; }
 };
 
-static std::shared_ptr<MvPlan> build_mv(Matrix* M, int trans, int64_t nrhs) {
+// The plan's steps and workspace layout (host only: no device memory).
+static std::shared_ptr<MvPlan> build_mv_host(Matrix* M, int trans, int64_t nrhs) {
   auto mv = std::make_shared<MvPlan>();
   mv->P = std::make_shared<Plan>();
   Plan& P = *mv->P;
@@ -2803,7 +2818,16 @@ static std::shared_ptr<MvPlan> build_mv(Matrix* M, int trans, int64_t nrhs) {
       near_items(g, t);
     }
   }
-  finalize(P, 0.0);
+  layout(P);
+  return mv;
+}
+
+static std::shared_ptr<MvPlan> build_mv(Matrix* M, int trans, int64_t nrhs) {
+  auto mv = build_mv_host(M, trans, nrhs);
+  Plan& P = *mv->P;
+  P.bufd.alloc(P.ws_bytes);
+  set_base(P, P.bufd.as<char>());
+  emit(P, 0.0);
   return mv;
 }
 
@@ -2827,6 +2851,48 @@ void matvec(Matrix* M, int trans, int64_t nrhs, const double* x, double* y) {
   for (int64_t i = 0; i < Ti.n; ++i) std::memcpy(&xt[i * nrhs], x + Ti.perm[i] * nrhs, nrhs * sizeof(double));
   H2_HIP(hipMemcpyAsync(mv->in(), xt.data(), xt.size() * sizeof(double), hipMemcpyHostToDevice, s));
   execute(ctx, ctx->lane0(), *mv->P, 0, nullptr);
+  H2_HIP(hipMemcpyAsync(yt.data(), mv->out(), yt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  H2_HIP(hipStreamSynchronize(s));
+  for (int64_t i = 0; i < To.n; ++i) std::memcpy(y + To.perm[i] * nrhs, &yt[i * nrhs], nrhs * sizeof(double));
+}
+
+// y = M x with every device buffer of the call (vectors, coefficient
+// vectors, launch descriptors) inside `scratch` (bytes long, 256-byte
+// aligned): no device allocation.  The plan's host part is cached per
+// (matrix, trans, nrhs); its descriptors are rebuilt against `scratch` and
+// copied there on every call, since other calls may have overwritten it.
+void matvec_scratch(Matrix* M, int trans, int64_t nrhs, const double* x, double* y, char* scratch, size_t bytes) {
+  Context* ctx = M->ctx;
+  hipStream_t s = ctx->stream;
+  const auto key = std::make_tuple(M->id, trans, nrhs);
+  std::shared_ptr<MvPlan> mv;
+  auto it = ctx->mvhost.find(key);
+  if (it != ctx->mvhost.end()) {
+    mv = it->second;
+  } else {
+    mv = build_mv_host(M, trans, nrhs);
+    mv->P->keep_protos = true;  // descriptors are rebuilt on every call
+    ctx->mvhost[key] = mv;
+  }
+  Plan& P = *mv->P;
+  const size_t desc_at = (P.ws_bytes + 255) & ~size_t(255);
+  if (desc_at > bytes)
+    throw Error(H2_ERR_TOO_LARGE, "matrix-vector product needs " + std::to_string(desc_at) +
+                                      " bytes of scratch workspace, above the scratch size " + std::to_string(bytes));
+  set_base(P, scratch);
+  const std::vector<char> blob = build_blob(P, 0.0);
+  if (desc_at + blob.size() > bytes)
+    throw Error(H2_ERR_TOO_LARGE, "matrix-vector product needs " + std::to_string(desc_at + blob.size()) +
+                                      " bytes of scratch (workspace and descriptors), above the scratch size " +
+                                      std::to_string(bytes));
+  const Tree& Ti = *mv->tin;
+  const Tree& To = *mv->tout;
+  std::vector<double> xt((size_t)Ti.n * nrhs), yt((size_t)To.n * nrhs);
+  for (int64_t i = 0; i < Ti.n; ++i) std::memcpy(&xt[i * nrhs], x + Ti.perm[i] * nrhs, nrhs * sizeof(double));
+  // blob and xt stay alive until the stream is synchronised below
+  H2_HIP(hipMemcpyAsync(scratch + desc_at, blob.data(), blob.size(), hipMemcpyHostToDevice, s));
+  H2_HIP(hipMemcpyAsync(mv->in(), xt.data(), xt.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  execute(ctx, ctx->lane0(), P, 0, nullptr, scratch + desc_at);
   H2_HIP(hipMemcpyAsync(yt.data(), mv->out(), yt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   H2_HIP(hipStreamSynchronize(s));
   for (int64_t i = 0; i < To.n; ++i) std::memcpy(y + To.perm[i] * nrhs, &yt[i * nrhs], nrhs * sizeof(double));

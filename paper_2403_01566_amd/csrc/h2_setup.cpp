@@ -207,6 +207,7 @@ Context::~Context() {
     if (l->l.stream) (void)hipStreamSynchronize(l->l.stream);
   plans.clear();
   mvplans.clear();
+  mvhost.clear();
   try {
     set_lanes(0);
   } catch (...) {
@@ -230,6 +231,10 @@ void Context::evict(uint64_t matrix_id) {
   }
   for (auto it = mvplans.begin(); it != mvplans.end();) {
     if (std::get<0>(it->first) == matrix_id) it = mvplans.erase(it);
+    else ++it;
+  }
+  for (auto it = mvhost.begin(); it != mvhost.end();) {
+    if (std::get<0>(it->first) == matrix_id) it = mvhost.erase(it);
     else ++it;
   }
   for (auto it = kc_raised.begin(); it != kc_raised.end();) {

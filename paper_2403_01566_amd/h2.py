@@ -32,7 +32,7 @@ EXPORTS = [
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
     "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error", "h2_block_tree_leaves", "h2_recompress",
     "h2_context_set_lanes", "h2_mul_submit", "h2_job_poll", "h2_job_wait", "h2_job_destroy",
-    "h2_export_host",
+    "h2_export_host", "h2_matvec_noalloc",
 ]
 NKERNEL = 13
 
@@ -97,6 +97,7 @@ _sig = {
     "h2_selftest": (C.c_int, [_vp, _dp, C.c_int, _ip]),
     "h2_kernel_name": (C.c_char_p, [C.c_int]),
     "h2_matvec": (C.c_int, [_vp, C.c_int, C.c_int64, _dp, _dp]),
+    "h2_matvec_noalloc": (C.c_int, [_vp, C.c_int, C.c_int64, _dp, _dp]),
     "h2_product_error": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp, _dp]),
     "h2_block_tree_leaves": (C.c_int, [_vp, _vp, C.c_double, _lp, _lp, _ip]),
     "h2_context_set_lanes": (C.c_int, [_vp, C.c_int]),
@@ -264,6 +265,18 @@ class Matrix:
         out["near"] = arrs["near"][: v.near_size]
         out.update(near_offset=noff, rank_row=rr, rank_col=rc)
         return out
+
+    def matvec_noalloc(self, x, trans=False):
+        """matvec through h2_matvec_noalloc (no device allocation: the library's
+        static scratch array); same result as matvec."""
+        xa = np.ascontiguousarray(x, dtype=np.float64)
+        x2 = xa.reshape(xa.shape[0], -1)
+        nin, nout = (self.shape[0], self.shape[1]) if trans else (self.shape[1], self.shape[0])
+        if x2.shape[0] != nin:
+            raise ValueError(f"x has {x2.shape[0]} rows, expected {nin}")
+        y2 = np.zeros((nout, x2.shape[1]), dtype=np.float64)
+        _check(_lib.h2_matvec_noalloc(self.h, int(bool(trans)), x2.shape[1], _dptr(x2), _dptr(y2)))
+        return y2[:, 0] if xa.ndim == 1 else y2
 
     def block_dense(self, b, m, n):
         out = np.zeros((m, n), dtype=np.float64)
