@@ -16,24 +16,30 @@ enum : int {
 };
 
 // One contribution alpha * op(A) * op(B) (or alpha * op(A)) to a task's output.
-// Matrices are row-major with the given leading dimensions.
+// Matrices are row-major with the given leading dimensions.  Optional device
+// ints k_dev, k_dev2 lower the inner dimension to min(k, *k_dev + *k_dev2)
+// (a width known only on the device, e.g. the packed columns of a merge; the
+// part beyond it is zero padding, so leaving it out changes no sum).
 template <typename T>
 struct GemmItem {
   const T* a;
   const T* b;
   const double* scale;  // optional device scalar (see IT_SCALE_INV)
+  const int* k_dev;
+  const int* k_dev2;
   int lda, ldb, k, flags;
   double alpha;
 };
 
-// Width of the K slices of the batched GEMM: a task's nslice is the sum over
-// its product items of ceil(k / kGemmSliceK).
+// Width of the K slices of the batched GEMM.
 constexpr int kGemmSliceK = 8;
 
 // One output matrix C (m x n, row-major, ldc): C = (beta ? C : 0) + sum of items.
 // Optional device ints: m_dev / n_dev lower m / n to min(m, *m_dev) etc.,
 // coff_dev shifts the output by *coff_dev columns and roff_dev by *roff_dev
 // rows (sizes known only on the device, e.g. truncation ranks).
+// Optional stat (3 ints, written by the task's first tile): the device-side
+// m and n and the sum of the product items' device-side k.
 template <typename T>
 struct GemmTask {
   T* c;
@@ -41,9 +47,10 @@ struct GemmTask {
   const int* n_dev;
   const int* coff_dev;
   const int* roff_dev;
+  int* stat;
   int ldc, m, n, item0, nitem, beta;
-  int nslice;  // 16-wide K slices of the product items: sum of ceil(k / 16)
   int ncopy;   // copy items
+  int pad;
 };
 
 struct GemmTile {

@@ -92,7 +92,14 @@ __global__ __launch_bounds__(256, 5) void gemm_kernel(const GemmItem<T>* __restr
   if (tk.n_dev) tk.n = min(tk.n, *tk.n_dev);
   if (tk.coff_dev) tk.c += *tk.coff_dev;
   if (tk.roff_dev) tk.c += (int64_t)*tk.roff_dev * tk.ldc;
-  if (tl.m0 >= tk.m || tl.n0 >= tk.n) return;  // whole tile outside the device-side size
+  if (tl.m0 >= tk.m || tl.n0 >= tk.n) {  // whole tile outside the device-side size
+    if (tk.stat && tl.m0 == 0 && tl.n0 == 0 && threadIdx.x == 0) {  // an empty task
+      tk.stat[0] = max(tk.m, 0);
+      tk.stat[1] = max(tk.n, 0);
+      tk.stat[2] = 0;
+    }
+    return;
+  }
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   const int wm = wv >> 1, wn = wv & 1;
@@ -103,10 +110,8 @@ __global__ __launch_bounds__(256, 5) void gemm_kernel(const GemmItem<T>* __restr
     for (int b = 0; b < 2; ++b)
       for (int v = 0; v < 4; ++v) acc[a][b][v] = T(0);
 
-  // copies (IT_COPY items) go straight into the accumulators; the task
-  // carries the number of product slices, so a task without copies never
-  // walks its item list here
-  const int nsl = tk.nslice;
+  // copies (IT_COPY items) go straight into the accumulators; a task
+  // without copies never walks its item list here
   for (int it = 0; it < (tk.ncopy > 0 ? tk.nitem : 0); ++it) {
     const GemmItem<T> item = items[tk.item0 + it];
     if (!(item.flags & IT_COPY)) continue;
@@ -130,8 +135,26 @@ __global__ __launch_bounds__(256, 5) void gemm_kernel(const GemmItem<T>* __restr
         }
   }
 
+  // number of K slices: the product items' device-side widths in slices of
+  // GBK (the part beyond a device-side width is zero padding)
+  int nsl = 0, ksum = 0;
+  for (int i = 0; i < tk.nitem; ++i) {
+    const GemmItem<T>* ip = items + tk.item0 + i;
+    if (ip->flags & IT_COPY) continue;
+    int ke = ip->k;
+    if (ip->k_dev) ke = min(ke, __builtin_amdgcn_readfirstlane(*ip->k_dev + (ip->k_dev2 ? *ip->k_dev2 : 0)));
+    ke = max(ke, 0);
+    ksum += ke;
+    nsl += (ke + GBK - 1) / GBK;
+  }
+  if (tk.stat && m0 == 0 && n0 == 0 && tid == 0) {
+    tk.stat[0] = tk.m;
+    tk.stat[1] = tk.n;
+    tk.stat[2] = ksum;
+  }
   if (nsl > 0) {
-    // slice cursor over the product items
+    // slice cursor over the product items (each item's K range lowered to its
+    // device-side width)
     int it = -1, k0 = 0, kend = 0;
     GemmItem<T> item{};
     T al = T(0);
@@ -151,6 +174,7 @@ __global__ __launch_bounds__(256, 5) void gemm_kernel(const GemmItem<T>* __restr
         al = T(alpha);
         k0 = 0;
         kend = item.k;
+        if (item.k_dev) kend = min(kend, __builtin_amdgcn_readfirstlane(*item.k_dev + (item.k_dev2 ? *item.k_dev2 : 0)));
       }
       return true;
     };

@@ -81,6 +81,7 @@ template <typename T>
 struct PItem {
   DRef<T> a, b;
   DRef<double> scale;
+  DRef<int> kd1, kd2;  // device-side inner dimension (sum of both), if set
   int lda, ldb, k, flags;
   double alpha;
 };
@@ -373,6 +374,13 @@ struct GW {
     s->flops += 2.0 * tk.m * tk.n * k;
     s->flops_tile += 2.0 * ((tk.m + 31) & ~31) * ((tk.n + 31) & ~31) * ((k + 15) & ~15);
     s->bytes += (double)sizeof(T) * ((double)tk.m * k + (double)k * tk.n);
+  }
+  // inner dimension of the last item known only on the device: *k1 + *k2
+  // (at most its planned k; the operands are zero beyond it)
+  void kdev(DRef<int> k1, DRef<int> k2 = DRef<int>()) {
+    auto& x = WS<T>::items(*s).back();
+    x.kd1 = k1;
+    x.kd2 = k2;
   }
   void copy(DRef<T> a, int lda, int flags = 0, double alpha = 1.0) {
     PItem<T> x;
@@ -1134,6 +1142,7 @@ void Planner::coarsen() {
     bool direct = false;
     int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
             Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
+    int64_t Wsum = -1;  // merge: packed width kappa_a + kappa_b (device int)
   };
   std::vector<MNode> mn;
   std::vector<int> of_un(un.size(), -1);
@@ -1259,16 +1268,32 @@ void Planner::coarsen() {
       if (mn[i].height == h) lv.push_back((int)i);
     if (lv.empty()) continue;
     if (h > 0) {  // U = [ext(U^_a S_a), ext(U^_b S_b)],  Z = [ext(V^_a), ext(V^_b)]
-      Step& fs = B.step(SK_FILL);
       for (int i : lv) {
         MNode& x = mn[i];
         x.K = 2 * kcap;
         x.U = B.wd((int64_t)x.m * x.K).off;
         x.Z = B.wd((int64_t)x.n * x.K).off;
-        fs.fill.push_back({Dw(x.U), x.K, x.m, x.K, 0, 0.0});
-        fs.fill.push_back({Dw(x.Z), x.K, x.n, x.K, 0, 0.0});
       }
-      // children's columns packed: [0, kappa_a) from a, [kappa_a, kappa_a + kappa_b) from b
+      {  // packed width of every merge: kappa_a + kappa_b
+        Step& sc = B.step(SK_SCAN);
+        for (int i : lv) {
+          MNode& x = mn[i];
+          x.Wsum = B.wi(1).off;
+          PScan c;
+          c.first = (int)sc.scansrc.size();
+          c.count = 2;
+          c.offs = Iw(B.wi(2).off);
+          c.total = Iw(x.Wsum);
+          sc.scansrc.push_back(Iw(mn[x.c0].Kap));
+          sc.scansrc.push_back(Iw(mn[x.c1].Kap));
+          sc.scan.push_back(c);
+        }
+      }
+      // Children's columns packed: [0, kappa_a) from a, [kappa_a, kappa_a +
+      // kappa_b) from b, each zero-extended to the rows of the merged block
+      // (tasks without items write the zeros).  Columns from kappa_a + kappa_b
+      // on are never written: every reader of U and Z takes that width from
+      // the device (QR widths, GEMM inner dimensions, the rows of U^* U^).
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
@@ -1277,12 +1302,22 @@ void Planner::coarsen() {
           const MNode& ch = mn[kid[c]];
           const int64_t ro = TI.begin[ch.t] - TI.begin[x.t], co = TK.begin[ch.r] - TK.begin[x.r];
           const DRef<int> off = c == 0 ? DRef<int>() : Iw(mn[x.c0].Kap);
+          const DRef<int> kap = Iw(ch.Kap);
+          auto zero = [&](int64_t base, int64_t r0, int64_t r1) {
+            if (r1 <= r0) return;
+            g.task(Dw(base) + r0 * x.K, x.K, (int)(r1 - r0), kcap);
+            g.dev(kap, off);
+          };
           g.task(Dw(x.U) + ro * x.K, x.K, ch.m, kcap);
-          g.dev(Iw(ch.Kap), off);
+          g.dev(kap, off);
           g.copy(Dw(ch.Wc), kcap);
+          zero(x.U, 0, ro);
+          zero(x.U, ro + ch.m, x.m);
           g.task(Dw(x.Z) + co * x.K, x.K, ch.n, kcap);
-          g.dev(Iw(ch.Kap), off);
+          g.dev(kap, off);
           g.copy(Dw(ch.Vh), kcap);
+          zero(x.Z, 0, co);
+          zero(x.Z, co + ch.n, x.n);
         }
       }
     } else {
@@ -1343,6 +1378,7 @@ void Planner::coarsen() {
         }
         g.task(Dw(x.Gh), x.K, x.m, x.K);
         g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
+        if (x.c0 >= 0) g.kdev(wd1(x), wd2(x));
       }
     }
     {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
@@ -1433,6 +1469,7 @@ void Planner::coarsen() {
         g.task(Dw(x.Yk), kcap, x.m, kcap);
         if (x.uI) g.mm(Dw(x.RZ), x.K, Dw(x.Vk), kcap, x.K, h2k::IT_TRANS_A);
         else g.mm(Dw(x.Gh), x.K, Dw(x.Vk), kcap, x.K);
+        if (x.c0 >= 0) g.kdev(wd1(x), wd2(x));
       }
     }
     {
@@ -1460,6 +1497,7 @@ void Planner::coarsen() {
         if (x.direct) continue;
         g.task(Dw(x.Uh), kcap, x.m, kcap);
         g.mm(Dw(x.Yk), kcap, Dw(x.T1), kcap, kcap);
+        g.kdev(Iw(x.Kap));
       }
     }
     {  // T = U^* U^  (U = I: T = U^)
@@ -1471,6 +1509,7 @@ void Planner::coarsen() {
           continue;
         }
         g.task(Dw(x.Tm), kcap, x.K, kcap);
+        if (x.c0 >= 0) g.dev(DRef<int>(), DRef<int>(), Iw(x.Wsum));  // rows beyond the packed width unused
         g.mm(Dw(x.U), x.K, Dw(x.Uh), kcap, x.m, h2k::IT_TRANS_A);
       }
     }
@@ -1484,6 +1523,7 @@ void Planner::coarsen() {
         }
         g.task(Dw(x.Zh), kcap, x.n, kcap);
         g.mm(Dw(x.Z), x.K, Dw(x.Tm), kcap, x.K);
+        if (x.c0 >= 0) g.kdev(wd1(x), wd2(x));
       }
     }
     {
@@ -1508,6 +1548,7 @@ void Planner::coarsen() {
         MNode& x = mn[i];
         g.task(Dw(x.Vh), kcap, x.n, kcap);
         g.mm(Dw(x.Zh), kcap, Dw(x.T2), kcap, kcap);
+        g.kdev(Iw(x.Kap));
         g.task(Dw(x.Sb), kcap, kcap, kcap);
         g.copy(Dw(x.R2), kcap, h2k::IT_TRANS_A);
       }
@@ -1518,6 +1559,7 @@ void Planner::coarsen() {
         MNode& x = mn[i];
         g.task(Dw(x.Wc), kcap, x.m, kcap);
         g.mm(Dw(x.Uh), kcap, Dw(x.Sb), kcap, kcap);
+        g.kdev(Iw(x.Kap));
       }
     }
   }
@@ -1630,15 +1672,18 @@ void Planner::bases() {
               g.task(out, w, kcap, w);
               g.dev(DRef<int>(), DRef<int>(), kap, ro);
               g.mm(Dw(u.Sb), kcap, Dw(X.rows ? u.Uh : u.Vh) + roff * kcap, kcap, kcap, fl, alpha, Dw(u.Sig));
+              g.kdev(kap);
             } else {
               // children's coefficients packed: [0, k_c0) and [k_c0, k_c0 + k_c1)
               const int c0 = T.children[s][0], c1 = T.children[s][1];
               g.task(out, w, kcap, kc);
               g.dev(X.rankout + c0, DRef<int>(), kap, ro);
               g.mm(Dw(u.Sb), kcap, Dw(X.proj[c0][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+              g.kdev(kap);
               g.task(out, w, kcap, kc);
               g.dev(X.rankout + c1, X.rankout + c0, kap, ro);
               g.mm(Dw(u.Sb), kcap, Dw(X.proj[c1][li]), kcap, kcap, fl, alpha, Dw(u.Sig));
+              g.kdev(kap);
             }
           }
         }
@@ -1717,7 +1762,9 @@ void Planner::bases() {
             for (int li : X.star[s]) {
               g.task(Dw(X.proj[s][li]), kcap, kc, kcap);
               g.mm(X.trout + (int64_t)c0 * kk, kc, Dw(X.proj[c0][li]), kcap, kc, h2k::IT_TRANS_A);
+              g.kdev(X.rankout + c0);
               g.mm(X.trout + (int64_t)c1 * kk, kc, Dw(X.proj[c1][li]), kcap, kc, h2k::IT_TRANS_A);
+              g.kdev(X.rankout + c1);
             }
           }
         }
@@ -1741,6 +1788,7 @@ void Planner::couplings() {
       tmp[li] = B.wd((int64_t)kc * kcap).off;
       g.task(Dw(tmp[li]), kcap, kc, kcap);
       g.mm(Dw(row_proj[nd.t][(int)li]), kcap, Dw(u.Sb), kcap, kcap);
+      g.kdev(Iw(u.Kap));
     }
   }
   {  // S_b = (V_t^* U^) S (W_r^* V^)^*
@@ -1749,6 +1797,7 @@ void Planner::couplings() {
       const auto& nd = C.nodes[C.adm[li]];
       g.task(P.res_S + (int64_t)li * kk, kc, kc, kc);
       g.mm(Dw(tmp[li]), kcap, Dw(col_proj[nd.s][(int)li]), kcap, kcap, h2k::IT_TRANS_B);
+      g.kdev(Iw(un[bnode[li]].Kap));
     }
   }
 }
@@ -1775,6 +1824,8 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     items[i].a = res(it[i].a, P);
     items[i].b = res(it[i].b, P);
     items[i].scale = res(it[i].scale, P);
+    items[i].k_dev = res(it[i].kd1, P);
+    items[i].k_dev2 = res(it[i].kd2, P);
     items[i].lda = it[i].lda;
     items[i].ldb = it[i].ldb;
     items[i].k = it[i].k;
@@ -1798,12 +1849,11 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     tasks[i].item0 = tk[i].item0;
     tasks[i].nitem = tk[i].nitem;
     tasks[i].beta = tk[i].beta;
-    tasks[i].nslice = tasks[i].ncopy = 0;
-    for (int q = 0; q < tk[i].nitem; ++q) {
-      const auto& x = it[tk[i].item0 + q];
-      if (x.flags & h2k::IT_COPY) ++tasks[i].ncopy;
-      else tasks[i].nslice += (x.k + h2k::kGemmSliceK - 1) / h2k::kGemmSliceK;
-    }
+    tasks[i].stat = st.stat_off >= 0 ? P.wi + st.stat_off + 3 * (int64_t)i : nullptr;
+    tasks[i].ncopy = 0;
+    tasks[i].pad = 0;
+    for (int q = 0; q < tk[i].nitem; ++q)
+      if (it[tk[i].item0 + q].flags & h2k::IT_COPY) ++tasks[i].ncopy;
     for (int m0 = 0; m0 < tk[i].m; m0 += 64)
       for (int n0 = 0; n0 < tk[i].n; n0 += 64) tiles.push_back({(int)i, m0, n0, 0});
   }
@@ -2082,8 +2132,10 @@ static size_t ws_part(int64_t count, size_t elem) { return ((size_t)std::max<int
 
 static void layout(Plan& P) {
   for (auto& st : P.steps) {
-    const int per = st.kind == SK_QR ? 2 : (st.kind == SK_SVD ? 4 : 0);
-    const size_t n = st.kind == SK_QR ? st.qr.size() : st.svd.size();
+    const bool gemm = st.kind == SK_GEMM_D || st.kind == SK_GEMM_F;
+    const int per = st.kind == SK_QR ? 2 : (st.kind == SK_SVD ? 4 : (gemm ? 3 : 0));
+    const size_t n = st.kind == SK_QR ? st.qr.size()
+                                      : (st.kind == SK_SVD ? st.svd.size() : (st.kind == SK_GEMM_D ? st.tkd.size() : st.tkf.size()));
     if (!per || !n) continue;
     st.stat_off = P.wsi;
     P.wsi += ((int64_t)(per * n) + 63) & ~int64_t(63);
@@ -2552,6 +2604,28 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
             P.flops_k[kid] += fl;
             P.bytes_k[kid] += 8.0 * (rows * cols + rows * st.svd[i].kcap + cols);
           }
+        }
+      } else if ((kind == SK_GEMM_D || kind == SK_GEMM_F) && st.stat_off >= 0 &&
+                 (kind == SK_GEMM_D ? !st.tkd.empty() : !st.tkf.empty())) {
+        // GEMM: the device-side sizes each task reported (m, n and the sum
+        // of its product items' inner dimensions), each operand read once and
+        // the output written once (read too with beta)
+        const int kid = kind == SK_GEMM_D ? h2k::K_GEMM_F64 : h2k::K_GEMM_F32;
+        const double w = kind == SK_GEMM_D ? 8.0 : 4.0;
+        const size_t n = kind == SK_GEMM_D ? st.tkd.size() : st.tkf.size();
+        stat.resize(3 * n);
+        H2_HIP(hipMemcpy(stat.data(), P.wi + st.stat_off, 3 * n * sizeof(int), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < n; ++i) {
+          const int beta = kind == SK_GEMM_D ? st.tkd[i].beta : st.tkf[i].beta;
+          const int item0 = kind == SK_GEMM_D ? st.tkd[i].item0 : st.tkf[i].item0;
+          const int nitem = kind == SK_GEMM_D ? st.tkd[i].nitem : st.tkf[i].nitem;
+          int ncopy = 0;
+          for (int q = 0; q < nitem; ++q)
+            ncopy += ((kind == SK_GEMM_D ? st.itd[item0 + q].flags : st.itf[item0 + q].flags) & h2k::IT_COPY) != 0;
+          const double m = std::max(stat[3 * i], 0), nn = std::max(stat[3 * i + 1], 0), ks = stat[3 * i + 2];
+          P.units_k[kid] += 1;
+          P.flops_k[kid] += 2.0 * m * nn * ks;
+          P.bytes_k[kid] += w * (m * ks + ks * nn + m * nn * (1 + (beta ? 1 : 0) + ncopy));
         }
       } else {
         static const int kmap[] = {h2k::K_GEMM_F64, h2k::K_GEMM_F32, -1, -1, h2k::K_CHOL, h2k::K_FILL, h2k::K_CVT,

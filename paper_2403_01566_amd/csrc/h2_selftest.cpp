@@ -35,8 +35,11 @@ std::vector<T> down(const T* d, size_t n) {
   return h;
 }
 
+// kdev > 0: item 0 takes its inner dimension min(k, kdev) from a device int
+// (its operands hold nonzero values beyond it, which must not contribute),
+// and the task's size report (m, n, sum of device-side k) is checked too.
 template <typename T>
-double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
+double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem, int kdev = 0) {
   std::vector<void*> keep;
   Lcg g(17 + flags + m);
   const bool ta = flags & h2k::IT_TRANS_A, tb = flags & h2k::IT_TRANS_B;
@@ -59,7 +62,13 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
   std::vector<T> c0((size_t)m * n);
   for (auto& x : c0) x = (T)g.next();
   T* dc = up(c0, keep);
-  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, n, m, n, 0, nitem, 1, nitem * ((k + h2k::kGemmSliceK - 1) / h2k::kGemmSliceK), 0};
+  int* dstat = up(std::vector<int>{-1, -1, -1}, keep);
+  if (kdev > 0) {
+    items[0].k_dev = up(std::vector<int>{kdev - 3}, keep);
+    items[0].k_dev2 = up(std::vector<int>{3}, keep);
+  }
+  h2k::GemmTask<T> task{dc, nullptr, nullptr, nullptr, nullptr, dstat, n, m, n, 0, nitem, 1, 0, 0};
+  const int k0eff = kdev > 0 ? std::min(k, kdev) : k;
   std::vector<h2k::GemmTile> tiles;
   for (int i = 0; i < m; i += 64)
     for (int j = 0; j < n; j += 64) tiles.push_back({0, i, j, 0});
@@ -77,7 +86,7 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
     for (int j = 0; j < n; ++j) {
       double v = c0[(size_t)i * n + j];
       for (int it = 0; it < nitem; ++it)
-        for (int q = 0; q < k; ++q) {
+        for (int q = 0; q < (it == 0 ? k0eff : k); ++q) {
           double a = ta ? A[it][(size_t)q * m + i] : A[it][(size_t)i * k + q];
           double b = tb ? B[it][(size_t)j * k + q] : B[it][(size_t)q * n + j];
           v += (1.0 + 0.5 * it) * a * b;
@@ -85,8 +94,10 @@ double gemm_test(hipStream_t s, int flags, int m, int n, int k, int nitem) {
       err = std::max(err, std::fabs(v - (double)c[(size_t)i * n + j]));
       ref = std::max(ref, std::fabs(v));
     }
+  const auto st = down(dstat, 3);
+  const bool stat_ok = st[0] == m && st[1] == n && st[2] == k0eff + (nitem - 1) * k;
   for (void* p : keep) (void)hipFree(p);
-  return err / std::max(ref, 1e-300);
+  return stat_ok ? err / std::max(ref, 1e-300) : 1.0;
 }
 
 double qr_test(hipStream_t s, int m, int w) {
@@ -376,6 +387,9 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   e.push_back(svd_test(s, 100, overflow, 1, 30.0, 1024));
   e.push_back(svd_test(s, 128, overflow, 1, 10.0, 1024));
   e.push_back(svd_test(s, 128, overflow, 0, 10.0, 1024));
+  // device-side inner dimension (the operands are nonzero beyond it)
+  e.push_back(gemm_test<double>(s, h2k::IT_TRANS_B, 70, 90, 77, 2, 21));
+  e.push_back(gemm_test<float>(s, h2k::IT_TRANS_A, 65, 40, 50, 3, 9));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
   return (int)e.size();
 }
