@@ -7,11 +7,11 @@ icosahedron refined 5 times (n = 20480 triangle centroids), single-layer
 kernel 1/(4 pi |x-y|) with the row-nearfield-mean diagonal, leaf size 64,
 eta = 1, tensor Chebyshev order 4 (k = 64), A*A at eps = 1e-6.
 
-Two legs are timed: plain FP64 and FP32 bulk / FP64 recompression.  The
-library runs the FP32 bulk only for eps >= 1e-5 (FP32 rounding of the exact
-product would exceed the coarsening tolerance below that), so at eps = 1e-6
-both legs compute in FP64 and `value` is the FP64 rate; the JSON says which
-precision each leg used.
+The headline leg is plain FP64 at the workload's eps.  The library runs the
+FP32 bulk only for eps >= 1e-5 (below that its rounding would exceed the
+coarsening tolerance), so the FP32-bulk / FP64-recompression form is timed
+against plain FP64 on the same operands at eps = 1e-4 (`modes`: products/s,
+precision used and roofline of each leg).
 
 Timing: `value`, ms_per_step and the latencies come from the timed steps
 without instrumentation (each product replays its HIP graph, captured in
@@ -23,11 +23,13 @@ launch come from one untimed counting call (timing mode 3: the QR and SVD
 kernels report the sizes they factored).  achieved = algorithmic work per
 launch / average launch duration.
 
-cpu_baseline: the FP64 oracle (test infrastructure) on the host cores, on a
-bounded sample: for the sphere workloads the full oracle product of the same
-construction one refinement level lower (n = 5120), scaled to the timed
-workload by the ratio of the two products' algorithmic flops as the library
-counts them; for the small grid workload the full product itself.
+cpu_baseline: the FP64 oracle (test infrastructure) on one host core (its many
+small factorizations run fastest single-threaded), on a bounded sample: the
+full oracle product of the same construction one refinement level lower
+(n = 5120), scaled to the timed workload by the oracle's own time ratio of
+the two products, both measured in full once on one host core
+(`--oracle-scaling`, recorded in profiles/oracle_icosphere5_slp.md); for the
+small grid workload the full product itself.
 
 global_error (untimed): the relative spectral error of one product, both
 norms estimated by ten device power-iteration steps, with the storage of the
@@ -66,7 +68,8 @@ WORKLOADS = {
                eps=1e-4, geom=("grid", 32), kernel=0, leaf=32, order=3, eta=0.5, diag=0, sample=None),
     "icosphere5_slp": dict(desc="icosphere level 5 (n=20480 centroids), 1/(4 pi |x-y|) (diag = row nearfield mean), leaf 64, "
                     "eta 1, Chebyshev order 4 (k=64), A*A, eps 1e-6",
-               eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1, sample=("ico", 4)),
+               eps=1e-6, geom=("ico", 5), kernel=1, leaf=64, order=4, eta=1.0, diag=1, sample=("ico", 4),
+               cmp_eps=1e-4),
     "icosphere6_slp_dlp": dict(desc="icosphere level 6 (n=81920 centroids), single layer 1/(4 pi |x-y|) times double layer "
                     "(x-y).n_y/(4 pi |x-y|^3), leaf 64, eta 1, Chebyshev order 4 (k=64), eps 1e-4",
                eps=1e-4, geom=("ico", 6), kernel=1, leaf=64, order=4, eta=1.0, diag=1, dlp=True,
@@ -176,34 +179,62 @@ def roofline(names, r, steps, workload):
     return roof
 
 
-def cpu_baseline(h2, ctx, cfg, gpu_flops_alg):
-    """The oracle (test infrastructure, untuned) on the host cores, on a bounded sample."""
+ORACLE_SCALING = os.path.join(ROOT, "profiles", "oracle_icosphere5_slp.md")
+
+
+def _oracle_time(cfg, geom, threads=1):
+    """Seconds of one full oracle product (test infrastructure, untuned) of
+    the workload's construction on `geom`, with `threads` BLAS threads."""
     import oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max((p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"), default=1)
-    except Exception:  # threadpoolctl missing: report the visible cores
-        cores = os.cpu_count() or 1
-    geom = cfg["sample"] or cfg["geom"]
+    from threadpoolctl import threadpool_limits
     P, nrm = geometry(geom)
     T = O.ClusterTree(P, cfg["leaf"])
     A = O.build_interpolated(T, cfg["kernel"], cfg["order"], cfg["eta"], diag=cfg["diag"], normals=nrm)
     B = O.build_interpolated(T, O.KERNEL_DLP, cfg["order"], cfg["eta"], normals=nrm) if cfg.get("dlp") else A
-    t0 = time.perf_counter()
-    O.mul(A, B, cfg["eps"])
-    dt = time.perf_counter() - t0
-    scale = 1.0
-    if cfg["sample"]:
-        _, As, Bs = build(h2, ctx, cfg, cfg["sample"])
-        _, ss = h2.mul(ctx, As, Bs, cfg["eps"])
-        scale = ss["flops_alg"] / gpu_flops_alg
-        sample = (f"full oracle product of the same construction at icosphere level {geom[1]} (n={len(P)}), "
-                  f"{dt:.1f} s, scaled by the ratio {scale:.4f} of the library's algorithmic flops "
-                  f"(n={len(P)} over the timed workload)")
-    else:
-        sample = f"full oracle product of the timed workload, {dt:.1f} s"
-    return {"value": scale / dt, "unit": "products/s", "cores": int(cores), "kind": "oracle", "sample": sample,
-            "seconds": dt}
+    with threadpool_limits(limits=threads, user_api="blas"):
+        t0 = time.perf_counter()
+        O.mul(A, B, cfg["eps"])
+        return time.perf_counter() - t0, len(P)
+
+
+def _oracle_scaling():
+    """The oracle's own ratio of its time on the timed workload to its time on
+    the sample, measured once in full on one core (bench.py --oracle-scaling),
+    as recorded in the profiles folder (a JSON line)."""
+    try:
+        for line in open(ORACLE_SCALING):
+            line = line.strip()
+            if line.startswith("{") and '"t_full_s"' in line:
+                return json.loads(line)
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(cfg, workload):
+    """The oracle (test infrastructure, untuned) on the host, one BLAS thread
+    (its many small factorizations run fastest that way), on a bounded sample:
+    the full oracle product of the same construction one refinement level
+    lower, scaled to the timed workload by the oracle's own measured time
+    ratio between the two (recorded from a full run of both on one core);
+    the small grid workload runs in full."""
+    geom = cfg["sample"] or cfg["geom"]
+    dt, n = _oracle_time(cfg, geom)
+    if not cfg["sample"]:
+        return {"value": 1.0 / dt, "unit": "products/s", "cores": 1, "kind": "oracle",
+                "sample": f"full oracle product of the timed workload, {dt:.1f} s", "seconds": dt}
+    rec = _oracle_scaling() if workload == "icosphere5_slp" else None
+    if rec is None:
+        return {"value": None, "unit": "products/s", "cores": 1, "kind": "oracle",
+                "sample": f"full oracle product at icosphere level {geom[1]} (n={n}), {dt:.1f} s; no recorded "
+                          f"scaling to the timed workload", "seconds": dt}
+    ratio = rec["t_full_s"] / rec["t_sample_s"]
+    return {"value": 1.0 / (dt * ratio), "unit": "products/s", "cores": 1, "kind": "oracle",
+            "sample": f"full oracle product of the same construction at icosphere level {geom[1]} (n={n}), "
+                      f"{dt:.1f} s on one core, scaled by the oracle's own time ratio {ratio:.1f} of the timed "
+                      f"workload to this sample (both measured in full on one core of {rec['host_cpu']}: "
+                      f"{rec['t_full_s']:.0f} s and {rec['t_sample_s']:.1f} s)",
+            "seconds": dt, "full_product_seconds_recorded": rec["t_full_s"]}
 
 
 def global_error(h2, ctx, A, B, n, eps, prec, iters=10):
@@ -469,6 +500,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="icosphere5_slp", choices=sorted(WORKLOADS) + ["batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-scaling", action="store_true",
+                    help="time the full oracle product on the sample and on the workload (one core), print "
+                         "the JSON line the cpu_baseline scaling reads, and exit (takes minutes)")
     ap.add_argument("--fp64-only", action="store_true")
     ap.add_argument("--no-global-error", action="store_true",
                     help="skip the untimed power-iteration error (profiled runs: only the products' kernels)")
@@ -500,6 +534,21 @@ def main():
         print(json.dumps({"error": "the product runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.oracle_scaling:
+        import platform
+        cfg = WORKLOADS[args.workload]
+        ts, ns = _oracle_time(cfg, cfg["sample"])
+        say(f"oracle sample (n={ns}): {ts:.1f} s")
+        tf, nf = _oracle_time(cfg, cfg["geom"])
+        say(f"oracle full workload (n={nf}): {tf:.1f} s")
+        model = platform.machine()
+        try:
+            model = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        print(json.dumps({"workload": args.workload, "t_sample_s": ts, "n_sample": ns, "t_full_s": tf, "n_full": nf,
+                          "blas_threads": 1, "host_cpu": model, "host_cpus_visible": os.cpu_count()}), flush=True)
+        return
     from paper_2403_01566_amd import h2
     if args.serve:
         print(json.dumps(run_serve(h2, args)), flush=True)
@@ -519,11 +568,21 @@ def main():
     ctx = h2.Context(0)
     say(f"building operands: {cfg['desc']}")
     T, A, B = build(h2, ctx, cfg)
-    modes = [("fp64", h2.PREC_FP64)] + ([] if args.fp64_only else [("fp32_bulk", h2.PREC_FP32_BULK)])
+    # headline: plain FP64 at the workload's eps.  The library runs the FP32
+    # bulk only at eps >= 1e-5, so the FP32-bulk / FP64-recompression form is
+    # compared with plain FP64 on the same operands at a looser eps.
+    modes = [("fp64", h2.PREC_FP64, eps)]
+    cmp_eps = cfg.get("cmp_eps")
+    if not args.fp64_only:
+        if cmp_eps:
+            modes += [("fp64_cmp", h2.PREC_FP64, cmp_eps), ("fp32_bulk_cmp", h2.PREC_FP32_BULK, cmp_eps)]
+        else:
+            modes += [("fp32_bulk", h2.PREC_FP32_BULK, eps)]
     res = {}
-    for name, prec in modes:
-        say(f"timing {name}: {args.warmup} warmup + {args.steps} steps")
-        res[name] = run_mode(h2, ctx, A, B, eps, prec, args.steps, args.warmup)
+    for name, prec, e in modes:
+        say(f"timing {name} (eps {e}): {args.warmup} warmup + {args.steps} steps")
+        res[name] = run_mode(h2, ctx, A, B, e, prec, args.steps, args.warmup)
+        res[name]["eps"] = e
         say(f"{name}: {1000.0 * res[name]['total'] / args.steps:.1f} ms per product")
     head = "fp32_bulk" if "fp32_bulk" in res and res["fp32_bulk"]["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"
     r = res[head]
@@ -565,17 +624,19 @@ def main():
                                / max(1e-12, r["t_k"][i] / args.steps * 1e-3)}
                     for i in range(len(names)) if r["cnt"]["launches_kernel"][i]},
         "headline_mode": head,
-        "modes": {name: {"products_per_s": args.steps / x["total"],
+        "modes": {name: {"eps": x["eps"], "products_per_s": args.steps / x["total"],
                          "ms_per_step": 1000.0 * x["total"] / args.steps,
-                         "precision_used": "fp32_bulk" if x["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64"}
+                         "precision_used": "fp32_bulk" if x["st"]["prec_used"] == h2.PREC_FP32_BULK else "fp64",
+                         "rank_max": [x["st"]["rank_max_row"], x["st"]["rank_max_col"]],
+                         "roofline": roofline(names, x, args.steps, args.workload if name == head else None)}
                   for name, x in res.items()},
     }
     if not args.no_global_error:
         say("global error of one product (10 power-iteration steps, untimed)")
         out["global_error"] = global_error(h2, ctx, A, B, int(T.n), eps, st["prec_used"])
     if not args.no_cpu_baseline:
-        say("oracle on the host cores (bounded sample)")
-        out["cpu_baseline"] = cpu_baseline(h2, ctx, cfg, st["flops_alg"])
+        say("oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.workload)
     print(json.dumps(out), flush=True)
 
 

@@ -457,11 +457,17 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
 
 int size_classes(int wmax) { return wmax > 64 ? 3 : (wmax > 32 ? 2 : 1); }
 
+#ifndef H2_QR32_NT
+#define H2_QR32_NT 128
+#endif
+#ifndef H2_QR64_NT
+#define H2_QR64_NT 256
+#endif
 void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s) {
   if (ntasks <= 0) return;
   // each workgroup exits unless its task's effective width falls into the class
-  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, 128>), dim3(ntasks), dim3(128), 0, s, tasks, 0);
-  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, 256>), dim3(ntasks), dim3(256), 0, s, tasks, 32);
+  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, H2_QR32_NT>), dim3(ntasks), dim3(H2_QR32_NT), 0, s, tasks, 0);
+  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, H2_QR64_NT>), dim3(ntasks), dim3(H2_QR64_NT), 0, s, tasks, 32);
   if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
 }
 

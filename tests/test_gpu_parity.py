@@ -231,6 +231,7 @@ CASES = [
     ("sphere3", 1e-4, 1),
     ("sphere4", 1e-6, 0),
     ("sphere4", 1e-4, 0),
+    ("sphere4", 1e-4, 1),
     ("sphere2dlp", 1e-4, 0),
     ("sphere2dlp", 1e-4, 1),
     ("random2d", 1e-5, 0),
