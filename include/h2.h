@@ -120,6 +120,11 @@ typedef struct {
                           whose Jacobi still rotates after the cap makes the product fail
                           with H2_ERR_NOT_CONVERGED instead of returning vectors that are
                           not singular vectors.                                          */
+  int chunks;          /* 0: automatic.  The exact product and the coarsening run in this
+                          many chunks of result-block subtrees, one after the other, so
+                          that a chunk's workspace is reused by the next (same arithmetic,
+                          more launches).  Automatic: one chunk while the plan's
+                          workspace fits the device, else 4, 16, ... chunks.            */
 } h2_mul_options;
 
 /* Number of kernels in the per-kernel statistics; h2_kernel_name(i) names kernel i. */

@@ -218,6 +218,7 @@ struct Plan {
   int qrcp = 1;  // pivoted-QR rank reveal before the Jacobi (square SVDs)
   double budget[3] = {0.25, 0.25, 0.25};
   int sweeps = 40;  // Jacobi sweep cap of the SVD descriptors
+  int nchunk = 1;   // chunks of the exact product and coarsening (memory)
   int64_t launches = 0;
   int max_coarse_K = 0;
   // per kernel (h2k::KernelId): device ms, launches; algorithmic units, flops, bytes
@@ -454,6 +455,23 @@ struct FB {
 };
 
 // ------------------------------------------------------------------ planner
+// A node of the merge tree below an admissible result leaf (coarsening):
+// a final node of the induced tree (exact factors U, Z) or a merge of two
+// children.
+struct MNode {
+  int t = 0, r = 0, m = 0, n = 0, K = 0, height = 0, below = -1, unode = -1;
+  int c0 = -1, c1 = -1;  // merged children (MNode indices), -1 for leaves
+  // dense leaf forms: U = I (uI) or Z = I (zI); the identity factor is never
+  // formed and the steps that would multiply by it are skipped
+  bool uI = false, zI = false;
+  // dense leaf block of at most 128 x 128: the left singular vectors U^ of
+  // G come straight from the SVD of G (no QR, no Y = G^ V_k orthonormalisation)
+  bool direct = false;
+  int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
+          Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
+  int64_t Wsum = -1;  // merge: packed width kappa_a + kappa_b (device int)
+};
+
 class Planner {
  public:
   Context* ctx;
@@ -471,6 +489,24 @@ class Planner {
   int kc, kcap;  // result rank cap, coarsened rank cap
   std::vector<std::map<int, int64_t>> row_proj, col_proj;
   std::vector<int> bnode;  // admissible result leaf -> union node rooting its coarsening
+  // chunks of the exact product and coarsening (memory): union node -> chunk
+  // (-1: above chunk_depth), admissible result leaf -> chunk (-1: rooted above)
+  int nchunk = 1, chunk_depth = 0;
+  std::vector<int> uchunk, bchunk;
+  void assign_chunks(int nch);
+  // merge trees of the coarsening
+  std::vector<MNode> mn;
+  std::vector<int> of_un;
+  std::vector<std::pair<int, int>> dense_asm;  // (MNode, union node of the result leaf)
+  int maxh = 0;
+  std::map<int, int> hmax;
+  std::map<int, double> barea;
+  std::map<int, int64_t> tau;
+  double share(const MNode& x) { return std::sqrt((double)x.m * x.n / barea[x.below]) / (hmax[x.below] + 1); }
+  int group_of(const MNode& x) const { return x.below < 0 ? 0 : bchunk[C.nodes[x.below].leaf_index] + 1; }
+  void coarsen_prepare();
+  void coarsen_group(int g);
+  void coarsen_finish();
 
   Planner(Context* c, Matrix* x, Matrix* y, Plan& p, int kc_, int kcap_)
       : ctx(c), X(x), Y(y), TI(*x->rows), TJ(*x->cols), TK(*y->cols), kX(x->kc), kY(y->kc), P(p), B(p),
@@ -483,8 +519,8 @@ class Planner {
 
   void build_union();
   template <typename T>
-  void phaseA();
-  void coarsen();
+  void phaseA();  // exact product, leaf forms and (per chunk) the coarsening
+  void coarsen();  // the coarsening alone (recompression)
   void bases();
   void couplings();
 };
@@ -918,38 +954,72 @@ void Planner::phaseA() {
     }
   }
   // ---------------- union tree: accumulators, top-down per depth ----------------
+  // Chunks (memory): the union nodes at depth >= chunk_depth form nchunk
+  // groups of whole subtrees.  Each chunk runs its exact product, the leaf
+  // forms of its final nodes and the coarsening of the result blocks that
+  // lie inside it before the next chunk starts, so the workspace of a chunk
+  // is reused by the next (buffers share memory by lifetime).  Result blocks
+  // rooted above chunk_depth ("top" blocks) collect their final forms from
+  // every chunk and are coarsened last.  One chunk reproduces the unchunked
+  // order.  The arithmetic of every task is the same either way.
   B.phase = PH_EXACT;
   const int kU = kY + kX;
-  // final forms; their buffers form one allocation (one conversion in FP32 bulk)
-  int64_t fin_first = -1, fin_last = -1;
-  int64_t fin_used = 0;
-  auto fin_alloc = [&](int64_t n) {  // offset inside the region (pass 1: sizes only)
-    const int64_t o = fin_used;
-    fin_used += (std::max<int64_t>(n, 1) + (isf ? 63 : 31)) & ~int64_t(isf ? 63 : 31);
+  const int ngroup = nchunk + 1;  // group g = chunk g - 1, group 0 = top
+  auto group_of_block = [&](int below) { return below < 0 ? 0 : bchunk[C.nodes[below].leaf_index] + 1; };
+  // final forms of each group's blocks: one allocation per group (one
+  // conversion per group in FP32 bulk), offsets inside it (pass 1: sizes)
+  std::vector<int64_t> fin_used(ngroup, 0), fin_first(ngroup, -1), fin64(ngroup, -1);
+  std::vector<int> fgroup(un.size(), -1);
+  auto fin_alloc = [&](int g, int64_t n) {
+    const int64_t o = fin_used[g];
+    fin_used[g] += (std::max<int64_t>(n, 1) + (isf ? 63 : 31)) & ~int64_t(isf ? 63 : 31);
     return o;
   };
-  for (auto& u : un) {
+  for (size_t i = 0; i < un.size(); ++i) {
+    UNode& u = un[i];
     if (!u.fin) continue;
     const int64_t m = TI.size(u.t), n = TK.size(u.r);
     if (u.tc >= 0 && C.nodes[u.tc].kind == BK_INADM) {
       u.form = 4;
-    } else if (u.hasN || std::min(m, n) < kU) {
+      continue;
+    }
+    const int g = fgroup[i] = group_of_block(u.below);
+    if (u.hasN || std::min(m, n) < kU) {
       u.form = (m >= n) ? 2 : 3;
-      u.offG = fin_alloc(m * n);
+      u.offG = fin_alloc(g, m * n);
     } else {
       u.form = 1;
-      u.offG = fin_alloc(m * kU);
-      u.offZa = fin_alloc(n * kU);
+      u.offG = fin_alloc(g, m * kU);
+      u.offZa = fin_alloc(g, n * kU);
     }
   }
-  if (fin_used > 0) {
-    fin_first = W(fin_used).off;
-    fin_last = fin_first + fin_used;
-    for (auto& u : un) {
-      if (!u.fin || u.form == 4) continue;
-      u.offG += fin_first;
-      if (u.form == 1) u.offZa += fin_first;
+  for (int g = 0; g < ngroup; ++g) {
+    if (fin_used[g] == 0) continue;
+    fin_first[g] = W(fin_used[g]).off;
+    fin64[g] = isf ? B.wd(fin_used[g]).off : fin_first[g];  // FP64 copy of the region (FP32 bulk)
+  }
+  for (size_t i = 0; i < un.size(); ++i) {
+    UNode& u = un[i];
+    if (!u.fin || u.form == 4) continue;
+    const int g = fgroup[i];
+    const int64_t shift = fin64[g];
+    u.m = (int)TI.size(u.t);
+    u.n = (int)TK.size(u.r);
+    if (u.form == 1) {
+      u.K = kU;
+      u.U = u.offG + shift;
+      u.Z = u.offZa + shift;
+      u.offZa += fin_first[g];
+    } else if (u.form == 2) {  // U = G, Z = I
+      u.K = u.n;
+      u.U = u.offG + shift;
+      u.Z = -2;
+    } else {  // U = I, Z = G^T
+      u.K = u.m;
+      u.U = -2;
+      u.Z = u.offG + shift;
     }
+    u.offG += fin_first[g];
   }
   int maxdep = 0;
   for (auto& u : un) {
@@ -968,16 +1038,37 @@ void Planner::phaseA() {
     if (u.parent >= 0 && un[u.parent].hasC && u.hasC && u.t != un[u.parent].t) u.offTmp = W(kk).off;
     if (u.fin && u.hasC && u.form != 1) u.offVC = W(m * kY).off;
   }
-  for (int d = 0; d <= maxdep; ++d) {
+  // result nearfield (inadmissible leaves of the result tree)
+  P.cnoff.assign(C.inadm.size() + 1, 0);
+  int64_t noff = 0;
+  for (size_t i = 0; i < C.inadm.size(); ++i) {
+    P.cnoff[i] = noff;
+    const auto& nd = C.nodes[C.inadm[i]];
+    noff += TI.size(nd.t) * TK.size(nd.s);
+  }
+  P.cnoff[C.inadm.size()] = noff;
+  P.cnsize = noff;
+  P.res_N = B.wd(noff);
+  DRef<T> nearT;
+  if constexpr (isf) nearT = W(noff);
+  else nearT = P.res_N;
+  // the merge trees of the coarsening (their buffers are placed as the
+  // groups' steps are emitted)
+  coarsen_prepare();
+
+  // steps of the exact product at depth d for the union nodes of chunk c (-1: above the chunks)
+  auto exact_depth = [&](int d, int c) {
     GW<T> g1 = newstep();
-    for (auto& u : un) {
-      if (u.depth != d || u.offTmp < 0) continue;
+    for (size_t i = 0; i < un.size(); ++i) {
+      const UNode& u = un[i];
+      if (u.depth != d || uchunk[i] != c || u.offTmp < 0) continue;
       g1.task(R(u.offTmp), kY, kX, kY);
       g1.mm(VX.E(u.t), kX, R(un[u.parent].offC), kY, kX);
     }
     GW<T> g2 = newstep();
-    for (auto& u : un) {
-      if (u.depth != d) continue;
+    for (size_t i = 0; i < un.size(); ++i) {
+      const UNode& u = un[i];
+      if (u.depth != d || uchunk[i] != c) continue;
       const int t = u.t, r = u.r;
       const int64_t m = TI.size(t), n = TK.size(r);
       const UNode* p = u.parent >= 0 ? &un[u.parent] : nullptr;
@@ -1028,32 +1119,21 @@ void Planner::phaseA() {
         }
       }
     }
-  }
-  // ---------------- leaf blocks of the induced tree ----------------
-  B.phase = PH_LEAF;
-  P.cnoff.assign(C.inadm.size() + 1, 0);
-  int64_t noff = 0;
-  for (size_t i = 0; i < C.inadm.size(); ++i) {
-    P.cnoff[i] = noff;
-    const auto& nd = C.nodes[C.inadm[i]];
-    noff += TI.size(nd.t) * TK.size(nd.s);
-  }
-  P.cnoff[C.inadm.size()] = noff;
-  P.cnsize = noff;
-  P.res_N = B.wd(noff);
-  DRef<T> nearT;
-  if constexpr (isf) nearT = W(noff);
-  else nearT = P.res_N;
-  {
+  };
+  // leaf forms of the final nodes of chunk c (-1: above the chunks)
+  auto leaf_forms = [&](int c) {
+    B.phase = PH_LEAF;
     GW<T> g1 = newstep();
-    for (auto& u : un) {
-      if (u.offVC < 0) continue;
+    for (size_t i = 0; i < un.size(); ++i) {
+      const UNode& u = un[i];
+      if (u.offVC < 0 || uchunk[i] != c) continue;
       g1.task(R(u.offVC), kY, (int)TI.size(u.t), kY);
       g1.mm(VX.full(u.t), kX, R(u.offC), kY, kX);
     }
     GW<T> g2 = newstep();
-    for (auto& u : un) {
-      if (!u.fin) continue;
+    for (size_t i = 0; i < un.size(); ++i) {
+      const UNode& u = un[i];
+      if (!u.fin || uchunk[i] != c) continue;
       const int t = u.t, r = u.r;
       const int64_t m = TI.size(t), n = TK.size(r);
       if (u.form == 1) {
@@ -1083,18 +1163,29 @@ void Planner::phaseA() {
         if (u.hasN) g2.copy(R(u.offN), (int)n, h2k::IT_TRANS_A);
       }
     }
-  }
-  // ---------------- hand over to the FP64 recompression ----------------
-  int64_t shift = 0;
-  if constexpr (isf) {
-    if (fin_last > fin_first && fin_first >= 0) {
-      DRef<double> d64 = B.wd(fin_last - fin_first);
-      shift = d64.off - fin_first;
-      Step& st = B.step(SK_CVT_F2D);
-      st.cvt_in = Tw<float>(fin_first);
-      st.cvt_out = d64;
-      st.cvt_n = fin_last - fin_first;
+  };
+  // FP32 bulk: the group's final forms handed over to the FP64 recompression
+  auto hand_over = [&](int g) {
+    if constexpr (isf) {
+      if (fin_used[g] > 0) {
+        Step& st = B.step(SK_CVT_F2D);
+        st.cvt_in = Tw<float>(fin_first[g]);
+        st.cvt_out = Dw(fin64[g]);
+        st.cvt_n = fin_used[g];
+      }
     }
+  };
+  for (int d = 0; d < chunk_depth; ++d) exact_depth(d, -1);
+  for (int c = 0; c < nchunk; ++c) {
+    B.phase = PH_EXACT;
+    for (int d = chunk_depth; d <= maxdep; ++d) exact_depth(d, c);
+    leaf_forms(c);
+    hand_over(c + 1);
+    coarsen_group(c + 1);
+  }
+  leaf_forms(-1);
+  hand_over(0);
+  if constexpr (isf) {
     if (noff > 0) {
       Step& st = B.step(SK_CVT_F2D);
       st.cvt_in = nearT;
@@ -1102,50 +1193,22 @@ void Planner::phaseA() {
       st.cvt_n = noff;
     }
   }
-  for (auto& u : un) {
-    if (!u.fin || u.form == 4 || u.below < 0) continue;
-    const int64_t m = TI.size(u.t), n = TK.size(u.r);
-    u.m = (int)m;
-    u.n = (int)n;
-    if (u.form == 1) {
-      u.K = kU;
-      u.U = u.offG + shift;
-      u.Z = u.offZa + shift;
-    } else if (u.form == 2) {  // U = G, Z = I
-      u.K = (int)n;
-      u.U = u.offG + shift;
-      u.Z = -2;
-    } else {  // U = I, Z = G^T
-      u.K = (int)m;
-      u.U = -2;
-      u.Z = u.offG + shift;
-    }
-  }
+  coarsen_group(0);
+  coarsen_finish();
 }
 
 // ------------------------------------------------------------------ coarsening
-void Planner::coarsen() {
-  B.phase = PH_COARSE;
+// Merge trees of all admissible result leaves (host only; the steps are
+// emitted per group by coarsen_group).
+void Planner::coarsen_prepare() {
   // Merge tree below every admissible result leaf: the leaves are the final
   // nodes of the induced tree (exact factors U, Z); every split node of the
   // induced tree merges its children pairwise (first the column pairs of
   // each row child, then the rows), so a merge never joins more than two
   // truncated pieces (width <= 2 * kcap).
-  struct MNode {
-    int t = 0, r = 0, m = 0, n = 0, K = 0, height = 0, below = -1, unode = -1;
-    int c0 = -1, c1 = -1;  // merged children (MNode indices), -1 for leaves
-    // dense leaf forms: U = I (uI) or Z = I (zI); the identity factor is never
-    // formed and the steps that would multiply by it are skipped
-    bool uI = false, zI = false;
-    // dense leaf block of at most 128 x 128: the left singular vectors U^ of
-    // G come straight from the SVD of G (no QR, no Y = G^ V_k orthonormalisation)
-    bool direct = false;
-    int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
-            Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
-    int64_t Wsum = -1;  // merge: packed width kappa_a + kappa_b (device int)
-  };
-  std::vector<MNode> mn;
-  std::vector<int> of_un(un.size(), -1);
+  mn.clear();
+  dense_asm.clear();
+  of_un.assign(un.size(), -1);
   std::function<int(int)> make = [&](int ui) -> int {
     UNode& u = un[ui];
     MNode x;
@@ -1193,7 +1256,6 @@ void Planner::coarsen() {
   // Result blocks of at most 128 x 128 whose induced sub-blocks are finer are
   // assembled densely from their exact pieces and truncated once (a direct
   // SVD of the block instead of a merge tree of small truncations).
-  std::vector<std::pair<int, int>> dense_asm;  // (MNode, union node of the result leaf)
   for (size_t li = 0; li < C.adm.size(); ++li) {
     UNode& u = un[bnode[li]];
     const int m = (int)TI.size(u.t), n = (int)TK.size(u.r);
@@ -1215,23 +1277,7 @@ void Planner::coarsen() {
     of_un[bnode[li]] = (int)mn.size() - 1;
     dense_asm.push_back({(int)mn.size() - 1, bnode[li]});
   }
-  if (!dense_asm.empty()) {
-    GW<double> g(B.step(SK_GEMM_D));
-    std::function<void(const MNode&, int)> add = [&](const MNode& x, int ui) {
-      const UNode& f = un[ui];
-      if (!f.fin) {
-        for (int c = 0; c < f.nchild; ++c) add(x, f.child0 + c);
-        return;
-      }
-      const int64_t ro = TI.begin[f.t] - TI.begin[x.t], co = TK.begin[f.r] - TK.begin[x.r];
-      g.task(Dw(x.U) + ro * x.n + co, x.n, f.m, f.n);
-      if (f.form == 1) g.mm(Dw(f.U), f.K, Dw(f.Z), f.K, f.K, h2k::IT_TRANS_B);
-      else if (f.form == 2) g.copy(Dw(f.U), f.K);
-      else g.copy(Dw(f.Z), f.K, h2k::IT_TRANS_A);
-    };
-    for (auto& d : dense_asm) add(mn[d.first], d.second);
-  }
-  int maxh = 0;
+  maxh = 0;
   for (auto& x : mn) maxh = std::max(maxh, x.height);
   if (std::getenv("H2_TRACE")) {  // shape summary of the merge tree
     std::map<std::tuple<int, int, int, int>, int> hist;  // (height, m bucket, n bucket, K)
@@ -1250,22 +1296,46 @@ void Planner::coarsen() {
   // a lower bound of ||G_b|| held on the device: first the largest row or
   // column norm of the leaves' condensed factors, raised after every height
   // by the largest singular values of that height's merged sub-blocks.
-  std::map<int, int> hmax;
-  std::map<int, double> barea;
+  hmax.clear();
+  barea.clear();
+  tau.clear();
   for (auto& x : mn) {
     hmax[x.below] = std::max(hmax[x.below], x.height);
     barea[x.below] = std::max(barea[x.below], (double)x.m * x.n);
   }
-  std::map<int, int64_t> tau;
   for (auto& kv : hmax) tau[kv.first] = B.wd(1).off;
-  auto share = [&](const MNode& x) {
-    return std::sqrt((double)x.m * x.n / barea[x.below]) / (hmax[x.below] + 1);
-  };
   P.max_coarse_K = 0;
+}
+
+// Steps of the coarsening of the result blocks of group g (0: blocks rooted
+// above the chunks, c + 1: chunk c), after the group's final forms exist.
+void Planner::coarsen_group(int grp) {
+  B.phase = PH_COARSE;
+  {  // dense assembly of the group's small blocks
+    bool any = false;
+    for (auto& d : dense_asm) any |= group_of(mn[d.first]) == grp;
+    if (any) {
+      GW<double> g(B.step(SK_GEMM_D));
+      std::function<void(const MNode&, int)> add = [&](const MNode& x, int ui) {
+        const UNode& f = un[ui];
+        if (!f.fin) {
+          for (int c = 0; c < f.nchild; ++c) add(x, f.child0 + c);
+          return;
+        }
+        const int64_t ro = TI.begin[f.t] - TI.begin[x.t], co = TK.begin[f.r] - TK.begin[x.r];
+        g.task(Dw(x.U) + ro * x.n + co, x.n, f.m, f.n);
+        if (f.form == 1) g.mm(Dw(f.U), f.K, Dw(f.Z), f.K, f.K, h2k::IT_TRANS_B);
+        else if (f.form == 2) g.copy(Dw(f.U), f.K);
+        else g.copy(Dw(f.Z), f.K, h2k::IT_TRANS_A);
+      };
+      for (auto& d : dense_asm)
+        if (group_of(mn[d.first]) == grp) add(mn[d.first], d.second);
+    }
+  }
   for (int h = 0; h <= maxh; ++h) {
     std::vector<int> lv;
     for (size_t i = 0; i < mn.size(); ++i)
-      if (mn[i].height == h) lv.push_back((int)i);
+      if (mn[i].height == h && group_of(mn[i]) == grp) lv.push_back((int)i);
     if (lv.empty()) continue;
     if (h > 0) {  // U = [ext(U^_a S_a), ext(U^_b S_b)],  Z = [ext(V^_a), ext(V^_b)]
       for (int i : lv) {
@@ -1563,7 +1633,10 @@ void Planner::coarsen() {
       }
     }
   }
-  // outputs of each block's root merge, used by the basis construction
+}
+
+// Outputs of each block's root merge, used by the basis construction.
+void Planner::coarsen_finish() {
   for (size_t li = 0; li < C.adm.size(); ++li) {
     UNode& u = un[bnode[li]];
     const MNode& x = mn[of_un[bnode[li]]];
@@ -1573,6 +1646,49 @@ void Planner::coarsen() {
     u.Sig = x.Sig;
     u.Kap = x.Kap;
   }
+}
+
+// The whole coarsening in one group (no exact product before it).
+void Planner::coarsen() {
+  assign_chunks(1);
+  coarsen_prepare();
+  for (int g = nchunk; g >= 0; --g) coarsen_group(g);
+  coarsen_finish();
+}
+
+// Chunks of nch groups of union subtrees below the shallowest depth with at
+// least 4 nch union nodes (one chunk: every node, from the root).
+void Planner::assign_chunks(int nch) {
+  nchunk = std::max(1, nch);
+  uchunk.assign(un.size(), 0);
+  bchunk.assign(C.adm.size(), 0);
+  chunk_depth = 0;
+  if (nchunk > 1) {
+    std::map<int, int> per_depth;
+    for (auto& u : un) per_depth[u.depth]++;
+    chunk_depth = -1;
+    for (auto& kv : per_depth)
+      if (kv.second >= 4 * nchunk) {
+        chunk_depth = kv.first;
+        break;
+      }
+    if (chunk_depth < 0) {  // too few nodes for chunks
+      nchunk = 1;
+      chunk_depth = 0;
+    }
+  }
+  if (nchunk > 1) {
+    int count = 0;
+    for (auto& u : un) count += u.depth == chunk_depth;
+    int seen = 0;
+    for (size_t i = 0; i < un.size(); ++i) {  // parents come before their children
+      const UNode& u = un[i];
+      if (u.depth < chunk_depth) uchunk[i] = -1;
+      else if (u.depth == chunk_depth) uchunk[i] = (int)((int64_t)(seen++) * nchunk / count);
+      else uchunk[i] = uchunk[u.parent];
+    }
+  }
+  for (size_t li = 0; li < C.adm.size(); ++li) bchunk[li] = bnode[li] >= 0 ? uchunk[bnode[li]] : -1;
 }
 
 // ------------------------------------------------------------------ adaptive bases
@@ -2387,14 +2503,14 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
   char* base = desc_base ? desc_base : (char*)P.desc.p;
   std::vector<hipEvent_t> ev;
   int cur_phase = -1;
-  if (timing) {
-    ev.resize(16);
-    for (auto& e : ev) H2_HIP(hipEventCreate(&e));
-  }
   std::vector<int> phase_mark;  // event index -> phase
   int nev = 0;
   auto mark = [&](int ph) {
     if (!timing) return;
+    if (nev == (int)ev.size()) {  // chunked plans change phase more often
+      ev.emplace_back();
+      H2_HIP(hipEventCreate(&ev.back()));
+    }
     H2_HIP(hipEventRecord(ev[nev], s));
     phase_mark.push_back(ph);
     ++nev;
@@ -2701,8 +2817,8 @@ static void quiesce(Context* ctx, Plan& P) {
   H2_HIP(hipStreamSynchronize(s));
 }
 
-static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
-                                       const h2_mul_options& opt, double eps) {
+static std::shared_ptr<Plan> make_plan_chunks(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
+                                              const h2_mul_options& opt, double eps, int nchunk) {
   auto P = std::make_shared<Plan>();
   P->f32 = f32;
   P->kc = kc;
@@ -2722,6 +2838,8 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   Planner pl(ctx, X, Y, *P, kc, kcap);
   Builder& B = pl.B;
   pl.build_union();
+  pl.assign_chunks(nchunk);
+  P->nchunk = pl.nchunk;
   // result arrays
   P->res_vleaf = B.wd(X->rows->n * kc);
   P->res_vtr = B.wd((int64_t)X->rows->ncl * kc * kc);
@@ -2738,10 +2856,8 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tp0).count());
   };
   ws("union");
-  if (f32) pl.phaseA<float>();
+  if (f32) pl.phaseA<float>();  // exact product, leaf forms and coarsening, chunk by chunk
   else pl.phaseA<double>();
-  ws("exact");
-  pl.coarsen();
   ws("coarsen");
   pl.bases();
   ws("bases");
@@ -2768,6 +2884,31 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   layout(*P);
   P->keep_protos = true;  // descriptors are emitted when the plan is bound to a lane
   ws("final");
+  return P;
+}
+
+// A plan whose workspace fits the device: one chunk first; while the
+// shared workspace exceeds what the device can hold (free memory plus the
+// lane arenas, which a plan's binding may replace, less a margin), the plan
+// is rebuilt with four times as many chunks (opt.chunks > 0 fixes the count).
+static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool f32, int kc, int kcap,
+                                       const h2_mul_options& opt, double eps) {
+  int nch = opt.chunks > 0 ? opt.chunks : 1;
+  auto P = make_plan_chunks(ctx, X, Y, f32, kc, kcap, opt, eps, nch);
+  if (opt.chunks > 0) return P;
+  size_t freeb = 0, total = 0;
+  H2_HIP(hipMemGetInfo(&freeb, &total));
+  size_t held = 0;
+  for (auto& l : ctx->lanes) held += l->arena.bytes;
+  // room for the result, operands and allocator granularity: 15 % of the memory
+  const size_t budget = (freeb + held) / 20 * 17;
+  while (P->ws_bytes > budget && nch < 256 && P->nchunk == nch) {
+    nch *= 4;
+    if (std::getenv("H2_TRACE"))
+      std::fprintf(stderr, "[h2 plan] workspace %.1f GB above the budget %.1f GB: %d chunks\n", P->ws_bytes * 1e-9,
+                   budget * 1e-9, nch);
+    P = make_plan_chunks(ctx, X, Y, f32, kc, kcap, opt, eps, nch);
+  }
   return P;
 }
 
@@ -3297,7 +3438,8 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   J->key = std::make_pair(X->id, Y->id * 4 + (f32 ? 1 : 0));
   auto it = ctx->plans.find(J->key);
   if (it != ctx->plans.end() && it->second->kc == kc && it->second->kappa_cap == kcap &&
-      it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta)) {
+      it->second->theta == (opt.theta > 0 ? opt.theta : it->second->theta) &&
+      (opt.chunks <= 0 || it->second->nchunk == opt.chunks)) {
     J->P = it->second;
   } else {
     if (it != ctx->plans.end()) quiesce(ctx, *it->second);

@@ -41,7 +41,7 @@ class MulOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("theta", C.c_double), ("budget_coarse", C.c_double),
                 ("budget_row", C.c_double), ("budget_col", C.c_double), ("max_rank", C.c_int),
                 ("coarse_rank", C.c_int), ("timing", C.c_int), ("graph", C.c_int),
-                ("jacobi_sweeps", C.c_int)]
+                ("jacobi_sweeps", C.c_int), ("chunks", C.c_int)]
 
 
 class MulStats(C.Structure):
