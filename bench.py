@@ -60,7 +60,7 @@ sys.path.insert(0, ROOT)
 METRIC = "H² products/s + roofline fraction at stated eps vs plain FP64; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6     # 256 CUs x 2.4 GHz x 128 FP64 flop/clk/CU (vector FMA and MFMA alike)
-ALU_KERNELS = ("qr_kernel", "svd_kernel", "chol_kernel")
+ALU_KERNELS = ("qr_kernel", "svd_kernel", "svd_narrow_kernel", "chol_kernel")
 
 WORKLOADS = {
     "grid32": dict(desc="32x32 grid in [0,1]^2, -log|x-y| (diag 0), leaf 32, eta 1/2, Chebyshev order 3 (k=9), "
@@ -235,6 +235,33 @@ def cpu_baseline(cfg, workload):
                       f"workload to this sample (both measured in full on one core of {rec['host_cpu']}: "
                       f"{rec['t_full_s']:.0f} s and {rec['t_sample_s']:.1f} s)",
             "seconds": dt, "full_product_seconds_recorded": rec["t_full_s"]}
+
+
+def hbm_probe(gib=4, reps=20):
+    """Rates that plain torch kernels reach on this device: a copy (read and
+    write), a sum (read) and a fill (write) of `gib` GiB of float64, each the
+    mean of `reps` launches after 3 untimed ones.  Context for the GEMM's
+    fraction of the HBM peak."""
+    import torch
+    n = gib << 30
+    a = torch.ones(n // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"bytes": n}
+    for name, fn, moved in (("copy", lambda: b.copy_(a), 2 * n), ("sum", lambda: a.sum(), n),
+                            ("fill", lambda: b.fill_(1.0), n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "GB_per_s": moved / ms / 1e6}
+        say(f"{name}: {ms:.3f} ms, {moved / ms / 1e9:.2f} TB/s")
+    return out
 
 
 def global_error(h2, ctx, A, B, n, eps, prec, iters=10):
@@ -508,6 +535,8 @@ def main():
                     help="skip the untimed power-iteration error (profiled runs: only the products' kernels)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device once (HBM counter calibration)")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only time plain device copy, sum and fill over 4 GiB (practical HBM rates)")
     ap.add_argument("--sweep", default="", metavar="LEVELS",
                     help="comma-separated icosphere levels: time per DOF, storage and error per n, then exit")
     ap.add_argument("--sweep-cube", default="", metavar="M",
@@ -529,6 +558,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": a.numel() * 8}), flush=True)
+        return
+    if args.hbm_probe:
+        print(json.dumps(hbm_probe()), flush=True)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "the product runs on one GPU; --gpus above 1 is not supported",

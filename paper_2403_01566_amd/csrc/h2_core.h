@@ -27,7 +27,8 @@ struct Error : std::runtime_error {
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \
     if (e_ != hipSuccess) {                                                                   \
-      if (e_ == hipErrorOutOfMemory) throw ::h2::Error(H2_ERR_OUT_OF_MEMORY, hipGetErrorString(e_)); \
+      if (e_ == hipErrorOutOfMemory)                                                          \
+        throw ::h2::Error(H2_ERR_OUT_OF_MEMORY, std::string(#call) + ": " + hipGetErrorString(e_)); \
       throw ::h2::Error(H2_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));    \
     }                                                                                         \
   } while (0)

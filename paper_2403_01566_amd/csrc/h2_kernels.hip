@@ -55,7 +55,7 @@ static_assert(GQA >= 1 && GQB >= 1 && GBM * GBK % 256 == 0 && GBK % 4 == 0, "GEM
 //
 // One workgroup (4 waves, each a 32 x 32 quarter) per 64 x 64 output tile.
 // The K dimension of all items of the task is walked as one sequence of
-// 16-wide slices: while the MFMAs consume slice s from one LDS buffer, the
+// GBK-wide slices: while the MFMAs consume slice s from one LDS buffer, the
 // global loads of slice s + 1 are in flight into registers and then land in
 // the other buffer, so each slice costs one barrier.  A wave whose quarter
 // lies outside the task's (device-side) size skips its MFMAs.

@@ -2393,6 +2393,17 @@ static void finalize(Plan& P, double eps) {
   emit(P, eps);
 }
 
+// Frees the arenas of the lanes other than `keep` that have no jobs in
+// flight (their plans are re-emitted at their next use).
+static void release_idle_arenas(Context* ctx, const LaneRes* keep) {
+  for (auto& o : ctx->lanes)
+    if (o.get() != keep && o->inflight == 0 && o->arena.p) {
+      for (hipStream_t s : {o->l.stream, o->l.aux[0], o->l.aux[1]}) H2_HIP(hipStreamSynchronize(s));
+      o->arena.release();
+      o->epoch = 0;
+    }
+}
+
 // A product plan bound to a lane: its workspaces are the lane's arena, grown
 // to the plan's size if needed (after the lane's work has finished; the
 // plans bound to it before are re-emitted at their next use). Only a plan
@@ -2407,16 +2418,17 @@ static void bind(Context* ctx, Plan& P, int lane, double eps) {
       LR.arena.alloc(P.ws_bytes);
     } catch (const Error& e) {
       if (e.code != H2_ERR_OUT_OF_MEMORY) throw;
-      // make room: the arenas of idle lanes go (their plans are re-emitted later)
-      for (auto& o : ctx->lanes)
-        if (o.get() != &LR && o->inflight == 0 && o->arena.p) {
-          for (hipStream_t s : {o->l.stream, o->l.aux[0], o->l.aux[1]}) H2_HIP(hipStreamSynchronize(s));
-          o->arena.release();
-          o->epoch = 0;
-        }
+      release_idle_arenas(ctx, &LR);
       LR.arena.alloc(P.ws_bytes);
     }
     LR.epoch = ++ctx->arena_epoch;
+  }
+  {
+    // the plan's descriptors and the result are allocated outside the arena:
+    // with less than a tenth of the device free, idle arenas make room
+    size_t freeb = 0, total = 0;
+    H2_HIP(hipMemGetInfo(&freeb, &total));
+    if (freeb < total / 10) release_idle_arenas(ctx, &LR);
   }
   if (P.bound_lane != lane || P.bound_epoch != LR.epoch || LR.epoch == 0 || !P.desc.p) {
     if (P.bound_lane != lane) {

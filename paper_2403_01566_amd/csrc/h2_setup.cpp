@@ -8,6 +8,7 @@
 // (eq. interpolation, vsw) with exact transfer matrices (eq. transfer).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -150,7 +151,23 @@ void build_block_tree(BlockTree& bt, const Tree& R, const Tree& C, double eta) {
 void DevBuf::alloc(size_t b) {
   release();
   if (b == 0) b = 256;
-  H2_HIP(hipMalloc(&p, b));
+  const hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    // the failure is reported by the exception; a caller may recover (free
+    // memory and try again), so it must not stay behind as the runtime's
+    // last error, which the launch checks read
+    (void)hipGetLastError();
+    p = nullptr;
+  }
+  if (e == hipErrorOutOfMemory) {
+    size_t freeb = 0, total = 0;
+    (void)hipMemGetInfo(&freeb, &total);
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "out of memory: a device allocation of %.3f GB failed (%.3f GB of %.3f GB free)",
+                  b * 1e-9, freeb * 1e-9, total * 1e-9);
+    throw Error(H2_ERR_OUT_OF_MEMORY, msg);
+  }
+  H2_HIP(e);
   bytes = b;
 }
 void DevBuf::release() {
