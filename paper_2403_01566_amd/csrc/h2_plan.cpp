@@ -45,6 +45,7 @@
 #include <set>
 #include <climits>
 #include <tuple>
+#include <unordered_map>
 #include <deque>
 #include <cstdio>
 #include <cstdlib>
@@ -2032,9 +2033,59 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
 // ------------------------------------------------------------------ workspace sharing
 // A workspace buffer lives from the first to the last step that refers to it
 // (steps run in order on one stream); buffers with disjoint lifetimes share
-// memory.  Buffers are placed in order of their first use, best fit into the
-// gaps left by buffers that died before it, else at the top.  The result
+// memory.  Buffers of equal lifetime form a group; groups are placed in order
+// of their first use, best fit into the gaps left by groups that died before
+// (a group that fits no gap buffer by buffer), else at the top.  The result
 // arrays stay live to the end (they are copied out after the product).
+// Calls f on every workspace reference of a step; refs of one vector are
+// visited in parallel when there are many (f must be safe for that).
+template <typename V, typename F>
+static void each_par(V& v, F&& f) {
+  const int64_t n = (int64_t)v.size();
+  if (n < 8192) {
+    for (auto& x : v) f(x);
+    return;
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) f(v[i]);
+}
+template <typename F>
+static void visit_refs_par(Step& st, F&& f) {
+  each_par(st.itd, [&](auto& x) {
+    f(x.a);
+    f(x.b);
+    f(x.scale);
+  });
+  each_par(st.tkd, [&](auto& x) { f(x.c); });
+  each_par(st.itf, [&](auto& x) {
+    f(x.a);
+    f(x.b);
+    f(x.scale);
+  });
+  each_par(st.tkf, [&](auto& x) { f(x.c); });
+  each_par(st.qr, [&](auto& x) {
+    f(x.a);
+    f(x.r);
+  });
+  each_par(st.svd, [&](auto& x) {
+    f(x.a);
+    f(x.u);
+    f(x.sigma);
+    f(x.u2);
+    f(x.tolref);
+  });
+  each_par(st.chol, [&](auto& x) {
+    f(x.g);
+    f(x.t);
+    f(x.r);
+  });
+  each_par(st.fill, [&](auto& x) { f(x.p); });
+  each_par(st.ref, [&](auto& x) { f(x.out); });
+  each_par(st.refmat, [&](auto& x) { f(x.a); });
+  f(st.cvt_in);
+  f(st.cvt_out);
+}
+
 template <typename F>
 static void visit_refs(Step& st, F&& f) {
   for (auto& x : st.itd) {
@@ -2096,17 +2147,55 @@ struct ArenaPlan {
     return (size_t)(it - base.begin()) - 1;
   }
   int64_t size(size_t i) const { return (i + 1 < base.size() ? base[i + 1] : total) - base[i]; }
+  // Steps are recorded in increasing order; the references of one step may
+  // be recorded from several threads, which all store the same step number.
   void use(int64_t off, int step) {
     if (base.empty()) return;
     const size_t i = find(off);
-    first[i] = std::min(first[i], step);
-    last[i] = std::max(last[i], step);
+    if (__atomic_load_n(&first[i], __ATOMIC_RELAXED) > step) __atomic_store_n(&first[i], step, __ATOMIC_RELAXED);
+    if (__atomic_load_n(&last[i], __ATOMIC_RELAXED) < step) __atomic_store_n(&last[i], step, __ATOMIC_RELAXED);
   }
+  // Buffers with the same lifetime (first and last step) form one group.
+  // Groups are placed in order of their first step: best fit of the whole
+  // group (its buffers contiguous, in index order) into the gaps left by
+  // groups that died before; a group that fits no gap places its buffers
+  // one by one, best fit each, else at the top.
   int64_t place() {
-    std::vector<size_t> order;
+    std::unordered_map<int64_t, int> gid;
+    std::vector<int> grp(base.size(), -1);
+    std::vector<int64_t> gsize;
+    std::vector<int> gfirst, glast;
+    const int64_t span = (int64_t)INT32_MAX + 1;
+    for (size_t i = 0; i < base.size(); ++i) {
+      if (last[i] < 0) continue;
+      const int64_t key = (int64_t)first[i] * span + last[i];
+      auto ins = gid.emplace(key, (int)gsize.size());
+      if (ins.second) {
+        gsize.push_back(0);
+        gfirst.push_back(first[i]);
+        glast.push_back(last[i]);
+      }
+      const int g = ins.first->second;
+      grp[i] = g;
+      placed[i] = gsize[g];  // offset inside the group while the group is whole
+      gsize[g] += size(i);
+    }
+    const size_t ng = gsize.size();
+    // members of each group, in index order
+    std::vector<int64_t> mbeg(ng + 1, 0);
     for (size_t i = 0; i < base.size(); ++i)
-      if (last[i] >= 0) order.push_back(i);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return first[a] < first[b]; });
+      if (grp[i] >= 0) ++mbeg[grp[i] + 1];
+    for (size_t g = 0; g < ng; ++g) mbeg[g + 1] += mbeg[g];
+    std::vector<size_t> mem(mbeg[ng]);
+    {
+      std::vector<int64_t> fill(mbeg.begin(), mbeg.end() - 1);
+      for (size_t i = 0; i < base.size(); ++i)
+        if (grp[i] >= 0) mem[fill[grp[i]]++] = i;
+    }
+    std::vector<size_t> order(ng);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return gfirst[a] < gfirst[b]; });
+    std::vector<int64_t> gplaced(ng, -1);  // -1: placed buffer by buffer
     std::map<int64_t, int64_t> byoff;                  // free gaps: offset -> size
     std::set<std::pair<int64_t, int64_t>> bysize;      // (size, offset)
     auto erase_gap = [&](std::map<int64_t, int64_t>::iterator g) {
@@ -2131,27 +2220,36 @@ struct ArenaPlan {
       byoff[off] = sz;
       bysize.emplace(sz, off);
     };
-    typedef std::pair<int, size_t> Live;  // (last step, allocation)
-    std::priority_queue<Live, std::vector<Live>, std::greater<Live>> live;
     int64_t top = 0;
-    for (size_t i : order) {
-      while (!live.empty() && live.top().first < first[i]) {
+    auto take = [&](int64_t need) -> int64_t {  // best fit, else the top
+      auto f = bysize.lower_bound({need, INT64_MIN});
+      if (f == bysize.end()) {
+        top += need;
+        return top - need;
+      }
+      const int64_t off = f->second, sz = f->first;
+      erase_gap(byoff.find(off));
+      if (sz > need) add_gap(off + need, sz - need);
+      return off;
+    };
+    typedef std::pair<int, size_t> Live;  // (last step, group)
+    std::priority_queue<Live, std::vector<Live>, std::greater<Live>> live;
+    for (size_t g : order) {
+      while (!live.empty() && live.top().first < gfirst[g]) {
         const size_t j = live.top().second;
         live.pop();
-        add_gap(placed[j], size(j));
+        if (gplaced[j] >= 0) add_gap(gplaced[j], gsize[j]);
+        else
+          for (int64_t q = mbeg[j]; q < mbeg[j + 1]; ++q) add_gap(placed[mem[q]], size(mem[q]));
       }
-      const int64_t need = size(i);
-      auto g = bysize.lower_bound({need, INT64_MIN});
-      if (g != bysize.end()) {
-        const int64_t off = g->second, sz = g->first;
-        erase_gap(byoff.find(off));
-        placed[i] = off;
-        if (sz > need) add_gap(off + need, sz - need);
+      const int64_t need = gsize[g];
+      if (bysize.empty() || bysize.rbegin()->first >= need) {
+        gplaced[g] = take(need);
+        for (int64_t q = mbeg[g]; q < mbeg[g + 1]; ++q) placed[mem[q]] += gplaced[g];
       } else {
-        placed[i] = top;
-        top += need;
+        for (int64_t q = mbeg[g]; q < mbeg[g + 1]; ++q) placed[mem[q]] = take(size(mem[q]));
       }
-      live.emplace(last[i], i);
+      live.emplace(glast[g], g);
     }
     return top;
   }
@@ -2163,6 +2261,8 @@ struct ArenaPlan {
 };
 
 static void share_workspace(Plan& P) {
+  const bool trace = std::getenv("H2_TRACE") != nullptr;
+  auto t0 = std::chrono::steady_clock::now();
   ArenaPlan ad(P.base_d, P.wsd), af(P.base_f, P.wsf);
   const int nst = (int)P.steps.size();
   int si = 0;
@@ -2172,9 +2272,10 @@ static void share_workspace(Plan& P) {
   };
   for (auto& r : P.inputs) use(r);  // filled before the first step
   for (auto& st : P.steps) {
-    visit_refs(st, use);
+    visit_refs_par(st, use);
     ++si;
   }
+  const auto t_use = std::chrono::steady_clock::now();
   si = nst;  // result arrays: live to the end
   for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) use(*r);
   P.wsd_planned = P.wsd;
@@ -2224,13 +2325,20 @@ static void share_workspace(Plan& P) {
                  peak * 8e-9, pk, pk < nst ? P.steps[pk].phase : -1, by[0], by[1], by[2], by[3], by[4], by[5], by[6],
                  by[7]);
   }
+  auto t1 = std::chrono::steady_clock::now();
   P.wsd = ad.place();
   P.wsf = af.place();
+  auto t2 = std::chrono::steady_clock::now();
   auto remap = [&](auto& r) {
     if (r.ws == WS_D) r.off = ad.remap(r.off);
     else if (r.ws == WS_F) r.off = af.remap(r.off);
   };
-  for (auto& st : P.steps) visit_refs(st, remap);
+  for (auto& st : P.steps) visit_refs_par(st, remap);
+  if (trace) {
+    auto ms = [](auto a, auto b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+    std::fprintf(stderr, "[h2 plan] sharing: %zu + %zu buffers, lifetimes %.0f ms, placement %.0f ms, remap %.0f ms\n",
+                 ad.base.size(), af.base.size(), ms(t0, t_use), ms(t1, t2), ms(t2, std::chrono::steady_clock::now()));
+  }
   for (DRef<double>* r : {&P.res_vleaf, &P.res_vtr, &P.res_wleaf, &P.res_wtr, &P.res_S, &P.res_N}) remap(*r);
   for (auto& r : P.inputs) remap(r);
 }
