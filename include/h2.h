@@ -147,10 +147,10 @@ typedef struct {
      units_kernel    matrices (tasks) the kernel processed (timing == 3)
      flops_kernel    algorithmic flops: QR 2mw^2 - 2w^3/3 of each factored m x w
                      matrix (2wm^2 - 2m^3/3 when m < w), SVD the pivoted QR steps and
-                     Jacobi rotations it ran,
-                     GEMM 2mnk of the planned (upper bound) sizes (timing == 3)
+                     Jacobi rotations it ran, GEMM 2mnk with the m, n and summed inner
+                     dimension k that each task reports from the device (timing == 3)
      bytes_kernel    algorithmic bytes: each input read once, each output written
-                     once (timing == 3)                                                  */
+                     once, with the same device-side sizes (timing == 3)               */
   double t_kernel[H2_NKERNEL];
   int64_t launches_kernel[H2_NKERNEL];
   double units_kernel[H2_NKERNEL];

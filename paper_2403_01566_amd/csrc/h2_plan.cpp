@@ -2377,8 +2377,6 @@ static void set_base(Plan& P, char* base) {
   P.wi = reinterpret_cast<int*>(base + ws_part(P.wsd, sizeof(double)) + ws_part(P.wsf, sizeof(float)));
 }
 
-// Descriptors of every step, resolved against the current workspace
-// pointers, uploaded to the device.
 // Descriptors of every step resolved against the current workspace pointers
 // (host bytes; st.desc_off etc. are offsets into them).
 static std::vector<char> build_blob(Plan& P, double eps) {
@@ -3527,6 +3525,52 @@ struct Job {
   }
 };
 
+// Device bytes of a product's result arrays (bases padded to kc columns,
+// couplings, nearfield, ranks; allocated when the product is submitted).
+static size_t result_bytes(const Matrix* X, const Matrix* Y, const Plan& P, int kc) {
+  const int64_t n = X->rows->n * kc + (int64_t)X->rows->ncl * kc * kc + Y->cols->n * kc +
+                    (int64_t)Y->cols->ncl * kc * kc + (int64_t)P.cbt.adm.size() * kc * kc + P.cnsize +
+                    X->rows->ncl + Y->cols->ncl;
+  return (size_t)(n + 7 * 32) * sizeof(double);
+}
+
+// Upper estimate of a plan's device descriptor bytes before they are built.
+static size_t desc_estimate(const Plan& P) {
+  size_t b = 0;
+  for (const auto& st : P.steps) {
+    b += st.itd.size() * sizeof(h2k::GemmItem<double>) + st.itf.size() * sizeof(h2k::GemmItem<float>);
+    b += (st.tkd.size() + st.tkf.size()) * (sizeof(h2k::GemmTask<double>) + 16 * sizeof(h2k::GemmTile));
+    b += (st.qr.size() * 2 + st.svd.size() + st.chol.size()) * 256 + st.refmat.size() * 64 + st.ref.size() * 64;
+    b += 4096;
+  }
+  return b;
+}
+
+// Admission by predicted footprint: the memory a product still needs (a
+// larger arena for its lane, its descriptors if not uploaded yet, its
+// result) against what the device can give (free memory, the lane's own
+// arena if it must be replaced, the arenas of idle lanes).  A product that
+// cannot fit is refused before anything is allocated.
+static void admit(Context* ctx, const LaneRes& LR, const Plan& P, size_t res_bytes) {
+  size_t need = res_bytes, give = 0, freeb = 0, total = 0;
+  if (LR.arena.bytes < P.ws_bytes) {
+    need += P.ws_bytes;
+    give += LR.arena.bytes;
+  }
+  if (!P.desc.p) need += desc_estimate(P);
+  H2_HIP(hipMemGetInfo(&freeb, &total));
+  give += freeb;
+  for (auto& o : ctx->lanes)
+    if (o.get() != &LR && o->inflight == 0) give += o->arena.bytes;
+  if (need > give) {
+    char msg[200];
+    std::snprintf(msg, sizeof msg,
+                  "out of memory: the product needs about %.3f GB more device memory, %.3f GB can be freed now",
+                  need * 1e-9, give * 1e-9);
+    throw Error(H2_ERR_OUT_OF_MEMORY, msg);
+  }
+}
+
 Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options& opt) {
   if (X->cols.get() != Y->rows.get()) throw Error(H2_ERR_INCOMPATIBLE, "X's column tree is not Y's row tree");
   if (!(eps > 0.0 && eps < 1.0) || !std::isfinite(eps)) throw Error(H2_ERR_INVALID_ARG, "eps must be in (0,1)");
@@ -3591,6 +3635,7 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   LaneRes& LR = *ctx->lanes[lane];
   if (LR.free_slots.empty()) throw Error(H2_ERR_TOO_LARGE, "more than 64 jobs in flight on one lane");
   if (tol_differs(P, eps, tol)) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
+  admit(ctx, LR, P, result_bytes(X, Y, P, kc));
   bind(ctx, P, lane, eps);
   set_tolerances(P, eps, tol);
   J->f32 = f32;
