@@ -45,6 +45,7 @@
 #include <set>
 #include <climits>
 #include <tuple>
+#include <type_traits>
 #include <unordered_map>
 #include <deque>
 #include <cstdio>
@@ -163,6 +164,7 @@ struct Step {
   int wmax = 0;
   size_t desc_off = 0, desc2_off = 0, tiles_off = 0;
   int ndesc = 0, ntiles = 0;
+  int64_t nitems = 0;  // GEMM: items at desc_off (ndesc tasks at desc2_off)
   double flops = 0, bytes = 0;
   double flops_tile = 0;  // GEMM: MFMA work incl. padding to 32 x 32 quarters and 16-wide slices
   int64_t stat_off = -1;  // QR / SVD: per-task size reports (int workspace)
@@ -186,6 +188,11 @@ struct Plan {
   int* wi = nullptr;
   size_t ws_bytes = 0;  // FP64, FP32 and int workspaces, each 256-byte aligned
   bool keep_protos = false;
+  bool own_protos = false;  // descriptors rebuilt from the protos on every use (matrix-vector plans)
+  // the uploaded descriptors: their size and the workspace base they were
+  // resolved against (a moved workspace is handled by rebasing them)
+  size_t desc_size = 0;
+  char* desc_base = nullptr;
   int bound_lane = -1;
   uint64_t bound_epoch = 0;
   // HIP graph of the product's launches (captured from the plan's streams).
@@ -200,7 +207,6 @@ struct Plan {
   ~Plan() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
   }
-  std::vector<char> hdesc;
   int kc = 0, kappa_cap = 0;
   DRef<double> res_vleaf, res_vtr, res_wleaf, res_wtr, res_S, res_N;
   DRef<int> res_rank_row, res_rank_col;
@@ -1950,6 +1956,7 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
     items[i].alpha = it[i].alpha;
   }
   blob.insert(blob.end(), (char*)items.data(), (char*)(items.data() + items.size()));
+  st.nitems = (int64_t)items.size();
   align(64);
   st.desc2_off = blob.size();
   std::vector<GemmTask<T>> tasks(tk.size());
@@ -1982,7 +1989,7 @@ static void emit_gemm(Plan& P, Step& st, std::vector<char>& blob, const std::vec
   st.ndesc = (int)tasks.size();
 }
 
-static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, bool inplace) {
+static std::vector<h2k::SvdTask> svd_tasks(Plan& P, Step& st, double eps) {
   std::vector<h2k::SvdTask> v(st.svd.size());
   const double dc = eps * P.budget[0], dr = eps * P.budget[1], dw = eps * P.budget[2];
   const double scale = std::sqrt(1.0 - P.sigma_br * P.theta);
@@ -2020,13 +2027,15 @@ static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps, 
     v[i].kcap = s.kcap;
     v[i].trans_a = s.trans_a;
   }
-  if (!inplace) {
-    while (blob.size() % 64) blob.push_back(0);
-    st.desc_off = blob.size();
-    blob.insert(blob.end(), (char*)v.data(), (char*)(v.data() + v.size()));
-  } else {
-    std::memcpy(blob.data() + st.desc_off, v.data(), v.size() * sizeof(h2k::SvdTask));
-  }
+  return v;
+}
+
+// The step's SVD descriptors appended to the blob.
+static void resolve_svd(Plan& P, Step& st, std::vector<char>& blob, double eps) {
+  const std::vector<h2k::SvdTask> v = svd_tasks(P, st, eps);
+  while (blob.size() % 64) blob.push_back(0);
+  st.desc_off = blob.size();
+  blob.insert(blob.end(), (const char*)v.data(), (const char*)(v.data() + v.size()));
   st.ndesc = (int)v.size();
 }
 
@@ -2394,20 +2403,24 @@ static std::vector<char> build_blob(Plan& P, double eps) {
         for (size_t i = 0; i < st.qr.size(); ++i) {
           const PQr& q = st.qr[i];
           int* stat = P.wi + st.stat_off + 2 * i;
-          h2k::QrTask t{res(q.a, P),  res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), res(q.m_dev, P), stat,
-                        q.lda,        q.ldr,       q.m,               q.w,                q.trans_r,         q.mul_we,
-                        q.part,       q.m_off};
+          h2k::QrTask t;
+          std::memset(&t, 0, sizeof t);  // deterministic bytes, padding included
+          t = h2k::QrTask{res(q.a, P), res(q.r, P), res(q.w_dev, P), res(q.w_dev2, P), res(q.m_dev, P), stat,
+                          q.lda,       q.ldr,       q.m,               q.w,                q.trans_r,         q.mul_we,
+                          q.part,      q.m_off};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.qr.size();
         break;
       }
-      case SK_SVD: resolve_svd(P, st, blob, eps, false); break;
+      case SK_SVD: resolve_svd(P, st, blob, eps); break;
       case SK_CHOL: {
         align(64);
         st.desc_off = blob.size();
         for (auto& c : st.chol) {
-          h2k::CholTask t{res(c.g, P), res(c.t, P), res(c.r, P), res(c.weff, P), c.ldg, c.ldt, c.ldr, c.w};
+          h2k::CholTask t;
+          std::memset(&t, 0, sizeof t);
+          t = h2k::CholTask{res(c.g, P), res(c.t, P), res(c.r, P), res(c.weff, P), c.ldg, c.ldt, c.ldr, c.w};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.chol.size();
@@ -2417,7 +2430,9 @@ static std::vector<char> build_blob(Plan& P, double eps) {
         align(64);
         st.desc_off = blob.size();
         for (auto& f : st.fill) {
-          h2k::FillTask t{res(f.p, P), f.ld, f.m, f.n, 0, f.value, f.diag, 8};
+          h2k::FillTask t;
+          std::memset(&t, 0, sizeof t);
+          t = h2k::FillTask{res(f.p, P), f.ld, f.m, f.n, 0, f.value, f.diag, 8};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.fill.size();
@@ -2427,13 +2442,21 @@ static std::vector<char> build_blob(Plan& P, double eps) {
         align(64);
         st.desc_off = blob.size();
         for (auto& r : st.ref) {
-          h2k::RefTask t{r.first, r.count, r.factor, res(r.out, P)};
+          h2k::RefTask t;
+          std::memset(&t, 0, sizeof t);
+          t = h2k::RefTask{r.first, r.count, r.factor, res(r.out, P)};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         align(64);
         st.desc2_off = blob.size();
         for (auto& m : st.refmat) {
-          h2k::RefMat t{res(m.a, P), m.lda, m.rows, m.cols, ref_scale(P, m, eps)};
+          h2k::RefMat t;
+          std::memset(&t, 0, sizeof t);  // 4 bytes of padding before scale
+          t.a = res(m.a, P);
+          t.lda = m.lda;
+          t.rows = m.rows;
+          t.cols = m.cols;
+          t.scale = ref_scale(P, m, eps);
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         st.ndesc = (int)st.ref.size();
@@ -2443,7 +2466,9 @@ static std::vector<char> build_blob(Plan& P, double eps) {
         align(64);
         st.desc_off = blob.size();
         for (auto& c : st.scan) {
-          h2k::ScanTask t{c.first, c.count, res(c.offs, P), res(c.total, P)};
+          h2k::ScanTask t;
+          std::memset(&t, 0, sizeof t);
+          t = h2k::ScanTask{c.first, c.count, res(c.offs, P), res(c.total, P)};
           blob.insert(blob.end(), (char*)&t, (char*)&t + sizeof(t));
         }
         align(64);
@@ -2461,9 +2486,110 @@ static std::vector<char> build_blob(Plan& P, double eps) {
   return blob;
 }
 
+// Workspace base of a plan's descriptors (its FP64 part starts the arena).
+static char* ws_base(const Plan& P) { return reinterpret_cast<char*>(P.wd); }
+
+// Shifts every workspace pointer of a descriptor blob (host copy) that lies
+// in [from, from + len) by `to - from`.  Pointers outside that range (the
+// operands, null) stay: they were allocated before the descriptors, while
+// the old workspace was live, so they cannot lie in it.
+static void rebase_blob(const Plan& P, std::vector<char>& blob, const char* from, const char* to, size_t len) {
+  auto fix = [&](auto& ptr) {
+    const char* q = reinterpret_cast<const char*>(ptr);
+    if (q >= from && q < from + len)
+      ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(const_cast<char*>(to + (q - from)));
+  };
+  auto arr = [&](size_t off, size_t n, auto* tag, auto&& f) {
+    using D = std::remove_pointer_t<decltype(tag)>;
+    D* a = reinterpret_cast<D*>(blob.data() + off);
+    for (size_t i = 0; i < n; ++i) f(a[i]);
+  };
+  for (const auto& st : P.steps) {
+    switch (st.kind) {
+      case SK_GEMM_D:
+      case SK_GEMM_F: {
+        auto items = [&](auto& it) {
+          fix(it.a);
+          fix(it.b);
+          fix(it.scale);
+          fix(it.k_dev);
+          fix(it.k_dev2);
+        };
+        auto tasks = [&](auto& t) {
+          fix(t.c);
+          fix(t.m_dev);
+          fix(t.n_dev);
+          fix(t.coff_dev);
+          fix(t.roff_dev);
+          fix(t.stat);
+        };
+        if (st.kind == SK_GEMM_D) {
+          arr(st.desc_off, st.nitems, (h2k::GemmItem<double>*)nullptr, items);
+          arr(st.desc2_off, st.ndesc, (h2k::GemmTask<double>*)nullptr, tasks);
+        } else {
+          arr(st.desc_off, st.nitems, (h2k::GemmItem<float>*)nullptr, items);
+          arr(st.desc2_off, st.ndesc, (h2k::GemmTask<float>*)nullptr, tasks);
+        }
+        break;
+      }
+      case SK_QR:
+        arr(st.desc_off, st.ndesc, (h2k::QrTask*)nullptr, [&](h2k::QrTask& t) {
+          fix(t.a);
+          fix(t.r);
+          fix(t.w_dev);
+          fix(t.w_dev2);
+          fix(t.m_dev);
+          fix(t.stat);
+        });
+        break;
+      case SK_SVD:
+        arr(st.desc_off, st.ndesc, (h2k::SvdTask*)nullptr, [&](h2k::SvdTask& t) {
+          fix(t.a);
+          fix(t.u);
+          fix(t.u2);
+          fix(t.sigma);
+          fix(t.rank);
+          fix(t.tol_ptr);
+          fix(t.w_dev);
+          fix(t.w_dev2);
+          fix(t.split_dev);
+          fix(t.stat);
+        });
+        break;
+      case SK_CHOL:
+        arr(st.desc_off, st.ndesc, (h2k::CholTask*)nullptr, [&](h2k::CholTask& t) {
+          fix(t.g);
+          fix(t.t);
+          fix(t.r);
+          fix(t.weff);
+        });
+        break;
+      case SK_FILL:
+        arr(st.desc_off, st.ndesc, (h2k::FillTask*)nullptr, [&](h2k::FillTask& t) { fix(t.p); });
+        break;
+      case SK_REF:
+        arr(st.desc_off, st.ndesc, (h2k::RefTask*)nullptr, [&](h2k::RefTask& t) { fix(t.out); });
+        arr(st.desc2_off, st.refmat.size(), (h2k::RefMat*)nullptr, [&](h2k::RefMat& t) { fix(t.a); });
+        break;
+      case SK_SCAN:
+        arr(st.desc_off, st.ndesc, (h2k::ScanTask*)nullptr, [&](h2k::ScanTask& t) {
+          fix(t.offs);
+          fix(t.total);
+        });
+        arr(st.desc2_off, st.scansrc.size(), (const int**)nullptr, [&](const int*& q) { fix(q); });
+        break;
+      case SK_CVT_F2D:
+        break;
+    }
+  }
+}
+
 static void drop_protos(Plan& P);
 
-// Descriptors uploaded to the plan's own descriptor buffer.
+// Descriptors uploaded to the plan's own descriptor buffer.  Built from the
+// step protos the first time; afterwards (the workspace moved: a new arena)
+// the uploaded descriptors are rebased, which keeps the tolerances they were
+// patched to (P.eps_set).
 static void emit(Plan& P, double eps) {
   // a captured graph holds workspace pointers as kernel arguments (the
   // FP32 -> FP64 conversions): new pointers need a new capture
@@ -2471,23 +2597,74 @@ static void emit(Plan& P, double eps) {
     H2_HIP(hipGraphExecDestroy(P.gexec));
     P.gexec = nullptr;
   }
+  static const bool check = std::getenv("H2_CHECK_REBASE") != nullptr;
+  if (P.desc.p && P.desc_base && !P.keep_protos) {
+    std::vector<char> blob(P.desc_size);
+    H2_HIP(hipMemcpy(blob.data(), P.desc.p, blob.size(), hipMemcpyDeviceToHost));
+    rebase_blob(P, blob, P.desc_base, ws_base(P), P.ws_bytes);
+    H2_HIP(hipMemcpy(P.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+    P.desc_base = ws_base(P);
+    return;
+  }
+  if (check && P.desc.p && P.desc_base && P.keep_protos && !P.own_protos) {
+    // diagnostic: a rebase of the uploaded descriptors equals a fresh build
+    std::vector<char> blob(P.desc_size);
+    H2_HIP(hipMemcpy(blob.data(), P.desc.p, blob.size(), hipMemcpyDeviceToHost));
+    rebase_blob(P, blob, P.desc_base, ws_base(P), P.ws_bytes);
+    const std::vector<char> fresh = build_blob(P, P.eps_set);
+    if (fresh.size() != blob.size() || std::memcmp(fresh.data(), blob.data(), blob.size()) != 0) {
+      size_t at = 0;
+      while (at < std::min(fresh.size(), blob.size()) && fresh[at] == blob[at]) ++at;
+      int sk = -1, kind = -1;
+      size_t rel = 0;
+      for (size_t i = 0; i < P.steps.size(); ++i)
+        if (P.steps[i].desc_off <= at && (sk < 0 || P.steps[i].desc_off >= P.steps[sk].desc_off)) sk = (int)i;
+      if (sk >= 0) {
+        kind = (int)P.steps[sk].kind;
+        rel = at - P.steps[sk].desc_off;
+      }
+      char msg[200];
+      std::snprintf(msg, sizeof msg,
+                    "descriptor rebase differs from a fresh build: byte %zu of %zu/%zu, step %d (kind %d) +%zu", at,
+                    blob.size(), fresh.size(), sk, kind, rel);
+      throw Error(H2_ERR_DEVICE, msg);
+    }
+    std::fprintf(stderr, "[h2 plan] rebase of %.3f GB of descriptors checked\n", blob.size() * 1e-9);
+  }
   std::vector<char> blob = build_blob(P, eps);
-  P.hdesc = blob;
+  if (std::getenv("H2_TRACE")) {
+    size_t proto = 0;
+    for (const auto& st : P.steps)
+      proto += st.itd.capacity() * sizeof(st.itd[0]) + st.tkd.capacity() * sizeof(st.tkd[0]) +
+               st.itf.capacity() * sizeof(st.itf[0]) + st.tkf.capacity() * sizeof(st.tkf[0]) +
+               st.qr.capacity() * sizeof(st.qr[0]) + st.svd.capacity() * sizeof(st.svd[0]) +
+               st.chol.capacity() * sizeof(st.chol[0]) + st.refmat.capacity() * sizeof(st.refmat[0]);
+    std::fprintf(stderr, "[h2 plan] descriptors %.3f GB on the device, step protos %.3f GB on the host\n",
+                 blob.size() * 1e-9, proto * 1e-9);
+  }
   if (P.desc.bytes < blob.size() || !P.desc.p) P.desc.alloc(std::max<size_t>(blob.size(), 64));
   H2_HIP(hipMemcpy(P.desc.p, blob.data(), blob.size(), hipMemcpyHostToDevice));
+  P.desc_size = blob.size();
+  P.desc_base = ws_base(P);
   P.eps_set = eps;
   drop_protos(P);
 }
 
 static void drop_protos(Plan& P) {
-  if (!P.keep_protos) {
-    // descriptors are on the device for good; drop the host-side proto lists of GEMM steps
-    for (auto& st : P.steps) {
-      st.itd.clear(); st.itd.shrink_to_fit();
-      st.tkd.clear(); st.tkd.shrink_to_fit();
-      st.itf.clear(); st.itf.shrink_to_fit();
-      st.tkf.clear(); st.tkf.shrink_to_fit();
-    }
+  // Plans that rebuild their descriptors on every use keep the protos;
+  // product plans rebase theirs when the workspace moves and keep only the
+  // protos that tolerance changes and the counting call read (SVD, REF,
+  // QR).  H2_CHECK_REBASE keeps them all, to check every rebase.
+  static const bool check = std::getenv("H2_CHECK_REBASE") != nullptr;
+  if (P.own_protos || check) return;
+  P.keep_protos = false;
+  for (auto& st : P.steps) {
+    std::vector<PItem<double>>().swap(st.itd);
+    std::vector<PTask<double>>().swap(st.tkd);
+    std::vector<PItem<float>>().swap(st.itf);
+    std::vector<PTask<float>>().swap(st.tkf);
+    std::vector<PChol>().swap(st.chol);
+    std::vector<PFill>().swap(st.fill);
   }
 }
 
@@ -2582,22 +2759,24 @@ static void set_tolerances(Plan& P, double eps, const Tol& t) {
   if (!tol_differs(P, eps, t)) return;
   for (int i = 0; i < 3; ++i) P.budget[i] = t.budget[i];
   P.sweeps = t.sweeps;
+  // (no host copy of the descriptors is kept: the SVD tasks are rebuilt from
+  // the step's protos, the block-norm matrices read back from the device)
   for (auto& st : P.steps)
     if (st.kind == SK_SVD) {
-      resolve_svd(P, st, P.hdesc, eps, true);
-      H2_HIP(hipMemcpy((char*)P.desc.p + st.desc_off, P.hdesc.data() + st.desc_off,
-                       st.ndesc * sizeof(h2k::SvdTask), hipMemcpyHostToDevice));
+      const std::vector<h2k::SvdTask> v = svd_tasks(P, st, eps);
+      H2_HIP(hipMemcpy((char*)P.desc.p + st.desc_off, v.data(), v.size() * sizeof(h2k::SvdTask),
+                       hipMemcpyHostToDevice));
     } else if (st.kind == SK_REF) {
-      auto* mats = (h2k::RefMat*)(P.hdesc.data() + st.desc2_off);
       bool any = false;
+      for (const auto& rm : st.refmat) any |= rm.approx;
+      if (!any) continue;
+      std::vector<h2k::RefMat> mats(st.refmat.size());
+      H2_HIP(hipMemcpy(mats.data(), (char*)P.desc.p + st.desc2_off, mats.size() * sizeof(h2k::RefMat),
+                       hipMemcpyDeviceToHost));
       for (size_t i = 0; i < st.refmat.size(); ++i)
-        if (st.refmat[i].approx) {
-          mats[i].scale = ref_scale(P, st.refmat[i], eps);
-          any = true;
-        }
-      if (any)
-        H2_HIP(hipMemcpy((char*)P.desc.p + st.desc2_off, mats, st.refmat.size() * sizeof(h2k::RefMat),
-                         hipMemcpyHostToDevice));
+        if (st.refmat[i].approx) mats[i].scale = ref_scale(P, st.refmat[i], eps);
+      H2_HIP(hipMemcpy((char*)P.desc.p + st.desc2_off, mats.data(), mats.size() * sizeof(h2k::RefMat),
+                       hipMemcpyHostToDevice));
     }
   P.eps_set = eps;
 }
@@ -2839,23 +3018,35 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
             P.bytes_k[kid] += 8.0 * (rows * cols + rows * st.svd[i].kcap + cols);
           }
         }
-      } else if ((kind == SK_GEMM_D || kind == SK_GEMM_F) && st.stat_off >= 0 &&
-                 (kind == SK_GEMM_D ? !st.tkd.empty() : !st.tkf.empty())) {
+      } else if ((kind == SK_GEMM_D || kind == SK_GEMM_F) && st.stat_off >= 0 && st.ndesc > 0) {
         // GEMM: the device-side sizes each task reported (m, n and the sum
         // of its product items' inner dimensions), each operand read once and
-        // the output written once (read too with beta)
+        // the output written once (read too with beta); beta and the copy
+        // count from the task descriptors on the device
         const int kid = kind == SK_GEMM_D ? h2k::K_GEMM_F64 : h2k::K_GEMM_F32;
         const double w = kind == SK_GEMM_D ? 8.0 : 4.0;
-        const size_t n = kind == SK_GEMM_D ? st.tkd.size() : st.tkf.size();
+        const size_t n = st.ndesc;
         stat.resize(3 * n);
         H2_HIP(hipMemcpy(stat.data(), P.wi + st.stat_off, 3 * n * sizeof(int), hipMemcpyDeviceToHost));
+        std::vector<int> beta_copy(2 * n);
+        {
+          const size_t tsz = kind == SK_GEMM_D ? sizeof(h2k::GemmTask<double>) : sizeof(h2k::GemmTask<float>);
+          std::vector<char> tb(n * tsz);
+          H2_HIP(hipMemcpy(tb.data(), base + st.desc2_off, tb.size(), hipMemcpyDeviceToHost));
+          for (size_t i = 0; i < n; ++i) {
+            if (kind == SK_GEMM_D) {
+              const auto& t = reinterpret_cast<const h2k::GemmTask<double>*>(tb.data())[i];
+              beta_copy[2 * i] = t.beta;
+              beta_copy[2 * i + 1] = t.ncopy;
+            } else {
+              const auto& t = reinterpret_cast<const h2k::GemmTask<float>*>(tb.data())[i];
+              beta_copy[2 * i] = t.beta;
+              beta_copy[2 * i + 1] = t.ncopy;
+            }
+          }
+        }
         for (size_t i = 0; i < n; ++i) {
-          const int beta = kind == SK_GEMM_D ? st.tkd[i].beta : st.tkf[i].beta;
-          const int item0 = kind == SK_GEMM_D ? st.tkd[i].item0 : st.tkf[i].item0;
-          const int nitem = kind == SK_GEMM_D ? st.tkd[i].nitem : st.tkf[i].nitem;
-          int ncopy = 0;
-          for (int q = 0; q < nitem; ++q)
-            ncopy += ((kind == SK_GEMM_D ? st.itd[item0 + q].flags : st.itf[item0 + q].flags) & h2k::IT_COPY) != 0;
+          const int beta = beta_copy[2 * i], ncopy = beta_copy[2 * i + 1];
           const double m = std::max(stat[3 * i], 0), nn = std::max(stat[3 * i + 1], 0), ks = stat[3 * i + 2];
           P.units_k[kid] += 1;
           P.flops_k[kid] += 2.0 * m * nn * ks;
@@ -3205,6 +3396,7 @@ void matvec_scratch(Matrix* M, int trans, int64_t nrhs, const double* x, double*
   } else {
     mv = build_mv_host(M, trans, nrhs);
     mv->P->keep_protos = true;  // descriptors are rebuilt on every call
+    mv->P->own_protos = true;
     ctx->mvhost[key] = mv;
   }
   Plan& P = *mv->P;

@@ -174,3 +174,38 @@ def test_graph_recaptured_after_the_arena_moves(h2):
     for _ in range(3):
         C, _ = h2.mul(ctx, A, A, 1e-4, f32g)             # re-emitted: a new capture
         assert np.array_equal(C.to_dense(T1.n, T1.n), refA)
+
+
+def test_plans_rebased_after_the_arena_moves(h2):
+    """A cached plan whose lane arena was replaced by a larger one is used
+    again: its device descriptors are rebased to the new workspace (the host
+    protos of its GEMM steps are gone), then patched to another tolerance.
+    Every result equals, bit for bit, the same product in a fresh context."""
+    ref = {}
+    ctx0 = h2.Context(0)
+    h2.set_lanes(ctx0, 1)
+    pts = [W.uniform2d(1000, 51), W.uniform2d(5000, 52), W.uniform2d(9000, 53)]
+
+    def ops(ctx):
+        out = []
+        for P in pts:
+            T = h2.Tree(ctx, P, 32)
+            out.append((T, h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, 4, 0.5)))
+        return out
+
+    o0 = ops(ctx0)
+    T1, A0 = o0[0]
+    for eps in (1e-5, 1e-3):
+        ref[eps] = h2.mul(ctx0, A0, A0, eps)[0].to_dense(T1.n, T1.n)
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, 1)
+    o = ops(ctx)
+    A = o[0][1]
+    C, _ = h2.mul(ctx, A, A, 1e-5)
+    assert np.array_equal(C.to_dense(T1.n, T1.n), ref[1e-5])
+    for k, eps in ((1, 1e-3), (2, 1e-5), (1, 1e-5), (2, 1e-3)):
+        Bk = o[k][1]
+        h2.mul(ctx, Bk, Bk, 1e-4)  # a larger plan on the lane: the arena may move
+        C, st = h2.mul(ctx, A, A, eps)
+        assert st["t_plan_ms"] == 0.0
+        assert np.array_equal(C.to_dense(T1.n, T1.n), ref[eps]), (k, eps)
