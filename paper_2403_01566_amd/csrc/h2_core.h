@@ -175,6 +175,7 @@ struct Context {
   // (its flags are separate from `overflow`); created by set_lanes
   std::vector<std::unique_ptr<LaneRes>> lanes;
   uint64_t arena_epoch = 0;  // source of LaneRes::epoch values (unique per allocation)
+  uint64_t submissions = 0;  // products submitted (the plans' last-use stamps)
   Lane lane0() const {
     Lane l;
     l.stream = stream;

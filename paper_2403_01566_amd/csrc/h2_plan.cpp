@@ -195,6 +195,7 @@ struct Plan {
   char* desc_base = nullptr;
   int bound_lane = -1;
   uint64_t bound_epoch = 0;
+  uint64_t last_use = 0;  // submission counter of the context at the plan's last use (cache eviction)
   // HIP graph of the product's launches (captured from the plan's streams).
   // Most kernels read their descriptors from device memory, so eps patches
   // keep it valid; emit() (new workspace pointers) drops it, because the
@@ -3754,6 +3755,22 @@ static void admit(Context* ctx, const LaneRes& LR, const Plan& P, size_t res_byt
   give += freeb;
   for (auto& o : ctx->lanes)
     if (o.get() != &LR && o->inflight == 0) give += o->arena.bytes;
+  // not enough: the least recently used cached plans without jobs go (their
+  // descriptors are freed; such a plan is built again when its operands
+  // are multiplied again)
+  while (need > give) {
+    auto victim = ctx->plans.end();
+    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
+      if (it->second.get() != &P && it->second->inflight == 0 && it->second.use_count() == 1 &&
+          (victim == ctx->plans.end() || it->second->last_use < victim->second->last_use))
+        victim = it;
+    if (victim == ctx->plans.end()) break;
+    const size_t freed = victim->second->desc.bytes;
+    Plan& V = *victim->second;
+    if (V.bound_lane >= 0 && V.bound_lane < (int)ctx->lanes.size()) --ctx->lanes[V.bound_lane]->nplans;
+    ctx->plans.erase(victim);
+    give += freed;
+  }
   if (need > give) {
     char msg[200];
     std::snprintf(msg, sizeof msg,
@@ -3828,6 +3845,7 @@ Job* submit(Context* ctx, Matrix* X, Matrix* Y, double eps, const h2_mul_options
   if (LR.free_slots.empty()) throw Error(H2_ERR_TOO_LARGE, "more than 64 jobs in flight on one lane");
   if (tol_differs(P, eps, tol)) quiesce(ctx, P);  // descriptors change: the plan's earlier jobs must be done
   admit(ctx, LR, P, result_bytes(X, Y, P, kc));
+  P.last_use = ++ctx->submissions;
   bind(ctx, P, lane, eps);
   set_tolerances(P, eps, tol);
   J->f32 = f32;
