@@ -208,6 +208,21 @@ h2_status h2_block_dense(h2_matrix M, int64_t b, double* out);
  * result of a job is the same, bit for bit, as that of h2_mul with the same
  * arguments. Not thread-safe: one host thread per context. */
 h2_status h2_context_set_lanes(h2_context ctx, int nlanes);
+/* Device memory admission (h2_mul and h2_mul_submit).  Before a product
+ * allocates anything, the library adds up what it still needs (a larger
+ * workspace arena for its lane, its launch descriptors if not uploaded yet,
+ * its result arrays) and compares it with what can be given: free device
+ * memory, the arena it replaces and the arenas of idle lanes.  If that is
+ * not enough, cached product plans without jobs are dropped, least recently
+ * used first (their descriptors are freed; such a plan is built again when
+ * its operands are multiplied again), but only when dropping them all would
+ * make room; otherwise the product fails with H2_ERR_OUT_OF_MEMORY and
+ * nothing is allocated or dropped.  h2_context_set_memory_limit(ctx, bytes)
+ * makes the admission treat the device as holding at most `bytes` (memory in
+ * use by anyone counts against it; 0 = the whole device), e.g. to leave room
+ * for other work on the GPU; it also bounds the workspace budget of new
+ * plans (chunking).  It does not restrict allocations outside products. */
+h2_status h2_context_set_memory_limit(h2_context ctx, uint64_t bytes);
 h2_status h2_mul_submit(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opts,
                         h2_job* job);
 h2_status h2_job_poll(h2_job job, int* done);

@@ -204,6 +204,13 @@ h2_status h2_context_set_lanes(h2_context ctx, int nlanes) {
   });
 }
 
+h2_status h2_context_set_memory_limit(h2_context ctx, uint64_t bytes) {
+  return guard([&] {
+    require(ctx != nullptr, "null argument");
+    ctx->c.mem_limit = bytes;
+  });
+}
+
 h2_status h2_mul_submit(h2_context ctx, h2_matrix X, h2_matrix Y, double eps, const h2_mul_options* opt,
                         h2_job* job) {
   if (job) *job = nullptr;

@@ -176,6 +176,9 @@ struct Context {
   std::vector<std::unique_ptr<LaneRes>> lanes;
   uint64_t arena_epoch = 0;  // source of LaneRes::epoch values (unique per allocation)
   uint64_t submissions = 0;  // products submitted (the plans' last-use stamps)
+  uint64_t mem_limit = 0;    // admission limit on device memory in use (0: the whole device)
+  // free device memory as the admission sees it: min(free, limit - in use)
+  size_t admissible_free() const;
   Lane lane0() const {
     Lane l;
     l.stream = stream;

@@ -3206,8 +3206,7 @@ static std::shared_ptr<Plan> make_plan(Context* ctx, Matrix* X, Matrix* Y, bool 
   int nch = opt.chunks > 0 ? opt.chunks : 1;
   auto P = make_plan_chunks(ctx, X, Y, f32, kc, kcap, opt, eps, nch);
   if (opt.chunks > 0) return P;
-  size_t freeb = 0, total = 0;
-  H2_HIP(hipMemGetInfo(&freeb, &total));
+  const size_t freeb = ctx->admissible_free();
   size_t held = 0;
   for (auto& l : ctx->lanes) held += l->arena.bytes;
   // room for the result, operands and allocator granularity: 15 % of the memory
@@ -3744,32 +3743,47 @@ static size_t desc_estimate(const Plan& P) {
 // result) against what the device can give (free memory, the lane's own
 // arena if it must be replaced, the arenas of idle lanes).  A product that
 // cannot fit is refused before anything is allocated.
+size_t Context::admissible_free() const {
+  size_t freeb = 0, total = 0;
+  H2_HIP(hipMemGetInfo(&freeb, &total));
+  if (mem_limit == 0) return freeb;
+  const size_t used = total - freeb;
+  return used >= mem_limit ? 0 : std::min<size_t>(freeb, mem_limit - used);
+}
+
 static void admit(Context* ctx, const LaneRes& LR, const Plan& P, size_t res_bytes) {
-  size_t need = res_bytes, give = 0, freeb = 0, total = 0;
+  size_t need = res_bytes, give = 0;
   if (LR.arena.bytes < P.ws_bytes) {
     need += P.ws_bytes;
     give += LR.arena.bytes;
   }
   if (!P.desc.p) need += desc_estimate(P);
-  H2_HIP(hipMemGetInfo(&freeb, &total));
-  give += freeb;
+  give += ctx->admissible_free();
   for (auto& o : ctx->lanes)
     if (o.get() != &LR && o->inflight == 0) give += o->arena.bytes;
   // not enough: the least recently used cached plans without jobs go (their
   // descriptors are freed; such a plan is built again when its operands
-  // are multiplied again)
-  while (need > give) {
-    auto victim = ctx->plans.end();
-    for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
-      if (it->second.get() != &P && it->second->inflight == 0 && it->second.use_count() == 1 &&
-          (victim == ctx->plans.end() || it->second->last_use < victim->second->last_use))
-        victim = it;
-    if (victim == ctx->plans.end()) break;
-    const size_t freed = victim->second->desc.bytes;
-    Plan& V = *victim->second;
-    if (V.bound_lane >= 0 && V.bound_lane < (int)ctx->lanes.size()) --ctx->lanes[V.bound_lane]->nplans;
-    ctx->plans.erase(victim);
-    give += freed;
+  // are multiplied again), if dropping them all would make room
+  auto idle = [&](const std::shared_ptr<Plan>& q) {
+    return q.get() != &P && q->inflight == 0 && q.use_count() == 1;
+  };
+  if (need > give) {
+    size_t evictable = 0;
+    for (auto& kv : ctx->plans)
+      if (idle(kv.second)) evictable += kv.second->desc.bytes;
+    while (need > give && need <= give + evictable) {
+      auto victim = ctx->plans.end();
+      for (auto it = ctx->plans.begin(); it != ctx->plans.end(); ++it)
+        if (idle(it->second) && (victim == ctx->plans.end() || it->second->last_use < victim->second->last_use))
+          victim = it;
+      if (victim == ctx->plans.end()) break;
+      const size_t freed = victim->second->desc.bytes;
+      Plan& V = *victim->second;
+      if (V.bound_lane >= 0 && V.bound_lane < (int)ctx->lanes.size()) --ctx->lanes[V.bound_lane]->nplans;
+      ctx->plans.erase(victim);
+      give += freed;
+      evictable -= freed;
+    }
   }
   if (need > give) {
     char msg[200];

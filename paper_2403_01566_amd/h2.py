@@ -31,7 +31,7 @@ EXPORTS = [
     "h2_build_interpolated", "h2_mul_default_options", "h2_mul", "h2_to_dense", "h2_block_dense",
     "h2_matrix_info", "h2_matrix_blocks", "h2_matrix_ranks", "h2_matrix_storage", "h2_matrix_destroy",
     "h2_selftest", "h2_kernel_name", "h2_matvec", "h2_product_error", "h2_block_tree_leaves", "h2_recompress",
-    "h2_context_set_lanes", "h2_mul_submit", "h2_job_poll", "h2_job_wait", "h2_job_destroy",
+    "h2_context_set_lanes", "h2_context_set_memory_limit", "h2_mul_submit", "h2_job_poll", "h2_job_wait", "h2_job_destroy",
     "h2_export_host", "h2_matvec_noalloc",
 ]
 NKERNEL = 13
@@ -101,6 +101,7 @@ _sig = {
     "h2_product_error": (C.c_int, [_vp, _vp, _vp, C.c_int, _dp, _dp, _dp]),
     "h2_block_tree_leaves": (C.c_int, [_vp, _vp, C.c_double, _lp, _lp, _ip]),
     "h2_context_set_lanes": (C.c_int, [_vp, C.c_int]),
+    "h2_context_set_memory_limit": (C.c_int, [_vp, C.c_uint64]),
     "h2_mul_submit": (C.c_int, [_vp, _vp, _vp, C.c_double, C.POINTER(MulOptions), C.POINTER(_vp)]),
     "h2_job_poll": (C.c_int, [_vp, _ip]),
     "h2_job_wait": (C.c_int, [_vp, C.POINTER(_vp), C.POINTER(MulStats)]),
@@ -361,6 +362,11 @@ class Job:
 
 def set_lanes(ctx: Context, nlanes: int):
     _check(_lib.h2_context_set_lanes(ctx.h, int(nlanes)))
+
+
+def set_memory_limit(ctx: Context, nbytes: int):
+    """Admission limit on device memory in use (0: the whole device)."""
+    _check(_lib.h2_context_set_memory_limit(ctx.h, int(nbytes)))
 
 
 def submit(ctx: Context, X: Matrix, Y: Matrix, eps: float, options: MulOptions | None = None) -> Job:

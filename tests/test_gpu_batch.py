@@ -209,3 +209,56 @@ def test_plans_rebased_after_the_arena_moves(h2):
         C, st = h2.mul(ctx, A, A, eps)
         assert st["t_plan_ms"] == 0.0
         assert np.array_equal(C.to_dense(T1.n, T1.n), ref[eps]), (k, eps)
+
+
+def _used_device_bytes():
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    f, t = ctypes.c_size_t(), ctypes.c_size_t()
+    assert hip.hipMemGetInfo(ctypes.byref(f), ctypes.byref(t)) == 0
+    return t.value - f.value
+
+
+def test_memory_admission_refuses_and_evicts(h2):
+    """Admission with a device memory limit: a product that cannot fit is
+    refused before anything is allocated and the cached plans are kept; a
+    product that fits once idle cached plans are dropped runs after the
+    least recently used ones were dropped, and a dropped plan is built again
+    on its next use with the same result bit for bit."""
+    ctx = h2.Context(0)
+    h2.set_lanes(ctx, 1)
+    ops = []
+    for n, p, seed in ((800, 4, 61), (8000, 4, 62), (8000, 6, 63)):
+        T = h2.Tree(ctx, W.uniform2d(n, seed), 32 if p <= 4 else 64)
+        ops.append((T, h2.Matrix.interpolated(ctx, T, T, h2.KERNEL_NEG_LOG, p, 0.5)))
+    (TA, A), (TB, B), (TD, D) = ops
+    refA = h2.mul(ctx, A, A, 1e-6)[0].export()
+    refB = h2.mul(ctx, B, B, 1e-6)[0].export()
+
+    def same(C, ref):
+        ex = C.export()
+        return all(np.array_equal(np.asarray(ex[k]), np.asarray(v)) for k, v in ref.items())
+
+    # no room at all: a new product whose workspace exceeds the lane's arena
+    # and everything that could be dropped is refused, the cached plans stay
+    h2.set_memory_limit(ctx, 1)
+    with pytest.raises(h2.H2Error) as e:
+        h2.mul(ctx, D, D, 1e-6)
+    assert e.value.code == h2.H2_ERR_OUT_OF_MEMORY
+    h2.set_memory_limit(ctx, 0)
+    for X, ref in ((A, refA), (B, refB)):
+        C, st = h2.mul(ctx, X, X, 1e-6)
+        assert st["t_plan_ms"] == 0.0
+        assert same(C, ref)
+        del C
+    # no free room beyond what is in use now: A's result fits only once the
+    # idle cached plans (B's, D's) have been dropped
+    h2.set_memory_limit(ctx, _used_device_bytes())
+    C, st = h2.mul(ctx, A, A, 1e-6)
+    assert st["t_plan_ms"] == 0.0
+    assert same(C, refA)
+    del C
+    h2.set_memory_limit(ctx, 0)
+    C, st = h2.mul(ctx, B, B, 1e-6)
+    assert st["t_plan_ms"] > 0.0  # B's plan was dropped and is built again
+    assert same(C, refB)
