@@ -2600,6 +2600,7 @@ static void emit(Plan& P, double eps) {
   }
   static const bool check = std::getenv("H2_CHECK_REBASE") != nullptr;
   if (P.desc.p && P.desc_base && !P.keep_protos) {
+    if (P.desc_base == ws_base(P)) return;  // the new arena is where the old one was
     std::vector<char> blob(P.desc_size);
     H2_HIP(hipMemcpy(blob.data(), P.desc.p, blob.size(), hipMemcpyDeviceToHost));
     rebase_blob(P, blob, P.desc_base, ws_base(P), P.ws_bytes);
