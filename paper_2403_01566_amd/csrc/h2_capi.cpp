@@ -34,6 +34,10 @@ h2_status guard(F&& f) {
     return H2_OK;
   } catch (const h2::Error& e) {
     g_err = e.what();
+    // a failed runtime call stays the runtime's "last error" until read; the
+    // failure is reported here, so it must not surface again in the launch
+    // checks of a later call (e.g. a product retried after out of memory)
+    (void)hipGetLastError();
     return e.code;
   } catch (const std::bad_alloc&) {
     g_err = "host allocation failed";

@@ -2798,6 +2798,8 @@ static double qr_flops(double m, double w) {
 // 3 also the algorithmic work from the sizes the QR / SVD kernels report.
 static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_phase, char* desc_base = nullptr) {
   (void)ctx;
+  // the launch check below must see only this execution's launches
+  (void)hipGetLastError();
   hipStream_t s = L.stream;
   char* base = desc_base ? desc_base : (char*)P.desc.p;
   std::vector<hipEvent_t> ev;
