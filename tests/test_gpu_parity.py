@@ -405,22 +405,25 @@ def test_budgets_sweep_cap_and_reuse_of_the_plan(h2, ctx):
     assert np.array_equal(C2.to_dense(T.n, T.n), D0)
 
 
-@pytest.mark.parametrize("case,eps,chunks", [("sphere4", 1e-6, 4), ("random2d", 1e-5, 16)])
-def test_chunked_plan_against_oracle(h2, ctx, case, eps, chunks):
+@pytest.mark.parametrize("case,eps,chunks,prec", [("sphere4", 1e-6, 4, 0), ("random2d", 1e-5, 16, 0),
+                                                  ("sphere4", 1e-4, 4, 1), ("random2d", 1e-4, 16, 1)])
+def test_chunked_plan_against_oracle(h2, ctx, case, eps, chunks, prec):
     """A plan run in chunks (exact product, leaf forms and coarsening chunk by
     chunk, blocks rooted above the chunks last) meets the same bounds; its
-    launches are smaller, so its rounding may differ from the one-chunk plan."""
-    _say(f"[parity] {case} eps={eps} chunks={chunks}")
+    launches are smaller, so its rounding may differ from the one-chunk plan.
+    With the FP32 bulk every chunk converts its final forms to FP64 itself."""
+    _say(f"[parity] {case} eps={eps} chunks={chunks} prec={prec}")
     T, A, B, To, Ao, Bo = _build(h2, ctx, case)
-    C1, s1 = h2.mul(ctx, A, B, eps)
-    Cg, st = h2.mul(ctx, A, B, eps, h2.default_options(chunks=chunks))
+    C1, s1 = h2.mul(ctx, A, B, eps, h2.default_options(precision=prec))
+    Cg, st = h2.mul(ctx, A, B, eps, h2.default_options(chunks=chunks, precision=prec))
+    assert st["prec_used"] == prec
     assert st["t_plan_ms"] > 0.0 and st["launches"] > s1["launches"]  # a plan of its own, in chunks
     key = (case, eps)
     if key not in _oracle_cache:
         _oracle_cache.clear()
         _oracle_cache[key] = O.mul(Ao, Bo, eps)
     Co, info = _oracle_cache[key]
-    worst, worst_o, Cd = _compare(h2, T, Cg, Ao, Bo, Co, eps, 0, case)
+    worst, worst_o, Cd = _compare(h2, T, Cg, Ao, Bo, Co, eps, prec, case)
     _check_result_arrays(Cg, T, Cd)
     _say(f"  worst block error {worst:.3e} (eps {eps}), distance to oracle {worst_o:.3e}, launches "
          f"{st['launches']} (one chunk {s1['launches']})")
