@@ -425,6 +425,11 @@ def test_chunked_plan_against_oracle(h2, ctx, case, eps, chunks, prec):
     Co, info = _oracle_cache[key]
     worst, worst_o, Cd = _compare(h2, T, Cg, Ao, Bo, Co, eps, prec, case)
     _check_result_arrays(Cg, T, Cd)
+    # the chunked plan replayed from its HIP graph: the eager result, bit for bit
+    for _ in range(2):
+        Cr, sr = h2.mul(ctx, A, B, eps, h2.default_options(chunks=chunks, precision=prec, graph=1))
+        assert sr["t_plan_ms"] == 0.0
+        assert np.array_equal(Cr.to_dense(T.n, T.n), Cd)
     _say(f"  worst block error {worst:.3e} (eps {eps}), distance to oracle {worst_o:.3e}, launches "
          f"{st['launches']} (one chunk {s1['launches']})")
     assert worst <= eps
