@@ -348,10 +348,9 @@ __device__ inline int pk(int j, int l, int w) { return j * w - (j * (j - 1)) / 2
 // next reflector at once from its updated registers and publishes it (the
 // vector's chunk part and tau) in a double-buffered LDS slot, so every column
 // step costs one barrier.
-template <int WMAX, int NT>
+template <int WMAX, int NT, int CH>
 __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks, int wlo) {
   constexpr int TPC = NT / WMAX;  // lanes per column
-  constexpr int CH = 64;          // chunk rows
   constexpr int RPT = CH / TPC;   // chunk rows per lane
   static_assert(TPC >= 1 && (TPC & (TPC - 1)) == 0 && TPC <= 16 && RPT * TPC == CH, "lanes per column");
   __shared__ double R[WMAX * (WMAX + 1) / 2];
@@ -457,18 +456,38 @@ __global__ __launch_bounds__(NT) void qr_kernel(const QrTask* __restrict__ tasks
 
 int size_classes(int wmax) { return wmax > 64 ? 3 : (wmax > 32 ? 2 : 1); }
 
+// Workgroup shapes per width class.  The two narrow classes walk 128-row
+// chunks with 8 lanes per column (half the column steps of 64-row chunks, as
+// many registers per lane).  The 128-wide class keeps 64-row chunks on 4
+// lanes per column: its packed R takes 66 KB of LDS, two workgroups per CU,
+// and 128-row chunks would need 1024 lanes per workgroup and leave one.
 #ifndef H2_QR32_NT
-#define H2_QR32_NT 128
+#define H2_QR32_NT 256
 #endif
 #ifndef H2_QR64_NT
-#define H2_QR64_NT 256
+#define H2_QR64_NT 512
+#endif
+#ifndef H2_QR32_CH
+#define H2_QR32_CH 128
+#endif
+#ifndef H2_QR64_CH
+#define H2_QR64_CH 128
+#endif
+#ifndef H2_QR128_CH
+#define H2_QR128_CH 64
+#endif
+#ifndef H2_QR128_NT
+#define H2_QR128_NT 512
 #endif
 void launch_qr_class(const QrTask* tasks, int ntasks, int cls, hipStream_t s) {
   if (ntasks <= 0) return;
   // each workgroup exits unless its task's effective width falls into the class
-  if (cls == 0) hipLaunchKernelGGL((qr_kernel<32, H2_QR32_NT>), dim3(ntasks), dim3(H2_QR32_NT), 0, s, tasks, 0);
-  if (cls == 1) hipLaunchKernelGGL((qr_kernel<64, H2_QR64_NT>), dim3(ntasks), dim3(H2_QR64_NT), 0, s, tasks, 32);
-  if (cls == 2) hipLaunchKernelGGL((qr_kernel<128, 512>), dim3(ntasks), dim3(512), 0, s, tasks, 64);
+  if (cls == 0)
+    hipLaunchKernelGGL((qr_kernel<32, H2_QR32_NT, H2_QR32_CH>), dim3(ntasks), dim3(H2_QR32_NT), 0, s, tasks, 0);
+  if (cls == 1)
+    hipLaunchKernelGGL((qr_kernel<64, H2_QR64_NT, H2_QR64_CH>), dim3(ntasks), dim3(H2_QR64_NT), 0, s, tasks, 32);
+  if (cls == 2)
+    hipLaunchKernelGGL((qr_kernel<128, H2_QR128_NT, H2_QR128_CH>), dim3(ntasks), dim3(H2_QR128_NT), 0, s, tasks, 64);
 }
 
 void launch_qr(const QrTask* tasks, int ntasks, int wmax, hipStream_t s) {
@@ -1175,8 +1194,8 @@ void launch_scan(const ScanTask* tasks, const int* const* src, int ntasks, hipSt
 
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {
-      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 128>",
-      "qr_kernel<64, 256>",        "qr_kernel<128, 512>",    "svd_kernel<32, 64>",
+      "gemm_kernel<double>",       "gemm_kernel<float>",         "qr_kernel<32, 256, 128>",
+      "qr_kernel<64, 512, 128>",   "qr_kernel<128, 512, 64>",    "svd_kernel<32, 64>",
       "svd_kernel<64, 256>",       "svd_narrow_kernel<128, 512, 64> + svd_kernel<128, 512>",       "chol_kernel",
       "fill_kernel",               "convert kernels",            "ref_kernel",
       "scan_kernel"};

@@ -3097,6 +3097,15 @@ static void execute(Context* ctx, const Lane& L, Plan& P, int timing, double* t_
 // Algorithmic flops and bytes of the QR, SVD, Cholesky, fill and conversion
 // steps from their planned sizes (GEMM steps count theirs when emitted).
 static void count_work(Plan& P) {
+  // A QR task walks its matrix in chunks of rows with one barrier per column,
+  // so its time grows with m * w, and a step's launch lasts until its longest
+  // task ends.  Workgroups start in task order: the longest tasks of a step
+  // go first, so that the last workgroups to start are short ones.
+  for (auto& st : P.steps)
+    if (st.kind == SK_QR)
+      std::stable_sort(st.qr.begin(), st.qr.end(), [](const PQr& a, const PQr& b) {
+        return (int64_t)a.m * a.w > (int64_t)b.m * b.w;
+      });
   double fl = 0;
   for (auto& st : P.steps) {
     if (st.kind == SK_QR)

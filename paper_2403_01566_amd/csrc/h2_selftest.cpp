@@ -390,6 +390,9 @@ int selftest(hipStream_t s, int* overflow, double* errors, int nerrors) {
   // device-side inner dimension (the operands are nonzero beyond it)
   e.push_back(gemm_test<double>(s, h2k::IT_TRANS_B, 70, 90, 77, 2, 21));
   e.push_back(gemm_test<float>(s, h2k::IT_TRANS_A, 65, 40, 50, 3, 9));
+  // the narrow QR classes over several 128-row chunks, the last one ragged
+  e.push_back(qr_test(s, 300, 50));
+  e.push_back(qr_test(s, 129, 32));
   for (int i = 0; i < nerrors && i < (int)e.size(); ++i) errors[i] = e[i];
   return (int)e.size();
 }

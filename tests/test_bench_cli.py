@@ -48,7 +48,7 @@ def test_roofline_bound_of_each_kernel_family():
     the QR, SVD (including the narrow first pass, whose combined entry starts
     with its own name) and Cholesky kernels against the FP64 peak (flops),
     each from the algorithmic figure per launch over the average launch time."""
-    names = ["gemm_kernel<double>", "qr_kernel<128, 512>",
+    names = ["gemm_kernel<double>", "qr_kernel<128, 512, 64>",
              "svd_narrow_kernel<128, 512, 64> + svd_kernel<128, 512>", "chol_kernel"]
     for dom, bound in ((0, "hbm"), (1, "alu"), (2, "alu"), (3, "alu")):
         roof = _roofline(names, dom, flops=4e12, nbytes=8e9, ms=10.0, launches=4)

@@ -9,9 +9,9 @@ NAMES = ["gemm_f64_nn", "gemm_f64_tn", "gemm_f64_nt", "gemm_f64_tt",
          "qr_w20", "qr_w64", "qr_w128", "qr_split_w100", "qr_split_w48", "svd_w24", "svd_w64", "svd_w128", "svd_qrcp_w40", "svd_qrcp_w128", "svd_qrcp_w100_r20",
          "chol_w12", "chol_w32", "chol_w50", "svd_empty",
          "svd_qrcp_w100_r20_x1024", "svd_qrcp_w128_x1024", "svd_w128_x1024",
-         "gemm_f64_nt_kdev", "gemm_f32_tn_kdev"]
+         "gemm_f64_nt_kdev", "gemm_f32_tn_kdev", "qr_w50_m300", "qr_w32_m129"]
 TOL = [1e-14] * 4 + [3e-6] * 4 + [1e-13] * 5 + [1e-9] * 3 + [1e-12] * 3 + [1e-12] * 3 + [0.0] + [1e-12, 1e-12, 1e-9] \
-    + [1e-14, 3e-6]
+    + [1e-14, 3e-6] + [1e-13] * 2
 
 
 def test_kernel_selftest():
