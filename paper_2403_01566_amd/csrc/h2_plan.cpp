@@ -475,9 +475,13 @@ struct MNode {
   // dense leaf block of at most 128 x 128: the left singular vectors U^ of
   // G come straight from the SVD of G (no QR, no Y = G^ V_k orthonormalisation)
   bool direct = false;
+  // merges: the two children share the merged block's rows (hz: Z is block
+  // diagonal) or its columns (vt: U is block diagonal)
+  bool hz = false, vt = false;
   int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
           Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
   int64_t Wsum = -1;  // merge: packed width kappa_a + kappa_b (device int)
+  int64_t Mv = -1;    // vertical merge: blockdiag(U^_a, U^_b)^* G^ (K x K)
 };
 
 class Planner {
@@ -1351,6 +1355,8 @@ void Planner::coarsen_group(int grp) {
         x.K = 2 * kcap;
         x.U = B.wd((int64_t)x.m * x.K).off;
         x.Z = B.wd((int64_t)x.n * x.K).off;
+        x.hz = mn[x.c0].t == x.t && mn[x.c1].t == x.t;
+        x.vt = mn[x.c0].r == x.r && mn[x.c1].r == x.r;
       }
       {  // packed width of every merge: kappa_a + kappa_b
         Step& sc = B.step(SK_SCAN);
@@ -1413,8 +1419,9 @@ void Planner::coarsen_group(int grp) {
       P.max_coarse_K = std::max(P.max_coarse_K, x.K);
       if (x.K > 128) throw Error(H2_ERR_TOO_LARGE, "coarsening width above 128");
       if (!x.direct) {
-        if (!x.zI) x.RZ = B.wd((int64_t)x.K * x.K).off;
-        if (!x.zI && !x.uI) x.Gh = B.wd((int64_t)x.m * x.K).off;
+        if (!x.zI && !x.hz) x.RZ = B.wd((int64_t)x.K * x.K).off;
+        if (!x.zI && !x.uI && !x.hz) x.Gh = B.wd((int64_t)x.m * x.K).off;
+        if (x.vt) x.Mv = B.wd((int64_t)x.K * x.K).off;
         if (!x.uI) x.RGt = B.wd((int64_t)x.K * x.K).off;
         x.Vk = B.wd((int64_t)x.K * kcap).off;
         x.Yk = B.wd((int64_t)x.m * kcap).off;
@@ -1437,26 +1444,50 @@ void Planner::coarsen_group(int grp) {
     // effective width of a merge: kappa of the two children (device side)
     auto wd1 = [&](const MNode& x) { return x.c0 >= 0 ? Iw(mn[x.c0].Kap) : DRef<int>(); };
     auto wd2 = [&](const MNode& x) { return x.c1 >= 0 ? Iw(mn[x.c1].Kap) : DRef<int>(); };
+    // A child's V^ and U^ have orthonormal columns.  Where the children share
+    // the merged block's rows, Z = [ext(V^_a), ext(V^_b)] is block diagonal
+    // with orthonormal columns, so R_Z = I and G^ = U (as for Z = I).
     {  // R_Z: R factor of Z (Z = I: R_Z = I, skipped)
       QrSplit q(B, wmax, lv.size());
       for (int i : lv) {
         MNode& x = mn[i];
-        if (!x.zI && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
+        if (!x.zI && !x.hz && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
       }
     }
     {  // condensed block G^ = U R_Z^* (same singular values as U Z^*);
-       // Z = I: G^ = U;  U = I: G^ = R_Z^*, used through a transposed operand
+       // Z = I or orthonormal: G^ = U;  U = I: G^ = R_Z^*, used through a transposed operand
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
         if (x.direct || x.uI) continue;
-        if (x.zI) {
+        if (x.zI || x.hz) {
           x.Gh = x.U;
           continue;
         }
         g.task(Dw(x.Gh), x.K, x.m, x.K);
         g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
         if (x.c0 >= 0) g.kdev(wd1(x), wd2(x));
+      }
+    }
+    // Where the children share the merged block's columns, U =
+    // blockdiag(U^_a S_a, U^_b S_b), so G^ = blockdiag(U^_a, U^_b) M with
+    // M = blockdiag(U^_a, U^_b)^* G^ (rows [0, kappa_a) from a, [kappa_a,
+    // kappa_a + kappa_b) from b): M^* M = G^^* G^, and the R factor of G^ is
+    // the one of M, a QR of kappa_a + kappa_b rows instead of m.
+    bool anyvt = false;
+    for (int i : lv) anyvt |= mn[i].vt && !mn[i].direct;
+    if (anyvt) {
+      GW<double> g(B.step(SK_GEMM_D));
+      for (int i : lv) {
+        MNode& x = mn[i];
+        if (!x.vt || x.direct) continue;
+        for (int c = 0; c < 2; ++c) {
+          const MNode& ch = mn[c == 0 ? x.c0 : x.c1];
+          const int64_t ro = TI.begin[ch.t] - TI.begin[x.t];
+          g.task(Dw(x.Mv), x.K, kcap, x.K);
+          g.dev(DRef<int>(), DRef<int>(), Iw(ch.Kap), c == 0 ? DRef<int>() : Iw(mn[x.c0].Kap));
+          g.mm(Dw(ch.Uh), kcap, Dw(x.Gh) + ro * x.K, x.K, ch.m, h2k::IT_TRANS_A);
+        }
       }
     }
     {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
@@ -1469,7 +1500,8 @@ void Planner::coarsen_group(int grp) {
           x.RGt = x.RZ;
           continue;
         }
-        q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
+        if (x.vt) q.add(Dw(x.Mv), x.K, x.K, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x), Iw(x.Wsum));
+        else q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
       }
     }
     if (h == 0) {  // lower bounds of the block norms: largest column norm of the leaves' condensed factors
