@@ -481,7 +481,9 @@ struct MNode {
   int64_t U = -1, Z = -1, RZ = -1, Gh = -1, RGt = -1, Vk = -1, Yk = -1, Gy = -1, T1 = -1, R1 = -1, Uh = -1,
           Tm = -1, Zh = -1, Gz = -1, T2 = -1, R2 = -1, Vh = -1, Sb = -1, Sig = -1, Kap = -1, Wc = -1;
   int64_t Wsum = -1;  // merge: packed width kappa_a + kappa_b (device int)
-  int64_t Mv = -1;    // vertical merge: blockdiag(U^_a, U^_b)^* G^ (K x K)
+  // hz / vt merges: C (kcap x kcap), P (rows x kcap) and R_P (kcap x kcap)
+  // of the Gram-Schmidt step against piece a
+  int64_t Cb = -1, Pb = -1, Rp = -1;
 };
 
 class Planner {
@@ -1419,9 +1421,13 @@ void Planner::coarsen_group(int grp) {
       P.max_coarse_K = std::max(P.max_coarse_K, x.K);
       if (x.K > 128) throw Error(H2_ERR_TOO_LARGE, "coarsening width above 128");
       if (!x.direct) {
-        if (!x.zI && !x.hz) x.RZ = B.wd((int64_t)x.K * x.K).off;
+        if (!x.zI && !x.hz && !x.vt) x.RZ = B.wd((int64_t)x.K * x.K).off;
         if (!x.zI && !x.uI && !x.hz) x.Gh = B.wd((int64_t)x.m * x.K).off;
-        if (x.vt) x.Mv = B.wd((int64_t)x.K * x.K).off;
+        if (x.hz || x.vt) {
+          x.Cb = B.wd((int64_t)kcap * kcap).off;
+          x.Pb = B.wd((int64_t)(x.hz ? x.m : x.n) * kcap).off;
+          x.Rp = B.wd((int64_t)kcap * kcap).off;
+        }
         if (!x.uI) x.RGt = B.wd((int64_t)x.K * x.K).off;
         x.Vk = B.wd((int64_t)x.K * kcap).off;
         x.Yk = B.wd((int64_t)x.m * kcap).off;
@@ -1444,23 +1450,134 @@ void Planner::coarsen_group(int grp) {
     // effective width of a merge: kappa of the two children (device side)
     auto wd1 = [&](const MNode& x) { return x.c0 >= 0 ? Iw(mn[x.c0].Kap) : DRef<int>(); };
     auto wd2 = [&](const MNode& x) { return x.c1 >= 0 ? Iw(mn[x.c1].Kap) : DRef<int>(); };
-    // A child's V^ and U^ have orthonormal columns.  Where the children share
-    // the merged block's rows, Z = [ext(V^_a), ext(V^_b)] is block diagonal
-    // with orthonormal columns, so R_Z = I and G^ = U (as for Z = I).
-    {  // R_Z: R factor of Z (Z = I: R_Z = I, skipped)
+    // A merge joins two truncated pieces W_a V^_a^* and W_b V^_b^* (W = U^ S,
+    // U^ and V^ with orthonormal columns; columns [0, kappa_a) of U and Z
+    // come from a, [kappa_a, kappa_a + kappa_b) from b).  The SVD needs a
+    // matrix whose Gram matrix is the one of G^ = U R_Z^*.  One Gram-Schmidt
+    // step against piece a's orthonormal factor gives it, with a QR of
+    // kappa_b columns only:
+    //  - the children share the merged block's rows (hz): Z is block diagonal
+    //    with orthonormal columns, R_Z = I and G^ = U = [W_a, W_b].  With
+    //    C = U^_a^* W_b and P = W_b - U^_a C = Q_P R_P,
+    //    U = [U^_a, Q_P] [[S_a, C], [0, R_P]], which is R_G.
+    //  - they share its columns (vt): Z = [V^_a, V^_b].  With C = V^_a^* V^_b
+    //    and P = V^_b - V^_a C = Q_P R_P, R_Z = [[I, C], [0, R_P]], so G^ has
+    //    the rows [W_a, 0] (of a) and [W_b C^*, W_b R_P^*] (of b), and
+    //    G^ = diag(U^_a, U^_b) M with M = [[S_a, 0], [S_b C^*, S_b R_P^*]]:
+    //    M^* M = G^^* G^, and M^* takes the place of R_G^*.
+    bool anygs = false;
+    for (int i : lv) anygs |= (mn[i].hz || mn[i].vt) && !mn[i].direct;
+    if (anygs) {
+      auto gs = [&](const MNode& x) { return (x.hz || x.vt) && !x.direct; };
+      {  // C
+        GW<double> g(B.step(SK_GEMM_D));
+        for (int i : lv) {
+          MNode& x = mn[i];
+          if (!gs(x)) continue;
+          const MNode &a = mn[x.c0], &b = mn[x.c1];
+          g.task(Dw(x.Cb), kcap, kcap, kcap);
+          g.dev(Iw(b.Kap), DRef<int>(), Iw(a.Kap));
+          if (x.hz) g.mm(Dw(a.Uh), kcap, Dw(b.Wc), kcap, x.m, h2k::IT_TRANS_A);
+          else g.mm(Dw(a.Vh), kcap, Dw(b.Vh), kcap, x.n, h2k::IT_TRANS_A);
+        }
+      }
+      {  // P = (W_b or V^_b) - (U^_a or V^_a) C
+        GW<double> g(B.step(SK_GEMM_D));
+        for (int i : lv) {
+          MNode& x = mn[i];
+          if (!gs(x)) continue;
+          const MNode &a = mn[x.c0], &b = mn[x.c1];
+          g.task(Dw(x.Pb), kcap, x.hz ? x.m : x.n, kcap);
+          g.dev(Iw(b.Kap));
+          g.copy(Dw(x.hz ? b.Wc : b.Vh), kcap);
+          g.mm(Dw(x.hz ? a.Uh : a.Vh), kcap, Dw(x.Cb), kcap, kcap, 0, -1.0);
+          g.kdev(Iw(a.Kap));
+        }
+      }
+      {  // R_P (kappa_b columns)
+        size_t n = 0;
+        for (int i : lv) n += gs(mn[i]);
+        QrSplit q(B, kcap, n);
+        for (int i : lv) {
+          MNode& x = mn[i];
+          if (gs(x)) q.add(Dw(x.Pb), kcap, x.hz ? x.m : x.n, kcap, Dw(x.Rp), kcap, 0, Iw(mn[x.c1].Kap));
+        }
+      }
+      {  // R_G^* (hz) or M^* (vt), and G^ of the vt merges
+        GW<double> g(B.step(SK_GEMM_D));
+        for (int i : lv) {
+          MNode& x = mn[i];
+          if (!gs(x)) continue;
+          const MNode &a = mn[x.c0], &b = mn[x.c1];
+          const DRef<int> ka = Iw(a.Kap), kb = Iw(b.Kap);
+          const DRef<double> rg = Dw(x.RGt);
+          const int K = x.K;
+          g.task(rg, K, kcap, kcap);  // [0, ka) x [0, ka): S_a^*
+          g.dev(ka, DRef<int>(), ka);
+          g.copy(Dw(a.Sb), kcap, h2k::IT_TRANS_A);
+          if (x.hz) {
+            g.task(rg, K, kcap, kcap);  // [0, ka) x [ka, ka + kb): 0
+            g.dev(kb, ka, ka);
+            g.task(rg, K, kcap, kcap);  // [ka, ka + kb) x [0, ka): C^*
+            g.dev(ka, DRef<int>(), kb, ka);
+            g.copy(Dw(x.Cb), kcap, h2k::IT_TRANS_A);
+            g.task(rg, K, kcap, kcap);  // [ka, ka + kb) x [ka, ka + kb): R_P^*
+            g.dev(kb, ka, kb, ka);
+            g.copy(Dw(x.Rp), kcap, h2k::IT_TRANS_A);
+            continue;
+          }
+          g.task(rg, K, kcap, kcap);  // [0, ka) x [ka, ka + kb): C S_b^*
+          g.dev(kb, ka, ka);
+          g.mm(Dw(x.Cb), kcap, Dw(b.Sb), kcap, kcap, h2k::IT_TRANS_B);
+          g.kdev(kb);
+          g.task(rg, K, kcap, kcap);  // [ka, ka + kb) x [0, ka): 0
+          g.dev(ka, DRef<int>(), kb, ka);
+          g.task(rg, K, kcap, kcap);  // [ka, ka + kb) x [ka, ka + kb): R_P S_b^*
+          g.dev(kb, ka, kb, ka);
+          g.mm(Dw(x.Rp), kcap, Dw(b.Sb), kcap, kcap, h2k::IT_TRANS_B);
+          g.kdev(kb);
+          // G^: rows of a [W_a, 0], rows of b [W_b C^*, W_b R_P^*]
+          const int64_t ra = TI.begin[a.t] - TI.begin[x.t], rb = TI.begin[b.t] - TI.begin[x.t];
+          g.task(Dw(x.Gh) + ra * K, K, a.m, kcap);
+          g.dev(ka);
+          g.copy(Dw(a.Wc), kcap);
+          g.task(Dw(x.Gh) + ra * K, K, a.m, kcap);
+          g.dev(kb, ka);
+          g.task(Dw(x.Gh) + rb * K, K, b.m, kcap);
+          g.dev(ka);
+          g.mm(Dw(b.Wc), kcap, Dw(x.Cb), kcap, kcap, h2k::IT_TRANS_B);
+          g.kdev(kb);
+          g.task(Dw(x.Gh) + rb * K, K, b.m, kcap);
+          g.dev(kb, ka);
+          g.mm(Dw(b.Wc), kcap, Dw(x.Rp), kcap, kcap, h2k::IT_TRANS_B);
+          g.kdev(kb);
+        }
+      }
+    }
+    bool anyrz = false, anygh = false, anyrg = false;
+    for (int i : lv) {
+      const MNode& x = mn[i];
+      if (x.direct || x.hz || x.vt) continue;
+      anyrz |= !x.zI;
+      anygh |= !x.uI && !x.zI;
+      anyrg |= !x.uI;
+    }
+    if (anyrz) {  // R_Z: R factor of Z (Z = I: R_Z = I, skipped)
       QrSplit q(B, wmax, lv.size());
       for (int i : lv) {
         MNode& x = mn[i];
-        if (!x.zI && !x.hz && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
+        if (!x.zI && !x.hz && !x.vt && !x.direct) q.add(Dw(x.Z), x.K, x.n, x.K, Dw(x.RZ), x.K, 0, wd1(x), wd2(x));
       }
     }
-    {  // condensed block G^ = U R_Z^* (same singular values as U Z^*);
-       // Z = I or orthonormal: G^ = U;  U = I: G^ = R_Z^*, used through a transposed operand
+    for (int i : lv)
+      if (mn[i].hz && !mn[i].direct) mn[i].Gh = mn[i].U;
+    if (anygh) {  // condensed block G^ = U R_Z^* (same singular values as U Z^*);
+                  // Z = I: G^ = U;  U = I: G^ = R_Z^*, used through a transposed operand
       GW<double> g(B.step(SK_GEMM_D));
       for (int i : lv) {
         MNode& x = mn[i];
-        if (x.direct || x.uI) continue;
-        if (x.zI || x.hz) {
+        if (x.direct || x.uI || x.hz || x.vt) continue;
+        if (x.zI) {
           x.Gh = x.U;
           continue;
         }
@@ -1468,41 +1585,25 @@ void Planner::coarsen_group(int grp) {
         g.mm(Dw(x.U), x.K, Dw(x.RZ), x.K, x.K, h2k::IT_TRANS_B);
         if (x.c0 >= 0) g.kdev(wd1(x), wd2(x));
       }
+    } else {
+      for (int i : lv)
+        if (mn[i].zI && !mn[i].direct && !mn[i].uI) mn[i].Gh = mn[i].U;
     }
-    // Where the children share the merged block's columns, U =
-    // blockdiag(U^_a S_a, U^_b S_b), so G^ = blockdiag(U^_a, U^_b) M with
-    // M = blockdiag(U^_a, U^_b)^* G^ (rows [0, kappa_a) from a, [kappa_a,
-    // kappa_a + kappa_b) from b): M^* M = G^^* G^, and the R factor of G^ is
-    // the one of M, a QR of kappa_a + kappa_b rows instead of m.
-    bool anyvt = false;
-    for (int i : lv) anyvt |= mn[i].vt && !mn[i].direct;
-    if (anyvt) {
-      GW<double> g(B.step(SK_GEMM_D));
-      for (int i : lv) {
-        MNode& x = mn[i];
-        if (!x.vt || x.direct) continue;
-        for (int c = 0; c < 2; ++c) {
-          const MNode& ch = mn[c == 0 ? x.c0 : x.c1];
-          const int64_t ro = TI.begin[ch.t] - TI.begin[x.t];
-          g.task(Dw(x.Mv), x.K, kcap, x.K);
-          g.dev(DRef<int>(), DRef<int>(), Iw(ch.Kap), c == 0 ? DRef<int>() : Iw(mn[x.c0].Kap));
-          g.mm(Dw(ch.Uh), kcap, Dw(x.Gh) + ro * x.K, x.K, ch.m, h2k::IT_TRANS_A);
-        }
-      }
-    }
-    {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
-       // vectors of G^ = R_Z^* as its left ones and replaces R_G^*
+    if (anyrg) {  // R factor of G^, stored transposed.  U = I: R_Z has the right singular
+                  // vectors of G^ = R_Z^* as its left ones and replaces R_G^*
       QrSplit q(B, wmax, lv.size());
       for (int i : lv) {
         MNode& x = mn[i];
-        if (x.direct) continue;
+        if (x.direct || x.hz || x.vt) continue;
         if (x.uI) {
           x.RGt = x.RZ;
           continue;
         }
-        if (x.vt) q.add(Dw(x.Mv), x.K, x.K, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x), Iw(x.Wsum));
-        else q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
+        q.add(Dw(x.Gh), x.K, x.m, x.K, Dw(x.RGt), x.K, 1, wd1(x), wd2(x));
       }
+    } else {
+      for (int i : lv)
+        if (mn[i].uI && !mn[i].direct) mn[i].RGt = mn[i].RZ;
     }
     if (h == 0) {  // lower bounds of the block norms: largest column norm of the leaves' condensed factors
       Step& st = B.step(SK_REF);
