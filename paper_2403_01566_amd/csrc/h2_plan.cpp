@@ -1405,6 +1405,14 @@ void Planner::coarsen_group(int grp) {
           zero(x.Z, 0, co);
           zero(x.Z, co + ch.n, x.n);
         }
+        if (x.hz || x.vt) {  // C of the Gram-Schmidt step below, in the same launch
+          const MNode &a = mn[x.c0], &b = mn[x.c1];
+          x.Cb = B.wd((int64_t)kcap * kcap).off;
+          g.task(Dw(x.Cb), kcap, kcap, kcap);
+          g.dev(Iw(b.Kap), DRef<int>(), Iw(a.Kap));
+          if (x.hz) g.mm(Dw(a.Uh), kcap, Dw(b.Wc), kcap, x.m, h2k::IT_TRANS_A);
+          else g.mm(Dw(a.Vh), kcap, Dw(b.Vh), kcap, x.n, h2k::IT_TRANS_A);
+        }
       }
     } else {
       for (int i : lv) {
@@ -1424,7 +1432,6 @@ void Planner::coarsen_group(int grp) {
         if (!x.zI && !x.hz && !x.vt) x.RZ = B.wd((int64_t)x.K * x.K).off;
         if (!x.zI && !x.uI && !x.hz) x.Gh = B.wd((int64_t)x.m * x.K).off;
         if (x.hz || x.vt) {
-          x.Cb = B.wd((int64_t)kcap * kcap).off;
           x.Pb = B.wd((int64_t)(x.hz ? x.m : x.n) * kcap).off;
           x.Rp = B.wd((int64_t)kcap * kcap).off;
         }
@@ -1469,19 +1476,7 @@ void Planner::coarsen_group(int grp) {
     for (int i : lv) anygs |= (mn[i].hz || mn[i].vt) && !mn[i].direct;
     if (anygs) {
       auto gs = [&](const MNode& x) { return (x.hz || x.vt) && !x.direct; };
-      {  // C
-        GW<double> g(B.step(SK_GEMM_D));
-        for (int i : lv) {
-          MNode& x = mn[i];
-          if (!gs(x)) continue;
-          const MNode &a = mn[x.c0], &b = mn[x.c1];
-          g.task(Dw(x.Cb), kcap, kcap, kcap);
-          g.dev(Iw(b.Kap), DRef<int>(), Iw(a.Kap));
-          if (x.hz) g.mm(Dw(a.Uh), kcap, Dw(b.Wc), kcap, x.m, h2k::IT_TRANS_A);
-          else g.mm(Dw(a.Vh), kcap, Dw(b.Vh), kcap, x.n, h2k::IT_TRANS_A);
-        }
-      }
-      {  // P = (W_b or V^_b) - (U^_a or V^_a) C
+      {  // P = (W_b or V^_b) - (U^_a or V^_a) C  (C formed with the packing of U and Z)
         GW<double> g(B.step(SK_GEMM_D));
         for (int i : lv) {
           MNode& x = mn[i];
