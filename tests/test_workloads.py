@@ -34,3 +34,72 @@ def test_cube_surface_invariants():
 def test_start_vector_is_seeded():
     a, b, c = W.start_vector(100, 7), W.start_vector(100, 7), W.start_vector(100, 8)
     assert np.array_equal(a, b) and not np.array_equal(a, c)
+
+
+def test_icosphere_level0_is_the_icosahedron():
+    """Level 0: the 20 faces of the icosahedron inscribed in the unit sphere;
+    every face centroid lies at the inradius sqrt((5 + 2 sqrt 5) / 15) and its
+    normal points along it."""
+    P, N = W.icosphere(0)
+    assert P.shape == (20, 3) and N.shape == (20, 3)
+    r_in = np.sqrt((5 + 2 * np.sqrt(5)) / 15)
+    assert np.allclose(np.linalg.norm(P, axis=1), r_in)
+    assert np.allclose(N, P / r_in)
+
+
+def test_icosphere_invariants():
+    for level in (1, 2, 3):
+        P, N = W.icosphere(level)
+        n = 20 * 4 ** level
+        assert P.shape == (n, 3) and N.shape == (n, 3)
+        r = np.linalg.norm(P, axis=1)
+        assert np.all(r < 1.0) and np.all(r > 0.79)                     # centroids of flat faces inside the sphere
+        assert np.allclose(np.linalg.norm(N, axis=1), 1.0)
+        assert np.all((P * N).sum(axis=1) > 0.0)                        # outward
+        assert np.all((P * N).sum(axis=1) / r > 0.99)                   # nearly radial
+        assert len(np.unique(P.round(12), axis=0)) == n                 # distinct
+        assert np.allclose(P.mean(axis=0), 0.0, atol=1e-12)             # symmetric mesh
+    a, b = W.icosphere(2), W.icosphere(2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_batched_instances_recipe():
+    """64 instances: n log-uniform in [1024, 32768] (total 540,638 for seed
+    2403), Chebyshev order 3..6, leaf 32 up to order 4 and 64 above."""
+    inst = W.batched_instances()
+    assert len(inst) == 64
+    assert sum(x["n"] for x in inst) == 540638
+    for x in inst:
+        assert 1024 <= x["n"] <= 32768
+        assert 3 <= x["order"] <= 6
+        assert x["leaf"] == (32 if x["order"] <= 4 else 64)
+    assert W.batched_instances() == inst
+    assert W.batched_instances(seed=1) != inst
+    logs = np.log2([x["n"] for x in inst])
+    assert logs.min() < 11 and logs.max() > 14                          # spread over the range
+
+
+def test_serving_requests_recipe():
+    """Poisson arrivals at the given rate; geometry, size, order and eps drawn
+    from the stated sets."""
+    req = W.serving_requests(2000, rate=200.0, m_range=(12, 15))
+    t = np.array([r["t"] for r in req])
+    assert np.all(np.diff(t) > 0)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 1 / 200.0) < 0.1 / 200.0                   # mean inter-arrival time
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.1                    # exponential: unit coefficient of variation
+    for r in req:
+        assert r["geometry"] in ("2d", "sphere")
+        assert 12 <= r["m"] <= 15
+        assert r["eps"] in (1e-4, 1e-6, 1e-8)
+        assert 3 <= r["order"] <= (8 if r["geometry"] == "2d" else 4)
+    assert {r["m"] for r in req} == {12, 13, 14, 15}
+    assert W.serving_requests(2000, rate=200.0, m_range=(12, 15)) == req
+
+
+def test_fibsphere_on_the_unit_sphere():
+    P, N = W.fibsphere(1000)
+    assert np.allclose(np.linalg.norm(P, axis=1), 1.0)
+    assert np.array_equal(P, N)
+    assert np.allclose(P.mean(axis=0), 0.0, atol=2e-3)
+    assert len(np.unique(P.round(12), axis=0)) == 1000
